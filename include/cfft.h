@@ -1,0 +1,183 @@
+/*
+ * cfft.h -- C ABI of the MI355X contour-FFT (C-FFT) tabulation library.
+ *
+ * The library tabulates the substrate-related reaction terms Z'_mn between
+ * Macro Basis Functions (MBFs) of identical printed antennas on a grounded
+ * dielectric slab, for every relative displacement on a regular grid, as in
+ * Jha & Craeye, "Contour-FFT based Spectral Domain MBF Analysis of Large
+ * Printed Antenna Arrays":
+ *
+ *   Z'_mn(Dx,Dy) = 1/(4 pi^2) sum_{n1,n2} I_mn(k) exp(-i k.D) T_P(gamma k.D) dkx dky
+ *   I_mn(k)      = W * M_m(k_c) . G_s(k_c) . M#_n(k_c),   k_c = (1 + i gamma) k
+ *
+ * (Sec. III-A eqs. spectral, MBF_mul, MBF_mul22, FTMBF; Sec. III-B.2 eqs.
+ * complexbeta..ratioNew and FFT; Sec. III-B.3 eqs. taylors, fftexp, fftarry;
+ * Appendix change of variables.)  T_P is the Taylor polynomial of order P of
+ * the contour's real exponential E_I, truncated at total degree P.
+ *
+ * Conventions.  Time dependence exp(+i w t); lengths in free-space
+ * wavelengths at f0 (lambda0 = 1), k0 = 2 pi f/f0; eta0 = 1; lossy
+ * permittivity eps_r (1 - i tan_delta); F(k) = int f(r) exp(-i k.r) dr;
+ * D = r_test - r_basis.  Complex numbers are interleaved (re, im).  Arrays
+ * are row-major with x fastest.
+ *
+ * Grids (Appendix).  Spectral samples kx(n1) = -kx_max + n1 * 2 kx_max/nx,
+ * n1 = 0..nx-1 (likewise y); output displacements Dx(j1) = -x_max + j1 pi/kx_max
+ * with x_max = nx pi/(2 kx_max), so D = 0 sits at j1 = nx/2.
+ *
+ * Memory ownership.  The caller owns every bulk device buffer (inputs and
+ * outputs).  A plan owns its twiddle tables, geometry tables and the
+ * workspace for the intermediate arrays between the row and column passes,
+ * and frees them in c_fft_plan_destroy.  Host arrays passed to a call are
+ * read during the call and not retained.
+ *
+ * Execution.  Entry points taking a `stream` (a hipStream_t, NULL = the
+ * default stream) enqueue their kernels on it and return without waiting,
+ * except where stated.  One plan must not be used from two streams at once.
+ *
+ * Errors.  Every call returns a status.  Arguments are validated on the host
+ * before anything is launched; on error nothing is enqueued and
+ * cfft_last_error() returns a message (thread-local).  No exception or abort
+ * crosses the ABI.  There is no CPU fallback: without a usable gfx950 device
+ * the calls fail with CFFT_ERR_HIP.
+ */
+#ifndef CFFT_H
+#define CFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cfft_plan_s* cfft_plan_t;
+
+typedef enum {
+  CFFT_OK = 0,
+  CFFT_ERR_INVALID_ARG = 1,   /* bad size, null pointer, out-of-range index, non-finite scalar */
+  CFFT_ERR_UNSUPPORTED = 2,   /* valid request outside what this build implements */
+  CFFT_ERR_ALLOC = 3,         /* device allocation failed */
+  CFFT_ERR_HIP = 4,           /* HIP runtime error (no device, launch failure) */
+  CFFT_ERR_NONFINITE = 5      /* a kernel produced NaN/Inf (only with CFFT_FLAG_CHECK_FINITE) */
+} cfft_status_t;
+
+enum { CFFT_CONTOUR_RAY = 0, CFFT_CONTOUR_PARABOLIC = 1 };
+enum { CFFT_FP64 = 0, CFFT_MIXED = 1 };
+enum { CFFT_ROOFTOP_X = 0, CFFT_ROOFTOP_Y = 1, CFFT_COSINE_X = 2, CFFT_COSINE_Y = 3 };
+enum { CFFT_FLAG_CHECK_FINITE = 1 };
+
+/* One spectral grid.  64 bytes, natural alignment. */
+typedef struct {
+  int32_t nx, ny;        /* samples = outputs per axis: powers of two, 8 <= n <= 4096 */
+  double kx_max, ky_max; /* spectral half-spans (rad per lambda0), > 0 */
+  double k0;             /* free-space wavenumber 2 pi f/f0, > 0 */
+  double gamma;          /* contour height ratio beta_I/beta_R (eq. ratioNew), > 0 */
+  int32_t contour;       /* CFFT_CONTOUR_RAY; PARABOLIC is rejected (UNSUPPORTED) */
+  int32_t order;         /* Taylor order P >= 0 of eq. taylors, total degree; P <= 7 */
+  double beta_end;       /* end of the parabolic deformation (unused for RAY) */
+  int32_t precision;     /* CFFT_FP64 (complex128 everywhere) or CFFT_MIXED */
+  int32_t reserved;      /* must be 0 */
+} cfft_grid_desc_t;
+
+/* One elementary basis function (40 bytes).  Sec. III-A: rooftops with an
+ * analytic Fourier transform.
+ *   CFFT_ROOFTOP_X: x-directed, triangle of half-base a along x, pulse of width b along y
+ *   CFFT_ROOFTOP_Y: y-directed transpose
+ *   CFFT_COSINE_X : x-directed cos(pi (x-cx)/a) on |x-cx| <= a/2, pulse of width b along y
+ *   CFFT_COSINE_Y : y-directed transpose
+ * (cx, cy) is the centre relative to the antenna's local origin. */
+typedef struct {
+  int32_t kind;
+  int32_t pad;           /* must be 0 */
+  double cx, cy, a, b;   /* a > 0, b > 0 */
+} cfft_basis_t;
+
+/* Create a plan for `ngrids` grids (a frequency sweep may use one grid per
+ * frequency) and up to `max_mbf` MBFs per antenna (1..16).  Allocates the
+ * twiddle tables on the current device (synchronous).  `flags` is a bitwise
+ * OR of CFFT_FLAG_*.  On success *out receives the plan. */
+cfft_status_t c_fft_plan(const cfft_grid_desc_t* grids, int32_t ngrids, int32_t max_mbf,
+                         int32_t flags, cfft_plan_t* out);
+
+/* Free a plan and everything it owns (synchronises the device first).
+ * NULL is accepted and ignored. */
+cfft_status_t c_fft_plan_destroy(cfft_plan_t plan);
+
+/* Grounded-slab spectral dyadic Green's function minus the effective
+ * homogeneous medium (eps_e = (eps_r + 1)/2) and its image through the ground
+ * plane (Sec. II, Sec. III-A), sampled at k_c = (1 + i gamma) k on every
+ * sample of grid `grid`, in FP64.
+ *   g : device, complex128 [3][ny][nx]: Gxx, Gxy (= Gyx), Gyy.
+ * eps_r >= 1 finite, tan_delta >= 0, h > 0 (in lambda0). */
+cfft_status_t slab_green_eval(cfft_plan_t plan, int32_t grid, double eps_r, double tan_delta,
+                              double h, void* g, void* stream);
+
+/* Spectra of the MBFs on the contour (eq. FTMBF), FP64.
+ *   basis : host, nbasis records (read during the call; the geometry is
+ *           uploaded to plan-owned device memory, blocking, and cached)
+ *   q     : device, complex128 [nmbf][nbasis], row m = coefficients of MBF m
+ *   spec  : device, complex128 [nmbf][4][ny][nx]:
+ *           [0] Mx_m(k_c) = sum_j conj(q_mj) Fx_j(k_c)    (testing side)
+ *           [1] My_m(k_c)
+ *           [2] Mx#_m(k_c) = sum_j q_mj Fx_j(-k_c)        (basis side: analytic
+ *           [3] My#_m(k_c)                                  reflection of conj M)
+ * 1 <= nmbf <= max_mbf, 1 <= nbasis <= 65536. */
+cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* basis,
+                          int32_t nbasis, const void* q, int32_t nmbf, void* spec, void* stream);
+
+/* The C-FFT table (eqs. FFT, fftexp, fftarry and the Appendix) for the
+ * listed MBF pairs: integrand assembly, contour weight, P+1 row FFTs per row
+ * with partial recombination, P+1 column FFTs per column with the per-output
+ * recombination and the Appendix scaling.
+ *   spec  : device, output of mbf_spectra for nmbf MBFs
+ *   g     : device, output of slab_green_eval
+ *   pairs : host, int32 [npairs][2] = (m, n), 0 <= m, n < nmbf (testing m, basis n)
+ *   z     : device [npairs][ny][nx], complex128 (FP64) or complex64 (MIXED);
+ *           z[p][j2][j1] = Z'_mn(Dx(j1), Dy(j2))
+ * 1 <= npairs <= 4096.  The plan's workspace grows on first use (allocation
+ * is synchronous; later calls of the same or smaller size do not allocate). */
+cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, int32_t nmbf,
+                            const void* g, const int32_t* pairs, int32_t npairs, void* z,
+                            void* stream);
+
+/* Bilinear interpolation in the table (first-order stand-in for the
+ * interpolation of Sec. III-B.3, last paragraph).
+ *   z   : device table as written by cfft_tabulate (precision of the grid)
+ *   pts : device, float64 [npts][2] = (Dx, Dy)
+ *   out : device, complex128 [npairs][npts]
+ * A point outside [Dx(0), Dx(nx-1)) x [Dy(0), Dy(ny-1)) yields NaN. */
+cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t npairs,
+                          const double* pts, int32_t npts, void* out, void* stream);
+
+/* Adjoint of cfft_lookup: dz[p][j2][j1] += sum over points of the bilinear
+ * weight times dout[p][q] (complex128, FP64 grids only).  dz must be zeroed
+ * by the caller before the first accumulation. */
+cfft_status_t cfft_lookup_backward(cfft_plan_t plan, int32_t grid, const void* dout,
+                                   int32_t npairs, const double* pts, int32_t npts, void* dz,
+                                   void* stream);
+
+/* Gradient of a real loss L through the whole table (FP64 grids only).
+ *   dz       : device complex128 [npairs][ny][nx], dL/dRe z + i dL/dIm z
+ *   eps_r, tan_delta, h, basis, nbasis, q, nmbf, pairs, npairs : the forward inputs
+ *   g, spec  : device, the forward's sampled Green's function and spectra
+ *              (the checkpoint of the sampled integrand; required)
+ *   grad_sub : device float64 [2] <- (dL/d eps_r, dL/d h), overwritten
+ *   grad_q   : device complex128 [nmbf][nbasis] <- dL/dRe q + i dL/dIm q, overwritten
+ * eps_r is differentiated as the real part eps' of eps' (1 - i tan_delta). */
+cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, double eps_r,
+                            double tan_delta, double h, const cfft_basis_t* basis, int32_t nbasis,
+                            const void* q, int32_t nmbf, const int32_t* pairs, int32_t npairs,
+                            const void* g, const void* spec, double* grad_sub, void* grad_q,
+                            void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* cfft_last_error(void);
+
+/* Library version string. */
+const char* cfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CFFT_H */

@@ -1,0 +1,129 @@
+"""MI355X (gfx950) contour-FFT tabulation of substrate-related MBF reaction terms.
+
+Python face of libcfft.so (include/cfft.h).  PyTorch provides device memory
+and streams; every step of the method runs in the library's HIP kernels.
+Importing the package fails loudly when the library is not built.
+
+    from paper_1404_7357_amd import Tabulator
+    tab = Tabulator(grid, basis, max_mbf=4)
+    g = tab.green(eps_r, tan_delta, h)          # [3][ny][nx] complex128
+    spec = tab.spectra(q)                       # [M][4][ny][nx] complex128
+    z = tab.tabulate(spec, g, pairs)            # [npairs][ny][nx]
+    vals = tab.lookup(z, pts)                   # [npairs][Q] complex128
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import _lib
+from ._lib import (CONTOUR_RAY, FLAG_CHECK_FINITE, FP64, MIXED, CfftError, Plan, cfft_backward,  # noqa: F401
+                   cfft_lookup, cfft_lookup_backward, cfft_tabulate, mbf_spectra, slab_green_eval)
+
+_lib.load()
+
+__all__ = ["Tabulator", "Plan", "CfftError", "TableFunction", "LookupFunction", "FP64", "MIXED",
+           "slab_green_eval", "mbf_spectra", "cfft_tabulate", "cfft_lookup", "cfft_lookup_backward",
+           "cfft_backward", "displacement_axis"]
+
+
+def displacement_axis(n: int, k_max: float):
+    """Output displacements of the table along one axis (host helper, float64)."""
+    x_max = n * math.pi / (2.0 * k_max)
+    return [-x_max + j * math.pi / k_max for j in range(n)]
+
+
+class Tabulator:
+    """One plan bound to one or more grids and one basis set."""
+
+    def __init__(self, grids, basis, max_mbf: int, flags: int = 0, device: str = "cuda"):
+        self.grids = list(grids) if isinstance(grids, (list, tuple)) else [grids]
+        self.plan = Plan(self.grids, max_mbf, flags)
+        self.basis = _lib.basis_array(basis)
+        self.nbasis = len(self.basis)
+        self.device = torch.device(device)
+
+    def _grid(self, i):
+        return self.grids[i]
+
+    def green(self, eps_r, tan_delta, h, grid: int = 0, out=None, stream=None):
+        gd = self._grid(grid)
+        g = out if out is not None else torch.empty((3, gd.ny, gd.nx), dtype=torch.complex128, device=self.device)
+        slab_green_eval(self.plan, grid, eps_r, tan_delta, h, g, stream)
+        return g
+
+    def spectra(self, q, grid: int = 0, out=None, stream=None):
+        gd = self._grid(grid)
+        q = q.contiguous()
+        if q.dtype != torch.complex128 or q.shape[1] != self.nbasis:
+            raise ValueError("q must be complex128 [M][nbasis]")
+        spec = out if out is not None else torch.empty((q.shape[0], 4, gd.ny, gd.nx), dtype=torch.complex128,
+                                                       device=self.device)
+        mbf_spectra(self.plan, grid, self.basis, q, spec, stream)
+        return spec
+
+    def tabulate(self, spec, g, pairs, grid: int = 0, out=None, stream=None):
+        gd = self._grid(grid)
+        dt = torch.complex128 if gd.precision == FP64 else torch.complex64
+        z = out if out is not None else torch.empty((len(pairs), gd.ny, gd.nx), dtype=dt, device=self.device)
+        cfft_tabulate(self.plan, grid, spec, spec.shape[0], g, pairs, z, stream)
+        return z
+
+    def lookup(self, z, pts, grid: int = 0, out=None, stream=None):
+        out = out if out is not None else torch.empty((z.shape[0], pts.shape[0]), dtype=torch.complex128,
+                                                      device=self.device)
+        cfft_lookup(self.plan, grid, z, z.shape[0], pts.contiguous(), out, stream)
+        return out
+
+    def close(self):
+        self.plan.close()
+
+
+class TableFunction(torch.autograd.Function):
+    """Z = table(eps_r, h, q) with the adjoint of cfft_backward.
+
+    eps_r and h are real 0-d float64 tensors, q complex128 [M][B].  The
+    forward keeps the sampled Green's function and spectra (the checkpoint of
+    the sampled integrand) for the backward.
+    """
+
+    @staticmethod
+    def forward(ctx, eps_r, h, q, tab: Tabulator, tan_delta: float, pairs, grid: int):
+        e = float(eps_r.item())
+        hh = float(h.item())
+        g = tab.green(e, tan_delta, hh, grid)
+        spec = tab.spectra(q.detach(), grid)
+        z = tab.tabulate(spec, g, pairs, grid)
+        ctx.save_for_backward(q.detach(), g, spec)
+        ctx.meta = (tab, tan_delta, list(pairs), grid, e, hh)
+        return z
+
+    @staticmethod
+    def backward(ctx, gz):
+        q, g, spec = ctx.saved_tensors
+        tab, tan_delta, pairs, grid, e, hh = ctx.meta
+        gz = gz.contiguous().to(torch.complex128)
+        grad_sub = torch.empty(2, dtype=torch.float64, device=gz.device)
+        grad_q = torch.empty_like(q)
+        cfft_backward(tab.plan, grid, gz, e, tan_delta, hh, tab.basis, q, pairs, g, spec, grad_sub, grad_q)
+        return grad_sub[0], grad_sub[1], grad_q, None, None, None, None
+
+
+class LookupFunction(torch.autograd.Function):
+    """Bilinear table lookup with its scatter-add adjoint."""
+
+    @staticmethod
+    def forward(ctx, z, pts, tab: Tabulator, grid: int):
+        out = tab.lookup(z, pts, grid)
+        ctx.save_for_backward(pts)
+        ctx.meta = (tab, grid, z.shape)
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        (pts,) = ctx.saved_tensors
+        tab, grid, shape = ctx.meta
+        dz = torch.zeros(shape, dtype=torch.complex128, device=gout.device)
+        cfft_lookup_backward(tab.plan, grid, gout.contiguous().to(torch.complex128), shape[0], pts, dz)
+        return dz, None, None, None

@@ -1,0 +1,662 @@
+// C-ABI layer of the contour-FFT library: argument validation, plans,
+// workspace and geometry management, and launch sequencing.  All arithmetic
+// of the method runs in the HIP kernels; this file only decides what to
+// launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cfft.h"
+#include "cfft_internal.h"
+
+using namespace cfft;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cfft_status_t fail(cfft_status_t st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+cfft_status_t hip_fail(hipError_t e, const char* what) {
+  return fail(CFFT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool env_flag(const char* name) {
+  const char* v = std::getenv(name);
+  return v && v[0] && std::strcmp(v, "0") != 0;
+}
+
+long long env_ll(const char* name, long long dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !v[0]) return dflt;
+  char* end = nullptr;
+  long long r = std::strtoll(v, &end, 10);
+  return (end && *end == 0) ? r : dflt;
+}
+
+// Device allocation with the test hook CFFT_TEST_FAIL_ALLOC=1.
+cfft_status_t dev_alloc(void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (env_flag("CFFT_TEST_FAIL_ALLOC")) return fail(CFFT_ERR_ALLOC, "%s: allocation refused (CFFT_TEST_FAIL_ALLOC)", what);
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(CFFT_ERR_ALLOC, "%s: hipMalloc(%zu) failed: %s", what, bytes, hipGetErrorString(e));
+  }
+  return CFFT_OK;
+}
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+struct GeomHost {
+  std::vector<GeomGroup> groups;
+  std::vector<double> xs, ys;
+  std::vector<int> index;
+  int total_p = 0, total_r = 0, total_idx = 0;
+};
+
+// Group bases by (kind, a, b); inside a group place each basis on the grid of
+// distinct centres.  A second basis on an occupied slot opens another group.
+bool build_geometry(const cfft_basis_t* basis, int nb, GeomHost& out) {
+  std::vector<int> pending(nb);
+  for (int i = 0; i < nb; ++i) pending[i] = i;
+  while (!pending.empty()) {
+    std::map<std::tuple<int, double, double>, std::vector<int>> by_shape;
+    for (int j : pending) by_shape[std::make_tuple(basis[j].kind, basis[j].a, basis[j].b)].push_back(j);
+    std::vector<int> overflow;
+    for (auto& kv : by_shape) {
+      const auto& mem = kv.second;
+      std::vector<double> xs, ys;
+      for (int j : mem) {
+        xs.push_back(basis[j].cx);
+        ys.push_back(basis[j].cy);
+      }
+      std::sort(xs.begin(), xs.end());
+      xs.erase(std::unique(xs.begin(), xs.end()), xs.end());
+      std::sort(ys.begin(), ys.end());
+      ys.erase(std::unique(ys.begin(), ys.end()), ys.end());
+      GeomGroup g;
+      g.kind = std::get<0>(kv.first);
+      g.a = std::get<1>(kv.first);
+      g.b = std::get<2>(kv.first);
+      g.np = (int)xs.size();
+      g.nr = (int)ys.size();
+      g.xoff = (int)out.xs.size();
+      g.yoff = (int)out.ys.size();
+      g.ioff = (int)out.index.size();
+      g.uoff = out.total_p;
+      std::vector<int> idx((size_t)g.np * g.nr, -1);
+      for (int j : mem) {
+        const int p = (int)(std::lower_bound(xs.begin(), xs.end(), basis[j].cx) - xs.begin());
+        const int r = (int)(std::lower_bound(ys.begin(), ys.end(), basis[j].cy) - ys.begin());
+        int& slot = idx[(size_t)p * g.nr + r];
+        if (slot < 0) slot = j;
+        else overflow.push_back(j);
+      }
+      out.xs.insert(out.xs.end(), xs.begin(), xs.end());
+      out.ys.insert(out.ys.end(), ys.begin(), ys.end());
+      out.index.insert(out.index.end(), idx.begin(), idx.end());
+      out.total_p += g.np;
+      out.total_r += g.nr;
+      out.total_idx += g.np * g.nr;
+      out.groups.push_back(g);
+      if ((int)out.groups.size() > 32) return false;
+    }
+    pending.swap(overflow);
+  }
+  return true;
+}
+
+uint64_t hash_bytes(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+}  // namespace
+
+struct GridState {
+  cfft_grid_desc_t d;
+  Axis x, y;
+  void* tw64x = nullptr;
+  void* tw64y = nullptr;
+  void* tw32x = nullptr;
+  void* tw32y = nullptr;
+  double2* utab = nullptr;       // spectra tables for the current geometry
+  uint64_t utab_geo = 0;
+  size_t utab_bytes = 0;
+};
+
+struct cfft_plan_s {
+  int device = 0;
+  int max_mbf = 0;
+  int flags = 0;
+  std::vector<GridState> grids;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* ws2 = nullptr;
+  size_t ws2_bytes = 0;
+  // geometry cache (one basis set at a time)
+  uint64_t geo_hash = 0;
+  int geo_nbasis = 0;
+  GeomHost geo_host;
+  GeomDevice geo_dev{};
+  void* geo_mem = nullptr;
+  int* flag_dev = nullptr;
+  int* flag_host = nullptr;
+};
+
+namespace {
+
+std::mutex g_plans_mu;
+std::set<cfft_plan_s*> g_plans;
+
+bool plan_live(cfft_plan_s* p) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  return g_plans.count(p) != 0;
+}
+
+void free_geometry(cfft_plan_s* p) {
+  if (p->geo_mem) (void)hipFree(p->geo_mem);
+  p->geo_mem = nullptr;
+  p->geo_hash = 0;
+  p->geo_nbasis = 0;
+  p->geo_dev = GeomDevice{};
+}
+
+cfft_status_t make_twiddles(int n, void** d64, void** d32) {
+  std::vector<double2> t64(n);
+  std::vector<float2> t32(n);
+  for (int j = 0; j < n; ++j) {
+    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)j / (long double)n;
+    const long double c = cosl(ang), s = sinl(ang);
+    t64[j] = make_double2((double)c, (double)s);
+    t32[j] = make_float2((float)c, (float)s);
+  }
+  cfft_status_t st = dev_alloc(d64, sizeof(double2) * n, "twiddles");
+  if (st != CFFT_OK) return st;
+  st = dev_alloc(d32, sizeof(float2) * n, "twiddles");
+  if (st != CFFT_OK) return st;
+  hipError_t e = hipMemcpy(*d64, t64.data(), sizeof(double2) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(*d32, t32.data(), sizeof(float2) * n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "twiddle upload");
+  return CFFT_OK;
+}
+
+cfft_status_t check_plan(cfft_plan_t plan, int grid) {
+  if (!plan) return fail(CFFT_ERR_INVALID_ARG, "plan is NULL");
+  if (!plan_live(plan)) return fail(CFFT_ERR_INVALID_ARG, "unknown or destroyed plan");
+  if (grid < 0 || grid >= (int)plan->grids.size())
+    return fail(CFFT_ERR_INVALID_ARG, "grid index %d out of range [0, %zu)", grid, plan->grids.size());
+  hipError_t e = hipSetDevice(plan->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return CFFT_OK;
+}
+
+PassParams pass_params(const GridState& gs) {
+  PassParams p;
+  p.x = gs.x;
+  p.y = gs.y;
+  p.gamma = gs.d.gamma;
+  p.order = gs.d.order;
+  p.precision = gs.d.precision;
+  return p;
+}
+
+cfft_status_t ensure_ws(void** ws, size_t* have, size_t need, const char* what) {
+  if (*have >= need) return CFFT_OK;
+  if (*ws) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronise before workspace growth");
+    (void)hipFree(*ws);
+    *ws = nullptr;
+    *have = 0;
+  }
+  cfft_status_t st = dev_alloc(ws, need, what);
+  if (st != CFFT_OK) return st;
+  *have = need;
+  return CFFT_OK;
+}
+
+cfft_status_t validate_basis(const cfft_basis_t* basis, int nbasis) {
+  if (!basis) return fail(CFFT_ERR_INVALID_ARG, "basis is NULL");
+  if (nbasis < 1 || nbasis > 65536) return fail(CFFT_ERR_INVALID_ARG, "nbasis %d outside [1, 65536]", nbasis);
+  for (int j = 0; j < nbasis; ++j) {
+    const cfft_basis_t& b = basis[j];
+    if (b.kind < CFFT_ROOFTOP_X || b.kind > CFFT_COSINE_Y)
+      return fail(CFFT_ERR_INVALID_ARG, "basis %d: unknown kind %d", j, b.kind);
+    if (b.pad != 0) return fail(CFFT_ERR_INVALID_ARG, "basis %d: pad must be 0", j);
+    if (!(std::isfinite(b.cx) && std::isfinite(b.cy) && b.a > 0 && b.b > 0 && std::isfinite(b.a) &&
+          std::isfinite(b.b)))
+      return fail(CFFT_ERR_INVALID_ARG, "basis %d: non-finite centre or non-positive size", j);
+  }
+  return CFFT_OK;
+}
+
+// Upload (or reuse) the separable geometry of a basis set and make sure the
+// grid's spectra tables match it.
+cfft_status_t ensure_geometry(cfft_plan_s* plan, GridState& gs, const cfft_basis_t* basis, int nbasis,
+                              hipStream_t s) {
+  const uint64_t h = hash_bytes(basis, sizeof(cfft_basis_t) * (size_t)nbasis, (uint64_t)nbasis * 0x9e3779b97f4a7c15ull);
+  if (!(plan->geo_mem && plan->geo_hash == h && plan->geo_nbasis == nbasis)) {
+    GeomHost gh;
+    if (!build_geometry(basis, nbasis, gh))
+      return fail(CFFT_ERR_UNSUPPORTED, "basis set needs more than 32 shape groups");
+    if ((size_t)plan->max_mbf * gh.total_p * 2 * sizeof(double2) > 65536)
+      return fail(CFFT_ERR_UNSUPPORTED, "max_mbf * distinct x-centres (%d * %d) too large for the LDS tables",
+                  plan->max_mbf, gh.total_p);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "synchronise before geometry upload");
+    free_geometry(plan);
+    const size_t bg = sizeof(GeomGroup) * gh.groups.size();
+    const size_t bx = sizeof(double) * gh.xs.size();
+    const size_t by = sizeof(double) * gh.ys.size();
+    const size_t bi = sizeof(int) * gh.index.size();
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t total = al(bg) + al(bx) + al(by) + al(bi);
+    cfft_status_t st = dev_alloc(&plan->geo_mem, total, "geometry");
+    if (st != CFFT_OK) return st;
+    char* base = (char*)plan->geo_mem;
+    GeomDevice gd;
+    gd.ngroups = (int)gh.groups.size();
+    gd.nbasis = nbasis;
+    gd.total_p = gh.total_p;
+    gd.total_r = gh.total_r;
+    gd.total_idx = gh.total_idx;
+    gd.groups = (GeomGroup*)base;
+    gd.xs = (double*)(base + al(bg));
+    gd.ys = (double*)(base + al(bg) + al(bx));
+    gd.index = (int*)(base + al(bg) + al(bx) + al(by));
+    e = hipMemcpy(gd.groups, gh.groups.data(), bg, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(gd.xs, gh.xs.data(), bx, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(gd.ys, gh.ys.data(), by, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(gd.index, gh.index.data(), bi, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_geometry(plan);
+      return hip_fail(e, "geometry upload");
+    }
+    plan->geo_dev = gd;
+    plan->geo_host = gh;
+    plan->geo_hash = h;
+    plan->geo_nbasis = nbasis;
+    for (auto& g : plan->grids) g.utab_geo = 0;
+  }
+  if (gs.utab_geo != plan->geo_hash) {
+    const size_t need = sizeof(double2) * (size_t)(2 * plan->geo_dev.total_p + plan->geo_dev.ngroups) * gs.x.n;
+    if (gs.utab_bytes < need) {
+      if (gs.utab) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "synchronise before table growth");
+        (void)hipFree(gs.utab);
+        gs.utab = nullptr;
+        gs.utab_bytes = 0;
+      }
+      cfft_status_t st = dev_alloc((void**)&gs.utab, need, "spectra tables");
+      if (st != CFFT_OK) return st;
+      gs.utab_bytes = need;
+    }
+    hipError_t e = launch_spectra_tables(gs.x, gs.d.gamma, plan->geo_dev, gs.utab, s);
+    if (e != hipSuccess) return hip_fail(e, "spectra tables launch");
+    gs.utab_geo = plan->geo_hash;
+  }
+  return CFFT_OK;
+}
+
+cfft_status_t validate_pairs(const int32_t* pairs, int npairs, int nmbf) {
+  if (!pairs) return fail(CFFT_ERR_INVALID_ARG, "pairs is NULL");
+  if (npairs < 1 || npairs > 4096) return fail(CFFT_ERR_INVALID_ARG, "npairs %d outside [1, 4096]", npairs);
+  for (int i = 0; i < npairs; ++i) {
+    if (pairs[2 * i] < 0 || pairs[2 * i] >= nmbf || pairs[2 * i + 1] < 0 || pairs[2 * i + 1] >= nmbf)
+      return fail(CFFT_ERR_INVALID_ARG, "pair %d = (%d, %d) outside [0, %d)", i, pairs[2 * i], pairs[2 * i + 1], nmbf);
+  }
+  return CFFT_OK;
+}
+
+__global__ void nonfinite_kernel(const double* v, size_t n, int* flag) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(v[i])) {
+      *flag = 1;
+      return;
+    }
+}
+__global__ void nonfinite_kernel_f(const float* v, size_t n, int* flag) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(v[i])) {
+      *flag = 1;
+      return;
+    }
+}
+
+cfft_status_t check_finite(cfft_plan_s* plan, const void* data, size_t nreal, bool fp32, hipStream_t s) {
+  if (!(plan->flags & CFFT_FLAG_CHECK_FINITE)) return CFFT_OK;
+  hipError_t e = hipMemsetAsync(plan->flag_dev, 0, sizeof(int), s);
+  if (e != hipSuccess) return hip_fail(e, "flag reset");
+  if (fp32)
+    hipLaunchKernelGGL(nonfinite_kernel_f, dim3(1024), dim3(256), 0, s, (const float*)data, nreal, plan->flag_dev);
+  else
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(1024), dim3(256), 0, s, (const double*)data, nreal, plan->flag_dev);
+  e = hipMemcpyAsync(plan->flag_host, plan->flag_dev, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "non-finite check");
+  if (*plan->flag_host) return fail(CFFT_ERR_NONFINITE, "output contains NaN or Inf");
+  return CFFT_OK;
+}
+
+void release_plan(cfft_plan_s* plan) {
+  (void)hipSetDevice(plan->device);
+  (void)hipDeviceSynchronize();
+  for (auto& g : plan->grids) {
+    if (g.tw64x) (void)hipFree(g.tw64x);
+    if (g.tw64y) (void)hipFree(g.tw64y);
+    if (g.tw32x) (void)hipFree(g.tw32x);
+    if (g.tw32y) (void)hipFree(g.tw32y);
+    if (g.utab) (void)hipFree(g.utab);
+  }
+  if (plan->ws) (void)hipFree(plan->ws);
+  if (plan->ws2) (void)hipFree(plan->ws2);
+  if (plan->flag_dev) (void)hipFree(plan->flag_dev);
+  if (plan->flag_host) (void)hipHostFree(plan->flag_host);
+  free_geometry(plan);
+  delete plan;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cfft_last_error(void) { return g_last_error.c_str(); }
+
+const char* cfft_version(void) { return "cfft-mi355x 0.1 (gfx950)"; }
+
+cfft_status_t c_fft_plan(const cfft_grid_desc_t* grids, int32_t ngrids, int32_t max_mbf, int32_t flags,
+                         cfft_plan_t* out) {
+  g_last_error.clear();
+  if (!out) return fail(CFFT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!grids) return fail(CFFT_ERR_INVALID_ARG, "grids is NULL");
+  if (ngrids < 1 || ngrids > 64) return fail(CFFT_ERR_INVALID_ARG, "ngrids %d outside [1, 64]", ngrids);
+  if (max_mbf < 1 || max_mbf > 16) return fail(CFFT_ERR_INVALID_ARG, "max_mbf %d outside [1, 16]", max_mbf);
+  if (flags & ~CFFT_FLAG_CHECK_FINITE) return fail(CFFT_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+  for (int i = 0; i < ngrids; ++i) {
+    const cfft_grid_desc_t& g = grids[i];
+    if (!pow2_in(g.nx, 16, 4096) || !pow2_in(g.ny, 16, 4096))
+      return fail(CFFT_ERR_INVALID_ARG, "grid %d: nx, ny = %d, %d must be powers of two in [16, 4096]", i, g.nx, g.ny);
+    if (!(g.kx_max > 0 && g.ky_max > 0 && std::isfinite(g.kx_max) && std::isfinite(g.ky_max)))
+      return fail(CFFT_ERR_INVALID_ARG, "grid %d: kx_max, ky_max must be finite and > 0", i);
+    if (!(g.k0 > 0 && std::isfinite(g.k0))) return fail(CFFT_ERR_INVALID_ARG, "grid %d: k0 must be finite and > 0", i);
+    if (!(g.gamma > 0 && std::isfinite(g.gamma))) return fail(CFFT_ERR_INVALID_ARG, "grid %d: gamma must be > 0", i);
+    if (g.order < 0 || g.order > kMaxOrder)
+      return fail(CFFT_ERR_INVALID_ARG, "grid %d: order %d outside [0, %d]", i, g.order, kMaxOrder);
+    if (g.precision != CFFT_FP64 && g.precision != CFFT_MIXED)
+      return fail(CFFT_ERR_INVALID_ARG, "grid %d: unknown precision %d", i, g.precision);
+    if (g.reserved != 0) return fail(CFFT_ERR_INVALID_ARG, "grid %d: reserved must be 0", i);
+    if (g.contour == CFFT_CONTOUR_PARABOLIC)
+      return fail(CFFT_ERR_UNSUPPORTED, "grid %d: the parabolic contour is not implemented (use RAY)", i);
+    if (g.contour != CFFT_CONTOUR_RAY) return fail(CFFT_ERR_INVALID_ARG, "grid %d: unknown contour %d", i, g.contour);
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(CFFT_ERR_HIP, "no HIP device available (%s)", e == hipSuccess ? "0 devices" : hipGetErrorString(e));
+  }
+  cfft_plan_s* p = new (std::nothrow) cfft_plan_s();
+  if (!p) return fail(CFFT_ERR_ALLOC, "host allocation of the plan failed");
+  e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  p->max_mbf = max_mbf;
+  p->flags = flags;
+  p->grids.resize(ngrids);
+  for (int i = 0; i < ngrids; ++i) {
+    GridState& gs = p->grids[i];
+    gs.d = grids[i];
+    const double xm = gs.d.nx * M_PI / (2.0 * gs.d.kx_max);
+    const double ym = gs.d.ny * M_PI / (2.0 * gs.d.ky_max);
+    gs.x = Axis{gs.d.nx, -gs.d.kx_max, 2.0 * gs.d.kx_max / gs.d.nx, -xm, M_PI / gs.d.kx_max};
+    gs.y = Axis{gs.d.ny, -gs.d.ky_max, 2.0 * gs.d.ky_max / gs.d.ny, -ym, M_PI / gs.d.ky_max};
+    cfft_status_t st = make_twiddles(gs.d.nx, &gs.tw64x, &gs.tw32x);
+    if (st == CFFT_OK) st = make_twiddles(gs.d.ny, &gs.tw64y, &gs.tw32y);
+    if (st != CFFT_OK) {
+      release_plan(p);
+      return st;
+    }
+  }
+  cfft_status_t st = dev_alloc((void**)&p->flag_dev, sizeof(int), "flag");
+  if (st != CFFT_OK) {
+    release_plan(p);
+    return st;
+  }
+  e = hipHostMalloc((void**)&p->flag_host, sizeof(int), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    p->flag_host = nullptr;
+    release_plan(p);
+    return fail(CFFT_ERR_ALLOC, "pinned flag allocation failed: %s", hipGetErrorString(e));
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    g_plans.insert(p);
+  }
+  *out = p;
+  return CFFT_OK;
+}
+
+cfft_status_t c_fft_plan_destroy(cfft_plan_t plan) {
+  g_last_error.clear();
+  if (!plan) return CFFT_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    if (!g_plans.erase(plan)) return fail(CFFT_ERR_INVALID_ARG, "unknown or already destroyed plan");
+  }
+  release_plan(plan);
+  return CFFT_OK;
+}
+
+cfft_status_t slab_green_eval(cfft_plan_t plan, int32_t grid, double eps_r, double tan_delta, double h, void* g,
+                              void* stream) {
+  g_last_error.clear();
+  cfft_status_t st = check_plan(plan, grid);
+  if (st != CFFT_OK) return st;
+  if (!g) return fail(CFFT_ERR_INVALID_ARG, "g is NULL");
+  if (!(std::isfinite(eps_r) && eps_r >= 1.0)) return fail(CFFT_ERR_INVALID_ARG, "eps_r must be finite and >= 1");
+  if (!(std::isfinite(tan_delta) && tan_delta >= 0.0))
+    return fail(CFFT_ERR_INVALID_ARG, "tan_delta must be finite and >= 0");
+  if (!(std::isfinite(h) && h > 0.0)) return fail(CFFT_ERR_INVALID_ARG, "h must be finite and > 0");
+  GridState& gs = plan->grids[grid];
+  GreenParams p{gs.x, gs.y, gs.d.gamma, gs.d.k0, eps_r, tan_delta, h};
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_green(p, (double2*)g, s);
+  if (e != hipSuccess) return hip_fail(e, "slab_green_eval launch");
+  return check_finite(plan, g, (size_t)6 * gs.x.n * gs.y.n, false, s);
+}
+
+cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* basis, int32_t nbasis, const void* q,
+                          int32_t nmbf, void* spec, void* stream) {
+  g_last_error.clear();
+  cfft_status_t st = check_plan(plan, grid);
+  if (st != CFFT_OK) return st;
+  if (!q || !spec) return fail(CFFT_ERR_INVALID_ARG, "q or spec is NULL");
+  if (nmbf < 1 || nmbf > plan->max_mbf)
+    return fail(CFFT_ERR_INVALID_ARG, "nmbf %d outside [1, max_mbf = %d]", nmbf, plan->max_mbf);
+  st = validate_basis(basis, nbasis);
+  if (st != CFFT_OK) return st;
+  GridState& gs = plan->grids[grid];
+  hipStream_t s = (hipStream_t)stream;
+  st = ensure_geometry(plan, gs, basis, nbasis, s);
+  if (st != CFFT_OK) return st;
+  hipError_t e = launch_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, (const double2*)q, nmbf,
+                                (double2*)spec, s);
+  if (e != hipSuccess) return hip_fail(e, "mbf_spectra launch");
+  return check_finite(plan, spec, (size_t)8 * nmbf * gs.x.n * gs.y.n, false, s);
+}
+
+cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, int32_t nmbf, const void* g,
+                            const int32_t* pairs, int32_t npairs, void* z, void* stream) {
+  g_last_error.clear();
+  cfft_status_t st = check_plan(plan, grid);
+  if (st != CFFT_OK) return st;
+  if (!spec || !g || !z) return fail(CFFT_ERR_INVALID_ARG, "spec, g or z is NULL");
+  if (nmbf < 1 || nmbf > plan->max_mbf)
+    return fail(CFFT_ERR_INVALID_ARG, "nmbf %d outside [1, max_mbf = %d]", nmbf, plan->max_mbf);
+  st = validate_pairs(pairs, npairs, nmbf);
+  if (st != CFFT_OK) return st;
+  GridState& gs = plan->grids[grid];
+  const PassParams pp = pass_params(gs);
+  const size_t n = (size_t)gs.x.n * gs.y.n;
+  const size_t cbytes = pp.precision == CFFT_FP64 ? 16 : 8;
+  const size_t per_pair = (size_t)(pp.order + 1) * n * cbytes;
+  const long long limit_mb = env_ll("CFFT_WORKSPACE_MB", 16384);
+  long long chunk = std::max<long long>(1, (limit_mb << 20) / (long long)per_pair);
+  chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
+  const long long forced = env_ll("CFFT_PAIR_CHUNK", 0);
+  if (forced > 0) chunk = std::min<long long>(chunk, forced);
+  hipStream_t s = (hipStream_t)stream;
+  st = ensure_ws(&plan->ws, &plan->ws_bytes, per_pair * (size_t)chunk, "pass workspace");
+  if (st != CFFT_OK) return st;
+  const void* twx = pp.precision == CFFT_FP64 ? gs.tw64x : gs.tw32x;
+  const void* twy = pp.precision == CFFT_FP64 ? gs.tw64y : gs.tw32y;
+  std::vector<int> pm(npairs), pn(npairs);
+  for (int i = 0; i < npairs; ++i) {
+    pm[i] = pairs[2 * i];
+    pn[i] = pairs[2 * i + 1];
+  }
+  for (int p0 = 0; p0 < npairs; p0 += (int)chunk) {
+    const int np = (int)std::min<long long>(chunk, npairs - p0);
+    hipError_t e = launch_row_pass(pp, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np,
+                                   plan->ws, twx, s);
+    if (e != hipSuccess) return hip_fail(e, "row pass launch");
+    e = launch_col_pass(pp, plan->ws, np, (char*)z + (size_t)p0 * n * cbytes, twy, s);
+    if (e != hipSuccess) return hip_fail(e, "column pass launch");
+  }
+  return check_finite(plan, z, 2 * n * (size_t)npairs, pp.precision != CFFT_FP64, s);
+}
+
+cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t npairs, const double* pts,
+                          int32_t npts, void* out, void* stream) {
+  g_last_error.clear();
+  cfft_status_t st = check_plan(plan, grid);
+  if (st != CFFT_OK) return st;
+  if (!z || !pts || !out) return fail(CFFT_ERR_INVALID_ARG, "z, pts or out is NULL");
+  if (npairs < 1 || npairs > 4096) return fail(CFFT_ERR_INVALID_ARG, "npairs %d outside [1, 4096]", npairs);
+  if (npts < 1 || (long long)npts * npairs > (1LL << 31) - 1)
+    return fail(CFFT_ERR_INVALID_ARG, "npts %d invalid", npts);
+  GridState& gs = plan->grids[grid];
+  hipError_t e = launch_lookup(pass_params(gs), z, npairs, pts, npts, (double2*)out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "lookup launch");
+  return CFFT_OK;
+}
+
+cfft_status_t cfft_lookup_backward(cfft_plan_t plan, int32_t grid, const void* dout, int32_t npairs,
+                                   const double* pts, int32_t npts, void* dz, void* stream) {
+  g_last_error.clear();
+  cfft_status_t st = check_plan(plan, grid);
+  if (st != CFFT_OK) return st;
+  if (!dout || !pts || !dz) return fail(CFFT_ERR_INVALID_ARG, "dout, pts or dz is NULL");
+  if (npairs < 1 || npairs > 4096) return fail(CFFT_ERR_INVALID_ARG, "npairs %d outside [1, 4096]", npairs);
+  if (npts < 1 || (long long)npts * npairs > (1LL << 31) - 1)
+    return fail(CFFT_ERR_INVALID_ARG, "npts %d invalid", npts);
+  GridState& gs = plan->grids[grid];
+  if (gs.d.precision != CFFT_FP64) return fail(CFFT_ERR_UNSUPPORTED, "lookup adjoint needs an FP64 grid");
+  hipError_t e =
+      launch_lookup_backward(pass_params(gs), (const double2*)dout, npairs, pts, npts, (double2*)dz, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "lookup adjoint launch");
+  return CFFT_OK;
+}
+
+cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, double eps_r, double tan_delta, double h,
+                            const cfft_basis_t* basis, int32_t nbasis, const void* q, int32_t nmbf,
+                            const int32_t* pairs, int32_t npairs, const void* g, const void* spec, double* grad_sub,
+                            void* grad_q, void* stream) {
+  g_last_error.clear();
+  cfft_status_t st = check_plan(plan, grid);
+  if (st != CFFT_OK) return st;
+  if (!dz || !q || !g || !spec || !grad_sub || !grad_q)
+    return fail(CFFT_ERR_INVALID_ARG, "dz, q, g, spec, grad_sub or grad_q is NULL");
+  if (!(std::isfinite(eps_r) && eps_r >= 1.0)) return fail(CFFT_ERR_INVALID_ARG, "eps_r must be finite and >= 1");
+  if (!(std::isfinite(tan_delta) && tan_delta >= 0.0))
+    return fail(CFFT_ERR_INVALID_ARG, "tan_delta must be finite and >= 0");
+  if (!(std::isfinite(h) && h > 0.0)) return fail(CFFT_ERR_INVALID_ARG, "h must be finite and > 0");
+  if (nmbf < 1 || nmbf > plan->max_mbf)
+    return fail(CFFT_ERR_INVALID_ARG, "nmbf %d outside [1, max_mbf = %d]", nmbf, plan->max_mbf);
+  st = validate_basis(basis, nbasis);
+  if (st != CFFT_OK) return st;
+  st = validate_pairs(pairs, npairs, nmbf);
+  if (st != CFFT_OK) return st;
+  GridState& gs = plan->grids[grid];
+  if (gs.d.precision != CFFT_FP64) return fail(CFFT_ERR_UNSUPPORTED, "the adjoint needs an FP64 grid");
+  hipStream_t s = (hipStream_t)stream;
+  st = ensure_geometry(plan, gs, basis, nbasis, s);
+  if (st != CFFT_OK) return st;
+  const PassParams pp = pass_params(gs);
+  const size_t n = (size_t)gs.x.n * gs.y.n;
+  const size_t per_pair = (size_t)(pp.order + 1) * n * 16 + n * 16;   // intermediates + gH
+  const long long limit_mb = env_ll("CFFT_WORKSPACE_MB", 16384);
+  long long chunk = std::max<long long>(1, (limit_mb << 20) / (long long)per_pair);
+  chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
+  const int green_blocks = 1024;
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t b_gg = al(3 * n * 16), b_gs = al((size_t)nmbf * 4 * n * 16);
+  const size_t b_row = al(adj_spectra_scratch(gs.y, plan->geo_dev, nmbf));
+  const size_t b_part = al(sizeof(double) * 2 * green_blocks);
+  st = ensure_ws(&plan->ws, &plan->ws_bytes, per_pair * (size_t)chunk, "adjoint workspace");
+  if (st != CFFT_OK) return st;
+  st = ensure_ws(&plan->ws2, &plan->ws2_bytes, b_gg + b_gs + b_row + b_part, "adjoint scratch");
+  if (st != CFFT_OK) return st;
+  char* w2 = (char*)plan->ws2;
+  double2* gg = (double2*)w2;
+  double2* gspec = (double2*)(w2 + b_gg);
+  double2* rowacc = (double2*)(w2 + b_gg + b_gs);
+  double* partial = (double*)(w2 + b_gg + b_gs + b_row);
+  double2* inter = (double2*)plan->ws;
+  double2* gi = (double2*)((char*)plan->ws + (size_t)(pp.order + 1) * n * 16 * chunk);
+  std::vector<int> pm(npairs), pn(npairs);
+  for (int i = 0; i < npairs; ++i) {
+    pm[i] = pairs[2 * i];
+    pn[i] = pairs[2 * i + 1];
+  }
+  for (int p0 = 0; p0 < npairs; p0 += (int)chunk) {
+    const int np = (int)std::min<long long>(chunk, npairs - p0);
+    hipError_t e = launch_adj_col_pass(pp, (const double2*)dz + (size_t)p0 * n, np, inter, gs.tw64y, s);
+    if (e == hipSuccess) e = launch_adj_row_pass(pp, inter, np, gi, gs.tw64x, s);
+    if (e == hipSuccess)
+      e = launch_adj_integrand(pp, gi, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np,
+                               nmbf, gg, gspec, p0 > 0 ? 1 : 0, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+  }
+  GreenParams gp{gs.x, gs.y, gs.d.gamma, gs.d.k0, eps_r, tan_delta, h};
+  hipError_t e = launch_adj_green(gp, gg, partial, green_blocks, s);
+  if (e == hipSuccess) e = launch_reduce_sum(partial, green_blocks, 2, grad_sub, s);
+  if (e == hipSuccess)
+    e = launch_adj_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, gspec, nmbf, rowacc, (double2*)grad_q, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint reduction launch");
+  return CFFT_OK;
+}
+
+}  // extern "C"

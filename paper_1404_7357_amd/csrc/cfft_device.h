@@ -1,0 +1,242 @@
+// Device-side building blocks for gfx950: complex arithmetic in FP64/FP32,
+// the radiating square root, and an LDS-exchanged Stockham FFT whose
+// butterflies run in registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cfft {
+
+// ---------------------------------------------------------------- complex
+template <typename R> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+
+template <typename V> struct real_of;
+template <> struct real_of<double2> { using type = double; };
+template <> struct real_of<float2> { using type = float; };
+
+__device__ __forceinline__ double2 mk(double x, double y) { return make_double2(x, y); }
+__device__ __forceinline__ float2 mk(float x, float y) { return make_float2(x, y); }
+
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
+  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) { return mk(a.x * s, a.y * s); }
+template <typename V> __device__ __forceinline__ V cconj(V a) { return mk(a.x, -a.y); }
+// multiply by i, by -i
+template <typename V> __device__ __forceinline__ V cmul_i(V a) { return mk(-a.y, a.x); }
+template <typename V> __device__ __forceinline__ V cmul_mi(V a) { return mk(a.y, -a.x); }
+
+__device__ __forceinline__ double2 to_d(double2 a) { return a; }
+__device__ __forceinline__ double2 to_d(float2 a) { return make_double2(a.x, a.y); }
+template <typename V> __device__ __forceinline__ V from_d(double2 a);
+template <> __device__ __forceinline__ double2 from_d<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 from_d<float2>(double2 a) {
+  return make_float2((float)a.x, (float)a.y);
+}
+
+// Smith's division (no intermediate overflow for large operands).
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, den = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / den, (a.y - a.x * r) / den);
+  }
+  const double r = b.x / b.y, den = b.x * r + b.y;
+  return make_double2((a.x * r + a.y) / den, (a.y * r - a.x) / den);
+}
+
+__device__ __forceinline__ double2 cexp(double2 z) {
+  double s, c;
+  sincos(z.y, &s, &c);
+  const double e = exp(z.x);
+  return make_double2(e * c, e * s);
+}
+
+// exp(z) - 1 without cancellation for small |z|.
+__device__ __forceinline__ double2 cexpm1(double2 z) {
+  double s, c;
+  sincos(z.y, &s, &c);
+  const double em1 = expm1(z.x);
+  // Re: e^x cos y - 1 = (e^x - 1) cos y - 2 sin^2(y/2)
+  const double sh = sin(0.5 * z.y);
+  return make_double2(em1 * c - 2.0 * sh * sh, (em1 + 1.0) * s);
+}
+
+// Principal square root.
+__device__ __forceinline__ double2 csqrt_principal(double2 z) {
+  if (z.x == 0.0 && z.y == 0.0) return make_double2(0.0, z.y);
+  const double r = hypot(z.x, z.y);
+  const double t = sqrt(0.5 * (r + fabs(z.x)));
+  if (z.x >= 0.0) return make_double2(t, z.y / (2.0 * t));
+  return make_double2(fabs(z.y) / (2.0 * t), copysign(t, z.y));
+}
+
+// Vertical wavenumber on the radiating branch: the root whose cut lies on the
+// positive imaginary axis, i.e. arg in (-3pi/4, pi/4].  On the closed lower
+// half plane (passive media, deformed contour) this is Im <= 0, Re >= 0 when
+// propagating; elsewhere it continues analytically.
+__device__ __forceinline__ double2 csqrt_radiating(double2 z) {
+  double2 w = csqrt_principal(z);
+  if (w.y > w.x) w = make_double2(-w.x, -w.y);
+  return w;
+}
+
+// sin(z)/z for complex z with the removable point handled by its series.
+__device__ __forceinline__ double2 csinc(double2 z) {
+  const double a2 = z.x * z.x + z.y * z.y;
+  if (a2 < 1e-8) {
+    const double2 z2 = cmul(z, z);
+    const double2 z4 = cmul(z2, z2);
+    return make_double2(1.0 - z2.x / 6.0 + z4.x / 120.0, -z2.y / 6.0 + z4.y / 120.0);
+  }
+  double s, c;
+  sincos(z.x, &s, &c);
+  const double sh = sinh(z.y), ch = cosh(z.y);
+  return cdiv(make_double2(s * ch, c * sh), z);
+}
+
+// ---------------------------------------------------------------- FFT
+__host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+// In-register forward DFT of 2, 4 or 8 points (omega = exp(-2 pi i / n)).
+template <typename V> __device__ __forceinline__ void dft2(V& a, V& b) {
+  const V t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <typename V> __device__ __forceinline__ void dft4(V& x0, V& x1, V& x2, V& x3) {
+  const V s02 = cadd(x0, x2), d02 = csub(x0, x2);
+  const V s13 = cadd(x1, x3), d13 = csub(x1, x3);
+  x0 = cadd(s02, s13);
+  x2 = csub(s02, s13);
+  x1 = cadd(d02, cmul_mi(d13));
+  x3 = csub(d02, cmul_mi(d13));
+}
+
+template <typename V> __device__ __forceinline__ void dft8(V* x) {
+  using R = typename real_of<V>::type;
+  const R h = (R)0.70710678118654752440;
+  V e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+  V o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  // o_k *= omega8^k
+  o1 = mk((R)((o1.x + o1.y) * h), (R)((o1.y - o1.x) * h));
+  o2 = cmul_mi(o2);
+  o3 = mk((R)((o3.y - o3.x) * h), (R)(-(o3.x + o3.y) * h));
+  x[0] = cadd(e0, o0);
+  x[4] = csub(e0, o0);
+  x[1] = cadd(e1, o1);
+  x[5] = csub(e1, o1);
+  x[2] = cadd(e2, o2);
+  x[6] = csub(e2, o2);
+  x[3] = cadd(e3, o3);
+  x[7] = csub(e3, o3);
+}
+
+template <typename V, int RHO> __device__ __forceinline__ void dft_small(V* y) {
+  if constexpr (RHO == 2) dft2(y[0], y[1]);
+  else if constexpr (RHO == 4) dft4(y[0], y[1], y[2], y[3]);
+  else dft8(y);
+}
+
+// One Stockham stage of radix RHO on a length-N transform spread over
+// T = N/R threads, each holding R points at stride T (x[r] = data[t + T r]).
+// L is the length of the sub-transforms already done.  Non-final stages
+// exchange through `lds` (N entries); the final stage leaves the outputs in
+// registers in the same stride-T order.
+template <typename V, int N, int R, int RHO, bool LAST>
+__device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* __restrict__ tw, int t, int L) {
+  constexpr int T = N / R;
+  constexpr int BPT = R / RHO;
+#pragma unroll
+  for (int mb = 0; mb < BPT; ++mb) {
+    const int i = t + T * mb;
+    const int k = i & (L - 1);
+    V y[RHO];
+#pragma unroll
+    for (int j = 0; j < RHO; ++j) y[j] = x[mb + j * BPT];
+    if (L > 1) {
+      const int step = N / (L * RHO);
+#pragma unroll
+      for (int j = 1; j < RHO; ++j) y[j] = cmul(y[j], tw[j * k * step]);
+    }
+    dft_small<V, RHO>(y);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int q = 0; q < RHO; ++q) x[mb + q * BPT] = y[q];
+    } else {
+      const int base = (i - k) * RHO + k;
+#pragma unroll
+      for (int q = 0; q < RHO; ++q) lds[base + q * L] = y[q];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = lds[t + T * r];
+    __syncthreads();
+  }
+}
+
+// Forward DFT X[j] = sum_n x[n] exp(-2 pi i n j / N), N = 2^m, 8 <= N.
+// Radices: one leading radix-2 or radix-4 stage when log2 N is not a
+// multiple of 3, then radix-8 stages.  All threads of the block must call
+// it (it contains block barriers).
+template <typename V, int N, int R>
+__device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* __restrict__ tw, int t) {
+  static_assert(R == 8, "8 points per thread");
+  constexpr int LOG = ilog2c(N);
+  constexpr int NR8 = LOG / 3;
+  constexpr int REM = LOG % 3;
+  int L = 1;
+  if constexpr (REM == 1) {
+    stockham_stage<V, N, R, 2, NR8 == 0>(x, lds, tw, t, L);
+    L *= 2;
+  } else if constexpr (REM == 2) {
+    stockham_stage<V, N, R, 4, NR8 == 0>(x, lds, tw, t, L);
+    L *= 4;
+  }
+  if constexpr (NR8 >= 1) {
+    if constexpr (NR8 >= 2) {
+#pragma unroll
+      for (int s = 0; s < NR8 - 1; ++s) {
+        stockham_stage<V, N, R, 8, false>(x, lds, tw, t, L);
+        L *= 8;
+      }
+    }
+    stockham_stage<V, N, R, 8, true>(x, lds, tw, t, L);
+  }
+}
+
+// Inverse (unnormalised) DFT: conj(DFT(conj x)).
+template <typename V, int N, int R>
+__device__ __forceinline__ void fft_inverse(V (&x)[R], V* lds, const V* __restrict__ tw, int t) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = cconj(x[r]);
+  fft_forward<V, N, R>(x, lds, tw, t);
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = cconj(x[r]);
+}
+
+// XCD-aware remap of the block index: the hardware deals consecutive block
+// ids round-robin to the 8 XCDs; this returns a logical id such that
+// consecutive logical ids run on the same XCD (and so share its L2).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int NXCD = 8;
+  const int per = nblocks / NXCD;
+  const int full = per * NXCD;
+  if (bid >= full) return bid;
+  return (bid % NXCD) * per + bid / NXCD;
+}
+
+}  // namespace cfft

@@ -1,0 +1,97 @@
+// Host-side interfaces between the C-ABI layer (cfft_api.cpp) and the kernel
+// launchers (*.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cfft {
+
+constexpr int kMaxPairsPerLaunch = 64;
+constexpr int kMaxOrder = 7;
+
+// Sampling of one axis: k(n) = k0 + n dk, D(j) = d0 + j dd.
+struct Axis {
+  int n;
+  double k_first, dk;   // spectral samples
+  double d_first, dd;   // output displacements
+};
+
+struct GreenParams {
+  Axis x, y;
+  double gamma, k0;
+  double eps_re, tan_delta, h;
+};
+
+// Separable geometry of a basis set: bases sharing (kind, a, b) form a
+// group; inside a group every basis sits on the product of the group's
+// distinct x- and y-centres, so its spectrum factorises in kx and ky.
+struct GeomGroup {
+  int kind;
+  int np, nr;         // distinct x-centres (p), distinct y-centres (r)
+  int xoff, yoff;     // offsets into the x / y centre arrays
+  int ioff;           // offset into the [np][nr] basis index array (-1 = empty slot)
+  int uoff;           // row offset of this group's x tables (U rows)
+  double a, b;
+};
+
+struct GeomDevice {
+  int ngroups;
+  int nbasis;
+  int total_p;        // sum of np
+  int total_r;        // sum of nr
+  int total_idx;      // sum of np*nr
+  GeomGroup* groups;  // device copies
+  double* xs;         // [total_p]
+  double* ys;         // [total_r]
+  int* index;         // [total_idx]
+};
+
+struct PassParams {
+  Axis x, y;
+  double gamma;
+  int order;
+  int precision;      // 0 FP64, 1 MIXED
+};
+
+// Launchers; all return hipSuccess or the launch error.
+hipError_t launch_green(const GreenParams& p, double2* g, hipStream_t s);
+
+hipError_t launch_spectra_tables(const Axis& x, double gamma, const GeomDevice& geo, double2* utab,
+                                 hipStream_t s);
+hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
+                          const double2* utab, const double2* q, int nmbf, double2* spec,
+                          hipStream_t s);
+
+// Row + column passes for one chunk of <= kMaxPairsPerLaunch pairs.
+hipError_t launch_row_pass(const PassParams& p, const double2* g, const double2* spec,
+                           const int* pm, const int* pn, int npairs, void* inter,
+                           const void* twx, hipStream_t s);
+hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, void* z,
+                           const void* twy, hipStream_t s);
+
+hipError_t launch_lookup(const PassParams& p, const void* z, int npairs, const double* pts,
+                         int npts, double2* out, hipStream_t s);
+hipError_t launch_lookup_backward(const PassParams& p, const double2* dout, int npairs,
+                                  const double* pts, int npts, double2* dz, hipStream_t s);
+
+// Adjoint.
+hipError_t launch_adj_col_pass(const PassParams& p, const double2* dz, int npairs, double2* inter,
+                               const void* twy, hipStream_t s);
+hipError_t launch_adj_row_pass(const PassParams& p, const double2* inter, int npairs, double2* gi,
+                               const void* twx, hipStream_t s);
+hipError_t launch_adj_integrand(const PassParams& p, const double2* gi, const double2* g,
+                                const double2* spec, const int* pm, const int* pn, int npairs,
+                                int nmbf, double2* gg, double2* gspec, int accumulate, hipStream_t s);
+hipError_t launch_adj_green(const GreenParams& p, const double2* gg, double* partial, int nblocks,
+                            hipStream_t s);
+hipError_t launch_reduce_sum(const double* partial, int n, int count, double* out, hipStream_t s);
+hipError_t launch_adj_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
+                              const double2* utab, const double2* gspec, int nmbf, double2* rowacc,
+                              double2* gq, hipStream_t s);
+
+// Sizes of the column tile and of the adjoint scratch (host helpers).
+int col_tile(int ny, int precision);
+size_t adj_spectra_scratch(const Axis& y, const GeomDevice& geo, int nmbf);
+
+}  // namespace cfft

@@ -1,0 +1,694 @@
+// The C-FFT passes (Sec. III-B.3, eqs. fftexp and fftarry; Appendix change
+// of variables), their adjoint, and the table lookup.
+//
+// With s(n) = (-1)^n, K = dkx dky / 4 pi^2, sigma = exp(-i pi (nx+ny)/2) and
+// the ray weight W = (1 + i gamma)^2, the table is
+//   Z(j1,j2) = K sigma W s(j1+j2) sum_b Dy(j2)^b/b! DFT_n2[ s(n2) (gamma ky)^b S_{P-b} ](j2)
+//   S_c(j1,n2) = sum_{a<=c} Dx(j1)^a/a! DFT_n1[ s(n1) (gamma kx)^a H(n1,n2) ](j1)
+//   H = M_m . G . M#_n
+// which is the total-degree-P Taylor expansion of E_I with every
+// displacement factor moved outside its transform.
+//
+// Row pass: one block handles one (row n2, pair) [or several short rows]; it
+// assembles H from G and the spectra (FP64), then for a = 0..P multiplies by
+// gamma kx, runs an in-register/LDS Stockham FFT along n1, folds the result
+// into the running partial sum S (FP64 accumulators) and writes S_a.
+// Column pass: one block handles a tile of C adjacent columns of one pair;
+// it stages each S_{P-b} tile through LDS (coalesced rows of C entries),
+// FFTs every column along n2, accumulates Dy^b/b! times the result, applies
+// the Appendix scale and writes the table through an LDS transpose.
+// The FFT precision is FP64 (CFFT_FP64) or FP32 (CFFT_MIXED); every
+// recombination weight and accumulator is FP64.
+#include "cfft_device.h"
+#include "cfft_internal.h"
+
+namespace cfft {
+
+template <int N> struct RowCfg {
+  static constexpr int R = 8;
+  static constexpr int T = N / R;
+  static constexpr int ROWS = T >= 64 ? 1 : 64 / T;
+  static constexpr int THREADS = ROWS * T;
+};
+
+struct RowArgs {
+  const double2* g;
+  const double2* spec;
+  void* inter;
+  const void* tw;
+  int nx, ny, order, npairs;
+  double kx0, dkx, x0, ddx, gamma;
+  int pm[kMaxPairsPerLaunch];
+  int pn[kMaxPairsPerLaunch];
+};
+
+template <typename V, int N>
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a) {
+  using Cfg = RowCfg<N>;
+  constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
+  using Rl = typename real_of<V>::type;
+  __shared__ V lds[ROWS * N];
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int pair = lid % a.npairs;
+  const int rb = lid / a.npairs;
+  const int grp = threadIdx.x / T;
+  const int t = threadIdx.x % T;
+  const int n2 = rb * ROWS + grp;
+  const bool valid = n2 < a.ny;
+  const size_t plane = (size_t)a.nx * a.ny;
+  const int m = a.pm[pair], n = a.pn[pair];
+  const V* tw = (const V*)a.tw;
+  V* inter = (V*)a.inter;
+
+  V f[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int n1 = t + T * r;
+    double2 h = make_double2(0.0, 0.0);
+    if (valid) {
+      const size_t idx = (size_t)n2 * N + n1;
+      const double2 gxx = a.g[idx], gxy = a.g[plane + idx], gyy = a.g[2 * plane + idx];
+      const double2 mx = a.spec[((size_t)m * 4 + 0) * plane + idx];
+      const double2 my = a.spec[((size_t)m * 4 + 1) * plane + idx];
+      const double2 mxh = a.spec[((size_t)n * 4 + 2) * plane + idx];
+      const double2 myh = a.spec[((size_t)n * 4 + 3) * plane + idx];
+      h = cadd(cmul(mx, cadd(cmul(gxx, mxh), cmul(gxy, myh))), cmul(my, cadd(cmul(gxy, mxh), cmul(gyy, myh))));
+      if (n1 & 1) h = make_double2(-h.x, -h.y);
+    }
+    f[r] = from_d<V>(h);
+  }
+  double2 S[R];
+  double cf[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    S[r] = make_double2(0.0, 0.0);
+    cf[r] = 1.0;
+  }
+  V* my_lds = lds + grp * N;
+  for (int ao = 0; ao <= a.order; ++ao) {
+    if (ao > 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int n1 = t + T * r;
+        f[r] = cscale(f[r], (Rl)(a.gamma * (a.kx0 + n1 * a.dkx)));
+        cf[r] *= (a.x0 + n1 * a.ddx) / ao;
+      }
+    }
+    V x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = f[r];
+    fft_forward<V, N, R>(x, my_lds, tw, t);
+    V* dst = inter + (((size_t)pair * (a.order + 1) + ao) * a.ny + (valid ? n2 : 0)) * N;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double2 xv = to_d(x[r]);
+      S[r] = make_double2(S[r].x + cf[r] * xv.x, S[r].y + cf[r] * xv.y);
+      if (valid) dst[t + T * r] = from_d<V>(S[r]);
+    }
+  }
+}
+
+struct ColArgs {
+  const void* inter;
+  void* z;
+  const void* tw;
+  int nx, ny, order, npairs;
+  double ky0, dky, y0, ddy, gamma;
+  double2 scale;   // K sigma W
+};
+
+template <int N, int C> struct ColCfg {
+  static constexpr int R = 8;
+  static constexpr int T = N / R;
+  static constexpr int THREADS = C * T;
+  static constexpr int LDP = N + 2;
+};
+
+template <typename V, int N, int C>
+__global__ void __launch_bounds__(C * (N / 8)) col_pass_kernel(ColArgs a) {
+  using Cfg = ColCfg<N, C>;
+  constexpr int T = Cfg::T, R = Cfg::R, LDP = Cfg::LDP;
+  using Rl = typename real_of<V>::type;
+  __shared__ V lds[C * LDP];
+  const int ntile = a.nx / C;
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = lid % ntile;
+  const int pair = lid / ntile;
+  const int c = threadIdx.x / T;
+  const int t = threadIdx.x % T;
+  const int j1 = tile * C + c;
+  const V* tw = (const V*)a.tw;
+  const V* inter = (const V*)a.inter;
+
+  double2 Z[R];
+  double cf[R];
+  Rl pw[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    Z[r] = make_double2(0.0, 0.0);
+    cf[r] = 1.0;
+    const int n2 = t + T * r;
+    pw[r] = (n2 & 1) ? (Rl)-1 : (Rl)1;
+  }
+  V* my_lds = lds + c * LDP;
+  for (int b = 0; b <= a.order; ++b) {
+    const V* src = inter + (((size_t)pair * (a.order + 1) + (a.order - b)) * N) * a.nx + (size_t)tile * C;
+    for (int i = threadIdx.x; i < C * N; i += Cfg::THREADS) {
+      const int row = i / C, col = i % C;
+      lds[col * LDP + row] = src[(size_t)row * a.nx + col];
+    }
+    __syncthreads();
+    V x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int n2 = t + T * r;
+      if (b > 0) pw[r] *= (Rl)(a.gamma * (a.ky0 + n2 * a.dky));
+      x[r] = cscale(my_lds[n2], pw[r]);
+    }
+    __syncthreads();
+    fft_forward<V, N, R>(x, my_lds, tw, t);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j2 = t + T * r;
+      if (b > 0) cf[r] *= (a.y0 + j2 * a.ddy) / b;
+      const double2 xv = to_d(x[r]);
+      Z[r] = make_double2(Z[r].x + cf[r] * xv.x, Z[r].y + cf[r] * xv.y);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j2 = t + T * r;
+    double2 v = cmul(Z[r], a.scale);
+    if ((j1 + j2) & 1) v = make_double2(-v.x, -v.y);
+    my_lds[j2] = from_d<V>(v);
+  }
+  __syncthreads();
+  V* dst = (V*)a.z + (size_t)pair * N * a.nx + (size_t)tile * C;
+  for (int i = threadIdx.x; i < C * N; i += Cfg::THREADS) {
+    const int row = i / C, col = i % C;
+    dst[(size_t)row * a.nx + col] = lds[col * LDP + row];
+  }
+}
+
+// Column tile width: as close to 128 B of contiguous row data as a 64 KiB
+// LDS tile and 1024 threads allow.
+__host__ __device__ constexpr int col_tile_c(int ny, int bytes) {
+  int c = 128 / bytes;
+  while (c > 1 && (c * ny * bytes > 65536 || c * (ny / 8) > 1024)) c /= 2;
+  return c;
+}
+
+int col_tile(int ny, int precision) { return col_tile_c(ny, precision == 0 ? 16 : 8); }
+
+// ------------------------------------------------ dispatch over sizes
+template <typename V, int N>
+static hipError_t row_launch(const RowArgs& args, hipStream_t s) {
+  using Cfg = RowCfg<N>;
+  const int nblk = ((args.ny + Cfg::ROWS - 1) / Cfg::ROWS) * args.npairs;
+  hipLaunchKernelGGL((row_pass_kernel<V, N>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
+  return hipGetLastError();
+}
+
+template <typename V, int N>
+static hipError_t col_launch(const ColArgs& args, hipStream_t s) {
+  constexpr int C = col_tile_c(N, sizeof(V));
+  using Cfg = ColCfg<N, C>;
+  if (args.nx % C != 0) return hipErrorInvalidValue;
+  const int nblk = (args.nx / C) * args.npairs;
+  hipLaunchKernelGGL((col_pass_kernel<V, N, C>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
+  return hipGetLastError();
+}
+
+#define CFFT_SIZE_SWITCH(n, F, ...)      \
+  switch (n) {                           \
+    case 16: return F<16>(__VA_ARGS__);     \
+    case 32: return F<32>(__VA_ARGS__);     \
+    case 64: return F<64>(__VA_ARGS__);     \
+    case 128: return F<128>(__VA_ARGS__);   \
+    case 256: return F<256>(__VA_ARGS__);   \
+    case 512: return F<512>(__VA_ARGS__);   \
+    case 1024: return F<1024>(__VA_ARGS__); \
+    case 2048: return F<2048>(__VA_ARGS__); \
+    case 4096: return F<4096>(__VA_ARGS__); \
+    default: return hipErrorInvalidValue;   \
+  }
+
+template <int N> static hipError_t row_fp64(const RowArgs& a, hipStream_t s) { return row_launch<double2, N>(a, s); }
+template <int N> static hipError_t row_fp32(const RowArgs& a, hipStream_t s) { return row_launch<float2, N>(a, s); }
+template <int N> static hipError_t col_fp64(const ColArgs& a, hipStream_t s) { return col_launch<double2, N>(a, s); }
+template <int N> static hipError_t col_fp32(const ColArgs& a, hipStream_t s) { return col_launch<float2, N>(a, s); }
+
+hipError_t launch_row_pass(const PassParams& p, const double2* g, const double2* spec, const int* pm,
+                           const int* pn, int npairs, void* inter, const void* twx, hipStream_t s) {
+  if (npairs < 1 || npairs > kMaxPairsPerLaunch) return hipErrorInvalidValue;
+  RowArgs a;
+  a.g = g;
+  a.spec = spec;
+  a.inter = inter;
+  a.tw = twx;
+  a.nx = p.x.n;
+  a.ny = p.y.n;
+  a.order = p.order;
+  a.npairs = npairs;
+  a.kx0 = p.x.k_first;
+  a.dkx = p.x.dk;
+  a.x0 = p.x.d_first;
+  a.ddx = p.x.dd;
+  a.gamma = p.gamma;
+  for (int i = 0; i < kMaxPairsPerLaunch; ++i) {
+    a.pm[i] = i < npairs ? pm[i] : 0;
+    a.pn[i] = i < npairs ? pn[i] : 0;
+  }
+  if (p.precision == 0) {
+    CFFT_SIZE_SWITCH(p.x.n, row_fp64, a, s)
+  }
+  CFFT_SIZE_SWITCH(p.x.n, row_fp32, a, s)
+}
+
+static double2 table_scale(const PassParams& p) {
+  const double K = p.x.dk * p.y.dk / (4.0 * M_PI * M_PI);
+  const int half = (p.x.n + p.y.n) / 2;
+  const double sigma = (half & 1) ? -1.0 : 1.0;
+  // W = (1 + i gamma)^2
+  const double wr = 1.0 - p.gamma * p.gamma, wi = 2.0 * p.gamma;
+  return make_double2(K * sigma * wr, K * sigma * wi);
+}
+
+hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, void* z, const void* twy,
+                           hipStream_t s) {
+  ColArgs a;
+  a.inter = inter;
+  a.z = z;
+  a.tw = twy;
+  a.nx = p.x.n;
+  a.ny = p.y.n;
+  a.order = p.order;
+  a.npairs = npairs;
+  a.ky0 = p.y.k_first;
+  a.dky = p.y.dk;
+  a.y0 = p.y.d_first;
+  a.ddy = p.y.dd;
+  a.gamma = p.gamma;
+  a.scale = table_scale(p);
+  if (p.precision == 0) {
+    CFFT_SIZE_SWITCH(p.y.n, col_fp64, a, s)
+  }
+  CFFT_SIZE_SWITCH(p.y.n, col_fp32, a, s)
+}
+
+// ------------------------------------------------ adjoint passes (FP64)
+// With h = conj(K sigma W) s(j1+j2) gZ, the adjoint of the table map is
+//   U_b(j1,n2) = IDFT_j2[ Dy^b/b! h ](n2),  V_c = sum_{b<=c} (gamma ky)^b U_b
+//   gH(n1,n2)  = s(n1+n2) sum_a (gamma kx)^a IDFT_j1[ Dx^a/a! V_{P-a} ](n1)
+// (unnormalised inverse DFTs; all weights are real).
+struct AdjColArgs {
+  const double2* dz;
+  double2* inter;
+  const double2* tw;
+  int nx, ny, order, npairs;
+  double ky0, dky, y0, ddy, gamma;
+  double2 cscale;  // conj(K sigma W)
+};
+
+template <int N, int C>
+__global__ void __launch_bounds__(C * (N / 8)) adj_col_kernel(AdjColArgs a) {
+  using Cfg = ColCfg<N, C>;
+  constexpr int T = Cfg::T, R = Cfg::R, LDP = Cfg::LDP;
+  __shared__ double2 lds[C * LDP];
+  const int ntile = a.nx / C;
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = lid % ntile;
+  const int pair = lid / ntile;
+  const int c = threadIdx.x / T;
+  const int t = threadIdx.x % T;
+  const int j1 = tile * C + c;
+  const double2* src = a.dz + (size_t)pair * N * a.nx + (size_t)tile * C;
+  for (int i = threadIdx.x; i < C * N; i += Cfg::THREADS) {
+    const int row = i / C, col = i % C;
+    lds[col * LDP + row] = src[(size_t)row * a.nx + col];
+  }
+  __syncthreads();
+  double2* my_lds = lds + c * LDP;
+  double2 h0[R], acc[R];
+  double cf[R], pw[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j2 = t + T * r;
+    double2 v = cmul(my_lds[j2], a.cscale);
+    if ((j1 + j2) & 1) v = make_double2(-v.x, -v.y);
+    h0[r] = v;
+    acc[r] = make_double2(0.0, 0.0);
+    cf[r] = 1.0;
+    pw[r] = 1.0;
+  }
+  __syncthreads();
+  for (int b = 0; b <= a.order; ++b) {
+    double2 x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j2 = t + T * r;
+      if (b > 0) cf[r] *= (a.y0 + j2 * a.ddy) / b;
+      x[r] = cscale(h0[r], cf[r]);
+    }
+    fft_inverse<double2, N, R>(x, my_lds, a.tw, t);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int n2 = t + T * r;
+      if (b > 0) pw[r] *= a.gamma * (a.ky0 + n2 * a.dky);
+      acc[r] = cadd(acc[r], cscale(x[r], pw[r]));
+      my_lds[n2] = acc[r];
+    }
+    __syncthreads();
+    double2* dst = a.inter + (((size_t)pair * (a.order + 1) + b) * N) * a.nx + (size_t)tile * C;
+    for (int i = threadIdx.x; i < C * N; i += Cfg::THREADS) {
+      const int row = i / C, col = i % C;
+      dst[(size_t)row * a.nx + col] = lds[col * LDP + row];
+    }
+    __syncthreads();
+  }
+}
+
+struct AdjRowArgs {
+  const double2* inter;
+  double2* gi;
+  const double2* tw;
+  int nx, ny, order, npairs;
+  double kx0, dkx, x0, ddx, gamma;
+};
+
+template <int N>
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs a) {
+  using Cfg = RowCfg<N>;
+  constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
+  __shared__ double2 lds[ROWS * N];
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int pair = lid % a.npairs;
+  const int rb = lid / a.npairs;
+  const int grp = threadIdx.x / T;
+  const int t = threadIdx.x % T;
+  const int n2 = rb * ROWS + grp;
+  const bool valid = n2 < a.ny;
+  double2 acc[R];
+  double cf[R], pw[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    acc[r] = make_double2(0.0, 0.0);
+    cf[r] = 1.0;
+    pw[r] = 1.0;
+  }
+  double2* my_lds = lds + grp * N;
+  for (int ao = 0; ao <= a.order; ++ao) {
+    const double2* src =
+        a.inter + (((size_t)pair * (a.order + 1) + (a.order - ao)) * a.ny + (valid ? n2 : 0)) * N;
+    double2 x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j1 = t + T * r;
+      if (ao > 0) cf[r] *= (a.x0 + j1 * a.ddx) / ao;
+      x[r] = valid ? cscale(src[j1], cf[r]) : make_double2(0.0, 0.0);
+    }
+    fft_inverse<double2, N, R>(x, my_lds, a.tw, t);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int n1 = t + T * r;
+      if (ao > 0) pw[r] *= a.gamma * (a.kx0 + n1 * a.dkx);
+      acc[r] = cadd(acc[r], cscale(x[r], pw[r]));
+    }
+  }
+  if (!valid) return;
+  double2* dst = a.gi + ((size_t)pair * a.ny + n2) * N;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int n1 = t + T * r;
+    double2 v = acc[r];
+    if ((n1 + n2) & 1) v = make_double2(-v.x, -v.y);
+    dst[n1] = v;
+  }
+}
+
+template <int N>
+static hipError_t adj_col_launch(const AdjColArgs& args, hipStream_t s) {
+  constexpr int C = col_tile_c(N, 16);
+  using Cfg = ColCfg<N, C>;
+  if (args.nx % C != 0) return hipErrorInvalidValue;
+  const int nblk = (args.nx / C) * args.npairs;
+  hipLaunchKernelGGL((adj_col_kernel<N, C>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t adj_row_launch(const AdjRowArgs& args, hipStream_t s) {
+  using Cfg = RowCfg<N>;
+  const int nblk = ((args.ny + Cfg::ROWS - 1) / Cfg::ROWS) * args.npairs;
+  hipLaunchKernelGGL((adj_row_kernel<N>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_col_pass(const PassParams& p, const double2* dz, int npairs, double2* inter,
+                               const void* twy, hipStream_t s) {
+  AdjColArgs a;
+  a.dz = dz;
+  a.inter = inter;
+  a.tw = (const double2*)twy;
+  a.nx = p.x.n;
+  a.ny = p.y.n;
+  a.order = p.order;
+  a.npairs = npairs;
+  a.ky0 = p.y.k_first;
+  a.dky = p.y.dk;
+  a.y0 = p.y.d_first;
+  a.ddy = p.y.dd;
+  a.gamma = p.gamma;
+  const double2 sc = table_scale(p);
+  a.cscale = make_double2(sc.x, -sc.y);
+  CFFT_SIZE_SWITCH(p.y.n, adj_col_launch, a, s)
+}
+
+hipError_t launch_adj_row_pass(const PassParams& p, const double2* inter, int npairs, double2* gi,
+                               const void* twx, hipStream_t s) {
+  AdjRowArgs a;
+  a.inter = inter;
+  a.gi = gi;
+  a.tw = (const double2*)twx;
+  a.nx = p.x.n;
+  a.ny = p.y.n;
+  a.order = p.order;
+  a.npairs = npairs;
+  a.kx0 = p.x.k_first;
+  a.dkx = p.x.dk;
+  a.x0 = p.x.d_first;
+  a.ddx = p.x.dd;
+  a.gamma = p.gamma;
+  CFFT_SIZE_SWITCH(p.x.n, adj_row_launch, a, s)
+}
+
+// ------------------------------------------------ integrand adjoint
+// For every sample, with gH_p the gradient w.r.t. H of pair p = (m, n):
+//   gG_xx += gH conj(Mx_m Mx#_n), gG_xy += gH conj(Mx_m My#_n + My_m Mx#_n),
+//   gG_yy += gH conj(My_m My#_n),
+//   gMx_m += gH conj(Gxx Mx#_n + Gxy My#_n), gMy_m += gH conj(Gxy Mx#_n + Gyy My#_n),
+//   gMx#_n += gH conj(Mx_m Gxx + My_m Gxy),  gMy#_n += gH conj(Mx_m Gxy + My_m Gyy).
+struct AdjIntArgs {
+  const double2* gi;
+  const double2* g;
+  const double2* spec;
+  double2* gg;
+  double2* gspec;
+  int n, npairs, nmbf, accumulate;
+  int pm[kMaxPairsPerLaunch];
+  int pn[kMaxPairsPerLaunch];
+};
+
+__global__ void __launch_bounds__(256) adj_integrand_kernel(AdjIntArgs a) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.n) return;
+  const size_t plane = (size_t)a.n;
+  const double2 gxx = a.g[idx], gxy = a.g[plane + idx], gyy = a.g[2 * plane + idx];
+  double2 ggxx = make_double2(0.0, 0.0), ggxy = ggxx, ggyy = ggxx;
+  if (a.accumulate) {
+    ggxx = a.gg[idx];
+    ggxy = a.gg[plane + idx];
+    ggyy = a.gg[2 * plane + idx];
+  }
+  for (int mm = 0; mm < a.nmbf; ++mm) {
+    // testing-side gradients of MBF mm and basis-side gradients of MBF mm
+    double2 gmx = make_double2(0.0, 0.0), gmy = gmx, gmxh = gmx, gmyh = gmx;
+    bool touched = false;
+    const double2 mx = a.spec[((size_t)mm * 4 + 0) * plane + idx];
+    const double2 my = a.spec[((size_t)mm * 4 + 1) * plane + idx];
+    const double2 mxh_self = a.spec[((size_t)mm * 4 + 2) * plane + idx];
+    const double2 myh_self = a.spec[((size_t)mm * 4 + 3) * plane + idx];
+    for (int p = 0; p < a.npairs; ++p) {
+      const int m = a.pm[p], n = a.pn[p];
+      if (m != mm && n != mm) continue;
+      touched = true;
+      const double2 gh = a.gi[(size_t)p * plane + idx];
+      if (m == mm) {
+        const double2 nxh = a.spec[((size_t)n * 4 + 2) * plane + idx];
+        const double2 nyh = a.spec[((size_t)n * 4 + 3) * plane + idx];
+        gmx = cadd(gmx, cmulc(gh, cadd(cmul(gxx, nxh), cmul(gxy, nyh))));
+        gmy = cadd(gmy, cmulc(gh, cadd(cmul(gxy, nxh), cmul(gyy, nyh))));
+        // Green's function gradient once per pair (on its testing MBF)
+        ggxx = cadd(ggxx, cmulc(gh, cmul(mx, nxh)));
+        ggxy = cadd(ggxy, cmulc(gh, cadd(cmul(mx, nyh), cmul(my, nxh))));
+        ggyy = cadd(ggyy, cmulc(gh, cmul(my, nyh)));
+      }
+      if (n == mm) {
+        const double2 tx = a.spec[((size_t)m * 4 + 0) * plane + idx];
+        const double2 ty = a.spec[((size_t)m * 4 + 1) * plane + idx];
+        gmxh = cadd(gmxh, cmulc(gh, cadd(cmul(tx, gxx), cmul(ty, gxy))));
+        gmyh = cadd(gmyh, cmulc(gh, cadd(cmul(tx, gxy), cmul(ty, gyy))));
+      }
+    }
+    (void)mxh_self;
+    (void)myh_self;
+    double2* gs = a.gspec + (size_t)mm * 4 * plane + idx;
+    if (a.accumulate) {
+      if (touched) {
+        gs[0] = cadd(gs[0], gmx);
+        gs[plane] = cadd(gs[plane], gmy);
+        gs[2 * plane] = cadd(gs[2 * plane], gmxh);
+        gs[3 * plane] = cadd(gs[3 * plane], gmyh);
+      }
+    } else {
+      gs[0] = gmx;
+      gs[plane] = gmy;
+      gs[2 * plane] = gmxh;
+      gs[3 * plane] = gmyh;
+    }
+  }
+  a.gg[idx] = ggxx;
+  a.gg[plane + idx] = ggxy;
+  a.gg[2 * plane + idx] = ggyy;
+}
+
+hipError_t launch_adj_integrand(const PassParams& p, const double2* gi, const double2* g, const double2* spec,
+                                const int* pm, const int* pn, int npairs, int nmbf, double2* gg, double2* gspec,
+                                int accumulate, hipStream_t s) {
+  if (npairs < 1 || npairs > kMaxPairsPerLaunch) return hipErrorInvalidValue;
+  AdjIntArgs a;
+  a.gi = gi;
+  a.g = g;
+  a.spec = spec;
+  a.gg = gg;
+  a.gspec = gspec;
+  a.n = p.x.n * p.y.n;
+  a.npairs = npairs;
+  a.nmbf = nmbf;
+  a.accumulate = accumulate;
+  for (int i = 0; i < kMaxPairsPerLaunch; ++i) {
+    a.pm[i] = i < npairs ? pm[i] : 0;
+    a.pn[i] = i < npairs ? pn[i] : 0;
+  }
+  hipLaunchKernelGGL(adj_integrand_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ lookup
+struct LookupArgs {
+  const void* z;
+  const double* pts;
+  double2* out;
+  int nx, ny, npairs, npts, precision;
+  double x0, ddx, y0, ddy;
+};
+
+__device__ __forceinline__ bool cell_of(const LookupArgs& a, int q, int& j1, int& j2, double& tx, double& ty) {
+  const double ux = (a.pts[2 * q] - a.x0) / a.ddx;
+  const double uy = (a.pts[2 * q + 1] - a.y0) / a.ddy;
+  // rejects NaN, negative and beyond-the-last-cell points before any cast
+  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux < (double)(a.nx - 1)) || !(uy < (double)(a.ny - 1))) return false;
+  j1 = (int)floor(ux);
+  j2 = (int)floor(uy);
+  if (j1 > a.nx - 2 || j2 > a.ny - 2) return false;
+  tx = ux - j1;
+  ty = uy - j2;
+  return true;
+}
+
+__global__ void lookup_kernel(LookupArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.npairs * a.npts) return;
+  const int p = e / a.npts, q = e % a.npts;
+  int j1, j2;
+  double tx, ty;
+  if (!cell_of(a, q, j1, j2, tx, ty)) {
+    a.out[e] = make_double2(__builtin_nan(""), __builtin_nan(""));
+    return;
+  }
+  const size_t base = (size_t)p * a.nx * a.ny;
+  const size_t i00 = base + (size_t)j2 * a.nx + j1;
+  double2 z00, z01, z10, z11;
+  if (a.precision == 0) {
+    const double2* z = (const double2*)a.z;
+    z00 = z[i00];
+    z01 = z[i00 + 1];
+    z10 = z[i00 + a.nx];
+    z11 = z[i00 + a.nx + 1];
+  } else {
+    const float2* z = (const float2*)a.z;
+    z00 = to_d(z[i00]);
+    z01 = to_d(z[i00 + 1]);
+    z10 = to_d(z[i00 + a.nx]);
+    z11 = to_d(z[i00 + a.nx + 1]);
+  }
+  const double w00 = (1 - tx) * (1 - ty), w01 = tx * (1 - ty), w10 = (1 - tx) * ty, w11 = tx * ty;
+  a.out[e] = make_double2(w00 * z00.x + w01 * z01.x + w10 * z10.x + w11 * z11.x,
+                          w00 * z00.y + w01 * z01.y + w10 * z10.y + w11 * z11.y);
+}
+
+__global__ void lookup_backward_kernel(LookupArgs a, const double2* __restrict__ dout, double2* dz) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.npairs * a.npts) return;
+  const int p = e / a.npts, q = e % a.npts;
+  int j1, j2;
+  double tx, ty;
+  if (!cell_of(a, q, j1, j2, tx, ty)) return;
+  const double2 g = dout[e];
+  const size_t i00 = (size_t)p * a.nx * a.ny + (size_t)j2 * a.nx + j1;
+  const double w[4] = {(1 - tx) * (1 - ty), tx * (1 - ty), (1 - tx) * ty, tx * ty};
+  const size_t id[4] = {i00, i00 + 1, i00 + a.nx, i00 + a.nx + 1};
+  double* d = (double*)dz;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    atomicAdd(d + 2 * id[k], w[k] * g.x);
+    atomicAdd(d + 2 * id[k] + 1, w[k] * g.y);
+  }
+}
+
+static LookupArgs lookup_args(const PassParams& p, const void* z, int npairs, const double* pts, int npts,
+                              double2* out) {
+  LookupArgs a;
+  a.z = z;
+  a.pts = pts;
+  a.out = out;
+  a.nx = p.x.n;
+  a.ny = p.y.n;
+  a.npairs = npairs;
+  a.npts = npts;
+  a.precision = p.precision;
+  a.x0 = p.x.d_first;
+  a.ddx = p.x.dd;
+  a.y0 = p.y.d_first;
+  a.ddy = p.y.dd;
+  return a;
+}
+
+hipError_t launch_lookup(const PassParams& p, const void* z, int npairs, const double* pts, int npts, double2* out,
+                         hipStream_t s) {
+  const LookupArgs a = lookup_args(p, z, npairs, pts, npts, out);
+  const long long n = (long long)npairs * npts;
+  hipLaunchKernelGGL(lookup_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lookup_backward(const PassParams& p, const double2* dout, int npairs, const double* pts,
+                                  int npts, double2* dz, hipStream_t s) {
+  const LookupArgs a = lookup_args(p, nullptr, npairs, pts, npts, nullptr);
+  const long long n = (long long)npairs * npts;
+  hipLaunchKernelGGL(lookup_backward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, dout, dz);
+  return hipGetLastError();
+}
+
+}  // namespace cfft

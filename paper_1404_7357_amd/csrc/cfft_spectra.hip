@@ -1,0 +1,277 @@
+// MBF spectra on the ray contour (eq. FTMBF), FP64, and their adjoint.
+//
+// Bases that share (kind, a, b) form a group whose members sit on the product
+// of the group's distinct x- and y-centres.  Their transforms factorise:
+//   F_j(k_c) = SX_g(kx) SY_g(ky) U_gp(kx) V_gr(ky),
+//   U_gp = exp(-i kcx X_p),  V_gr = exp(-i kcy Y_r),
+// so   M_m(k_c) = sum_g SX_g SY_g sum_p U_gp [ sum_r conj(q_m,j(g,p,r)) V_gr ].
+// The inner sum over r is done once per row (LDS), the outer one per sample.
+// The reflected spectrum M#_m(k_c) = sum_j q_mj F_j(-k_c) uses U#, V# =
+// exp(+i k_c .) and the even shape factors.
+#include "cfft_device.h"
+#include "cfft_internal.h"
+
+namespace cfft {
+
+__device__ __forceinline__ bool is_ydir(int kind) { return kind == 1 || kind == 3; }
+__device__ __forceinline__ bool is_cos(int kind) { return kind == 2 || kind == 3; }
+
+// Shape factor along the current: triangle a sinc^2(k a/2) or half-cosine
+// (a/2)[sinc((k a - pi)/2) + sinc((k a + pi)/2)]; across: b sinc(k b/2).
+__device__ __forceinline__ double2 along_factor(int kind, double a, double2 k) {
+  if (is_cos(kind)) {
+    const double2 ka = cscale(k, a);
+    const double2 s1 = csinc(cscale(make_double2(ka.x - M_PI, ka.y), 0.5));
+    const double2 s2 = csinc(cscale(make_double2(ka.x + M_PI, ka.y), 0.5));
+    return cscale(cadd(s1, s2), 0.5 * a);
+  }
+  const double2 s = csinc(cscale(k, 0.5 * a));
+  return cscale(cmul(s, s), a);
+}
+__device__ __forceinline__ double2 across_factor(double b, double2 k) {
+  return cscale(csinc(cscale(k, 0.5 * b)), b);
+}
+
+// exp(-i (1 + i gamma) k X) and exp(+i (1 + i gamma) k X).
+__device__ __forceinline__ void phase_pair(double k, double gamma, double X, double2& u, double2& uh) {
+  double s, c;
+  sincos(k * X, &s, &c);
+  const double e = exp(gamma * k * X);
+  const double ei = 1.0 / e;
+  u = make_double2(e * c, -e * s);
+  uh = make_double2(ei * c, ei * s);
+}
+
+// utab rows: [2 (uoff+p)] = U, [2 (uoff+p) + 1] = U#, [2 total_p + g] = SX_g.
+__global__ void spectra_tables_kernel(Axis x, double gamma, GeomDevice geo, double2* __restrict__ utab) {
+  const int n1 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.y;
+  if (n1 >= x.n) return;
+  const double kx = x.k_first + n1 * x.dk;
+  const double2 kcx = make_double2(kx, gamma * kx);
+  if (row < geo.total_p) {
+    // find the group owning this p row
+    int g = 0;
+    while (g + 1 < geo.ngroups && geo.groups[g + 1].uoff <= row) ++g;
+    const GeomGroup gr = geo.groups[g];
+    const double X = geo.xs[gr.xoff + (row - gr.uoff)];
+    double2 u, uh;
+    phase_pair(kx, gamma, X, u, uh);
+    utab[(size_t)(2 * row) * x.n + n1] = u;
+    utab[(size_t)(2 * row + 1) * x.n + n1] = uh;
+  } else {
+    const int g = row - geo.total_p;
+    const GeomGroup gr = geo.groups[g];
+    const double2 sx = is_ydir(gr.kind) ? across_factor(gr.b, kcx) : along_factor(gr.kind, gr.a, kcx);
+    utab[(size_t)(2 * geo.total_p + g) * x.n + n1] = sx;
+  }
+}
+
+hipError_t launch_spectra_tables(const Axis& x, double gamma, const GeomDevice& geo, double2* utab,
+                                 hipStream_t s) {
+  dim3 grid((x.n + 127) / 128, geo.total_p + geo.ngroups);
+  hipLaunchKernelGGL(spectra_tables_kernel, grid, dim3(128), 0, s, x, gamma, geo, utab);
+  return hipGetLastError();
+}
+
+constexpr int kSpecThreads = 256;
+constexpr int kMaxGroups = 32;  // host refuses basis sets needing more
+constexpr int kMChunk = 4;
+
+// One block per row n2.  Dynamic LDS: w and w# = [nmbf][total_p] complex each.
+__global__ void __launch_bounds__(kSpecThreads)
+spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __restrict__ utab,
+               const double2* __restrict__ q, int nmbf, double2* __restrict__ spec) {
+  extern __shared__ double2 sh[];
+  double2* w = sh;                              // [nmbf][total_p]
+  double2* wh = sh + nmbf * geo.total_p;        // [nmbf][total_p]
+  __shared__ GeomGroup grp[kMaxGroups];
+  const int n2 = blockIdx.x;
+  const double ky = y.k_first + n2 * y.dk;
+  const double2 kcy = make_double2(ky, gamma * ky);
+  if (threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
+  __syncthreads();
+  // w[m][uoff+p] = SY_g sum_r conj(q) V_gr ; wh = SY_g sum_r q V#_gr
+  const int nw = nmbf * geo.total_p;
+  for (int e = threadIdx.x; e < nw; e += blockDim.x) {
+    const int m = e / geo.total_p;
+    const int prow = e % geo.total_p;
+    int g = 0;
+    while (g + 1 < geo.ngroups && grp[g + 1].uoff <= prow) ++g;
+    const GeomGroup gr = grp[g];
+    const int p = prow - gr.uoff;
+    const double2 sy = is_ydir(gr.kind) ? along_factor(gr.kind, gr.a, kcy) : across_factor(gr.b, kcy);
+    double2 acc = make_double2(0.0, 0.0), acch = make_double2(0.0, 0.0);
+    for (int r = 0; r < gr.nr; ++r) {
+      const int j = geo.index[gr.ioff + p * gr.nr + r];
+      if (j < 0) continue;
+      double2 v, vh;
+      phase_pair(ky, gamma, geo.ys[gr.yoff + r], v, vh);
+      const double2 qq = q[(size_t)m * geo.nbasis + j];
+      acc = cadd(acc, cmulc(v, qq));      // conj(q) V
+      acch = cadd(acch, cmul(qq, vh));    // q V#
+    }
+    w[e] = cmul(acc, sy);
+    wh[e] = cmul(acch, sy);
+  }
+  __syncthreads();
+  const size_t plane = (size_t)x.n * y.n;
+  for (int n1 = threadIdx.x; n1 < x.n; n1 += blockDim.x) {
+    for (int m0 = 0; m0 < nmbf; m0 += kMChunk) {
+      double2 acc[kMChunk][4];
+#pragma unroll
+      for (int i = 0; i < kMChunk; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[i][c] = make_double2(0.0, 0.0);
+      for (int g = 0; g < geo.ngroups; ++g) {
+        const GeomGroup gr = grp[g];
+        const int comp = is_ydir(gr.kind) ? 1 : 0;
+        const double2 sx = utab[(size_t)(2 * geo.total_p + g) * x.n + n1];
+        double2 sg[kMChunk], sgh[kMChunk];
+#pragma unroll
+        for (int i = 0; i < kMChunk; ++i) sg[i] = sgh[i] = make_double2(0.0, 0.0);
+        for (int p = 0; p < gr.np; ++p) {
+          const int prow = gr.uoff + p;
+          const double2 u = utab[(size_t)(2 * prow) * x.n + n1];
+          const double2 uh = utab[(size_t)(2 * prow + 1) * x.n + n1];
+#pragma unroll
+          for (int i = 0; i < kMChunk; ++i) {
+            if (m0 + i < nmbf) {
+              sg[i] = cadd(sg[i], cmul(u, w[(m0 + i) * geo.total_p + prow]));
+              sgh[i] = cadd(sgh[i], cmul(uh, wh[(m0 + i) * geo.total_p + prow]));
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kMChunk; ++i) {
+          acc[i][comp] = cadd(acc[i][comp], cmul(sg[i], sx));
+          acc[i][2 + comp] = cadd(acc[i][2 + comp], cmul(sgh[i], sx));
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kMChunk; ++i) {
+        if (m0 + i < nmbf) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            spec[((size_t)(m0 + i) * 4 + c) * plane + (size_t)n2 * x.n + n1] = acc[i][c];
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
+                          const double2* utab, const double2* q, int nmbf, double2* spec, hipStream_t s) {
+  const size_t lds = sizeof(double2) * 2 * (size_t)nmbf * geo.total_p;
+  hipLaunchKernelGGL(spectra_kernel, dim3(y.n), dim3(kSpecThreads), lds, s, x, y, gamma, geo, utab, q, nmbf,
+                     spec);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ adjoint
+// Gradient of L w.r.t. q from the gradient w.r.t. the spectra (gspec, same
+// layout as spec, in the d/dRe + i d/dIm convention):
+//   gq_mj = sum_n conj(gM_m(n)) F_j(k_c(n)) + gM#_m(n) conj(F_j(-k_c(n))).
+// Per row n2 the sums over n1 are reduced per (m, g, p) in the block, then
+// multiplied by the row factors and written to rowacc[n2][m][j]; a second
+// kernel sums rowacc over rows in a fixed order.
+constexpr int kAdjThreads = 256;
+
+__global__ void __launch_bounds__(kAdjThreads)
+adj_spectra_rows_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __restrict__ utab,
+                        const double2* __restrict__ gspec, int nmbf, double2* __restrict__ rowacc) {
+  extern __shared__ double2 sh[];
+  // a1, a2: [nmbf][total_p]
+  double2* a1 = sh;
+  double2* a2 = sh + nmbf * geo.total_p;
+  __shared__ double2 red[2][kAdjThreads];
+  __shared__ GeomGroup grp[kMaxGroups];
+  const int n2 = blockIdx.x;
+  const double ky = y.k_first + n2 * y.dk;
+  const double2 kcy = make_double2(ky, gamma * ky);
+  if (threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
+  __syncthreads();
+  const size_t plane = (size_t)x.n * y.n;
+  for (int m = 0; m < nmbf; ++m) {
+    for (int g = 0; g < geo.ngroups; ++g) {
+      const GeomGroup gr = grp[g];
+      const int comp = is_ydir(gr.kind) ? 1 : 0;
+      for (int p = 0; p < gr.np; ++p) {
+        const int prow = gr.uoff + p;
+        double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+        for (int n1 = threadIdx.x; n1 < x.n; n1 += blockDim.x) {
+          const double2 sx = utab[(size_t)(2 * geo.total_p + g) * x.n + n1];
+          const double2 u = utab[(size_t)(2 * prow) * x.n + n1];
+          const double2 uh = utab[(size_t)(2 * prow + 1) * x.n + n1];
+          const double2 gm = gspec[((size_t)m * 4 + comp) * plane + (size_t)n2 * x.n + n1];
+          const double2 gmh = gspec[((size_t)m * 4 + 2 + comp) * plane + (size_t)n2 * x.n + n1];
+          s1 = cadd(s1, cmulc(cmul(sx, u), gm));          // conj(gM) SX U  (conj applied below)
+          s2 = cadd(s2, cmulc(gmh, cmul(sx, uh)));        // gM# conj(SX U#)
+        }
+        red[0][threadIdx.x] = s1;
+        red[1][threadIdx.x] = s2;
+        __syncthreads();
+        for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
+          if (threadIdx.x < w) {
+            red[0][threadIdx.x] = cadd(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+            red[1][threadIdx.x] = cadd(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+          }
+          __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+          a1[m * geo.total_p + prow] = red[0][0];
+          a2[m * geo.total_p + prow] = red[1][0];
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // rowacc[n2][m][j] = SY V_r a1[p] + conj(SY V#_r) a2[p]
+  const int nent = nmbf * geo.total_idx;
+  for (int e = threadIdx.x; e < nent; e += blockDim.x) {
+    const int m = e / geo.total_idx;
+    const int li = e % geo.total_idx;
+    int g = 0;
+    while (g + 1 < geo.ngroups && grp[g + 1].ioff <= li) ++g;
+    const GeomGroup gr = grp[g];
+    const int j = geo.index[li];
+    if (j < 0) continue;
+    const int p = (li - gr.ioff) / gr.nr;
+    const int r = (li - gr.ioff) % gr.nr;
+    const double2 sy = is_ydir(gr.kind) ? along_factor(gr.kind, gr.a, kcy) : across_factor(gr.b, kcy);
+    double2 v, vh;
+    phase_pair(ky, gamma, geo.ys[gr.yoff + r], v, vh);
+    const double2 t1 = cmul(cmul(sy, v), a1[m * geo.total_p + gr.uoff + p]);
+    const double2 t2 = cmulc(a2[m * geo.total_p + gr.uoff + p], cmul(sy, vh));
+    rowacc[((size_t)n2 * nmbf + m) * geo.nbasis + j] = cadd(t1, t2);
+  }
+}
+
+// gq[m][j] = sum_n2 rowacc[n2][m][j]  (fixed summation order)
+__global__ void adj_spectra_sum_kernel(const double2* __restrict__ rowacc, int nrows, int count,
+                                       double2* __restrict__ gq) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int r = 0; r < nrows; ++r) acc = cadd(acc, rowacc[(size_t)r * count + e]);
+  gq[e] = acc;
+}
+
+size_t adj_spectra_scratch(const Axis& y, const GeomDevice& geo, int nmbf) {
+  return sizeof(double2) * (size_t)y.n * nmbf * geo.nbasis;
+}
+
+hipError_t launch_adj_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
+                              const double2* utab, const double2* gspec, int nmbf, double2* rowacc,
+                              double2* gq, hipStream_t s) {
+  const size_t lds = sizeof(double2) * 2 * (size_t)nmbf * geo.total_p;
+  hipLaunchKernelGGL(adj_spectra_rows_kernel, dim3(y.n), dim3(kAdjThreads), lds, s, x, y, gamma, geo, utab,
+                     gspec, nmbf, rowacc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int count = nmbf * geo.nbasis;
+  hipLaunchKernelGGL(adj_spectra_sum_kernel, dim3((count + 255) / 256), dim3(256), 0, s, rowacc, y.n, count, gq);
+  return hipGetLastError();
+}
+
+}  // namespace cfft

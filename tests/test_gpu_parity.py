@@ -1,0 +1,238 @@
+"""GPU parity of every step of the hot path against the CPU FP64 oracle.
+
+Metric: the paper's max-normalised error, err = max|Z_gpu - Z_oracle| /
+max|Z_oracle| per table (Sec. IV, error definition).  Bars: FP64 path
+1e-10, mixed path (FP32 FFTs, FP64 Green's function, spectra and
+recombination) 1e-5; Green's function and spectra 1e-12 (pure FP64
+evaluation, rounding only).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cfft_oracle as co
+from workloads import (FP64, MIXED, Grid, Substrate, c1_single_cosine, c2_rooftop_512, gaussian_coefficients,
+                       rooftop_lattice)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+K0 = 2 * math.pi
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _tab(grid, basis, max_mbf, flags=0):
+    from paper_1404_7357_amd import Tabulator
+    return Tabulator(grid, basis, max_mbf=max_mbf, flags=flags)
+
+
+def _err(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+def _run(grid, sub, basis, q, pairs):
+    tab = _tab(grid, basis, q.shape[0])
+    g = tab.green(sub.eps_r, sub.tan_delta, sub.h)
+    spec = tab.spectra(torch.tensor(q, device="cuda"))
+    z = tab.tabulate(spec, g, [tuple(p) for p in pairs])
+    torch.cuda.synchronize()
+    out = (g.cpu().numpy(), spec.cpu().numpy(), z.cpu().numpy())
+    tab.close()
+    return out
+
+
+GREEN_CASES = [
+    ("c1 64x64 eps2.2", Grid(64, 64, 8 * K0, 8 * K0, K0), Substrate(2.2, 0.0, 0.05)),
+    ("c2-like 32x64 eps4.4 lossy", Grid(32, 64, 10.488 * K0, 7 * K0, K0), Substrate(4.4, 0.002, 0.06)),
+    ("c4-like 128x128 eps10.2", Grid(128, 128, 10.24 * K0, 10.24 * K0, K0), Substrate(10.2, 0.0, 0.12)),
+    ("free space eps1", Grid(16, 16, 6 * K0, 6 * K0, K0), Substrate(1.0, 0.0, 0.05)),
+]
+
+
+@pytest.mark.parametrize("name,grid,sub", GREEN_CASES, ids=[c[0] for c in GREEN_CASES])
+def test_green_matches_oracle(name, grid, sub):
+    _say(f"green {name}")
+    tab = _tab(grid, rooftop_lattice(1, 1), 1)
+    g = tab.green(sub.eps_r, sub.tan_delta, sub.h).cpu().numpy().reshape(3, -1)
+    tab.close()
+    kx, ky = co.grid_samples(grid.nx, grid.ny, grid.kx_max, grid.ky_max)
+    ref = np.stack(co.green_remainder(kx, ky, grid.gamma, grid.k0, sub.eps_r, sub.tan_delta, sub.h))
+    if sub.eps_r == 1.0:
+        assert np.abs(g).max() < 1e-13
+    else:
+        assert _err(g, ref) < 1e-12
+
+
+def test_spectra_match_oracle():
+    _say("spectra c2 basis 64x32")
+    rng = np.random.default_rng(7)
+    grid = Grid(64, 32, 10.488 * K0, 10.488 * K0, K0)
+    basis = rooftop_lattice(8, 16)
+    q = gaussian_coefficients(rng, 3, basis.shape[0])
+    tab = _tab(grid, basis, 3)
+    spec = tab.spectra(torch.tensor(q, device="cuda")).cpu().numpy().reshape(3, 4, -1)
+    tab.close()
+    kx, ky = co.grid_samples(grid.nx, grid.ny, grid.kx_max, grid.ky_max)
+    kcx, kcy, _ = co.ray_contour(kx, ky, grid.gamma)
+    mt, mh = co.mbf_spectra(basis, q, kcx, kcy)
+    ref = np.concatenate([mt, mh], axis=1)
+    assert _err(spec, ref) < 1e-12
+
+
+def test_spectra_cosine_and_duplicates():
+    """Half-cosine basis, y-directed kinds, and two bases on one slot (overflow group)."""
+    _say("spectra mixed kinds")
+    from workloads import COSINE_X, COSINE_Y, ROOFTOP_X, basis_array
+    basis = basis_array([(COSINE_X, 0.0, 0.0, 0.3, 0.02), (COSINE_Y, 0.05, -0.02, 0.2, 0.03),
+                         (ROOFTOP_X, 0.01, 0.0, 0.05, 0.02), (ROOFTOP_X, 0.01, 0.0, 0.05, 0.02)])
+    q = np.array([[1.0, 0.5 - 0.2j, 0.3j, -0.7], [0.2, 1.0, 1.0j, 0.1]], dtype=complex)
+    grid = Grid(32, 32, 8 * K0, 8 * K0, K0)
+    tab = _tab(grid, basis, 2)
+    spec = tab.spectra(torch.tensor(q, device="cuda")).cpu().numpy().reshape(2, 4, -1)
+    tab.close()
+    kx, ky = co.grid_samples(32, 32, grid.kx_max, grid.ky_max)
+    kcx, kcy, _ = co.ray_contour(kx, ky, grid.gamma)
+    mt, mh = co.mbf_spectra(basis, q, kcx, kcy)
+    assert _err(spec, np.concatenate([mt, mh], axis=1)) < 1e-12
+
+
+def _full_case(name, grid, sub, basis, q, pairs, tol):
+    _say(f"tabulate full {name}")
+    _, _, z = _run(grid, sub, basis, q, pairs)
+    ref = co.tabulate(grid, sub, basis, q, np.asarray(pairs))
+    for p in range(len(pairs)):
+        e = _err(z[p], ref[p])
+        assert e < tol, (name, p, e)
+
+
+def test_c1_full_grid_fp64():
+    wl = c1_single_cosine()
+    _full_case("c1 fp64", wl.grids[0], wl.substrates[0], wl.basis, wl.q, wl.pairs.tolist(), 1e-10)
+
+
+def test_c1_full_grid_mixed():
+    wl = c1_single_cosine(precision=MIXED)
+    _full_case("c1 mixed", wl.grids[0], wl.substrates[0], wl.basis, wl.q, wl.pairs.tolist(), 1e-5)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 5])
+def test_orders_nonsquare_fp64(order):
+    rng = np.random.default_rng(100 + order)
+    grid = Grid(64, 32, 9 * K0, 7 * K0, K0, order=order)
+    basis = rooftop_lattice(3, 4)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 0), (0, 1), (1, 0), (1, 1), (1, 1)]
+    _full_case(f"64x32 P={order}", grid, Substrate(4.4, 0.002, 0.06), basis, q, pairs, 1e-10)
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (16, 128), (128, 32), (256, 16)])
+def test_shapes_fp64_and_mixed(nx, ny):
+    rng = np.random.default_rng(nx * 7 + ny)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 1), (1, 0), (0, 0)]
+    for prec, tol in [(FP64, 1e-10), (MIXED, 1e-5)]:
+        grid = Grid(nx, ny, 8 * K0, 6 * K0, K0, precision=prec)
+        _full_case(f"{nx}x{ny} prec={prec}", grid, Substrate(2.2, 0.0, 0.05), basis, q, pairs, tol)
+
+
+def test_many_pairs_chunked(monkeypatch):
+    """More pairs than one launch holds, with a forced small chunk (ragged last chunk)."""
+    monkeypatch.setenv("CFFT_PAIR_CHUNK", "3")
+    rng = np.random.default_rng(5)
+    grid = Grid(32, 32, 8 * K0, 8 * K0, K0)
+    basis = rooftop_lattice(2, 2)
+    q = gaussian_coefficients(rng, 3, basis.shape[0])
+    pairs = [(m, n) for m in range(3) for n in range(3)] + [(2, 0), (0, 2)]
+    _full_case("32x32 11 pairs chunk 3", grid, Substrate(4.4, 0.002, 0.06), basis, q, pairs, 1e-10)
+
+
+def _sample_idx(nx, ny, count, seed):
+    rng = np.random.default_rng(seed)
+    idx = set(rng.choice(nx * ny, count, replace=False).tolist())
+    idx |= {(ny // 2) * nx + nx // 2, 0, nx - 1, nx * ny - 1, (ny - 1) * nx}
+    return np.array(sorted(idx))
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-10), (MIXED, 1e-5)])
+def test_c2_full_size_sampled(prec, tol):
+    """The benchmark workload (512^2, 16 pairs, B = 256) at sampled outputs."""
+    wl = c2_rooftop_512(precision=prec)
+    grid, sub = wl.grids[0], wl.substrates[0]
+    _say(f"c2 512x512 16 pairs prec={prec}")
+    _, _, z = _run(grid, sub, wl.basis, wl.q, wl.pairs.tolist())
+    idx = _sample_idx(grid.nx, grid.ny, 48, 11)
+    ref = co.tabulate(grid, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=8)
+    zs = z.reshape(len(wl.pairs), -1)[:, idx]
+    # normalise by the table maximum (at Delta = 0, included in the sample)
+    scale = np.abs(ref).max(axis=1)
+    err = (np.abs(zs - ref).max(axis=1) / scale).max()
+    assert err < tol, err
+
+
+def test_deterministic():
+    wl = c2_rooftop_512(n=128)
+    _say("determinism 128^2")
+    a = _run(wl.grids[0], wl.substrates[0], wl.basis, wl.q, wl.pairs.tolist())[2]
+    b = _run(wl.grids[0], wl.substrates[0], wl.basis, wl.q, wl.pairs.tolist())[2]
+    assert np.array_equal(a, b)
+
+
+def test_lookup_matches_oracle_bilinear():
+    _say("lookup")
+    from paper_1404_7357_amd import Tabulator
+    rng = np.random.default_rng(3)
+    for prec in (FP64, MIXED):
+        grid = Grid(64, 32, 8 * K0, 6 * K0, K0, precision=prec)
+        tab = Tabulator(grid, rooftop_lattice(1, 1), 1)
+        dt = torch.complex128 if prec == FP64 else torch.complex64
+        table = (rng.standard_normal((3, 32, 64)) + 1j * rng.standard_normal((3, 32, 64)))
+        zt = torch.tensor(table, dtype=dt, device="cuda")
+        dxa = co.displacement_axis(64, grid.kx_max)
+        dya = co.displacement_axis(32, grid.ky_max)
+        pts = np.stack([rng.uniform(dxa[0], dxa[-1] - 1e-9, 500), rng.uniform(dya[0], dya[-1] - 1e-9, 500)], 1)
+        pts = np.concatenate([pts, [[dxa[-1] + 1.0, 0.0], [0.0, dya[0] - 0.5]]])
+        out = tab.lookup(zt, torch.tensor(pts, device="cuda")).cpu().numpy()
+        tab.close()
+        ref = co.bilinear_lookup(grid, zt.cpu().numpy().astype(np.complex128), pts[:-2])
+        assert np.abs(out[:, :-2] - ref).max() < 1e-13
+        assert np.isnan(out[:, -2:]).all()
+
+
+def test_nonfinite_flag_reports_nan_input():
+    _say("non-finite flag")
+    from paper_1404_7357_amd import FLAG_CHECK_FINITE, CfftError
+    grid = Grid(32, 32, 8 * K0, 8 * K0, K0)
+    basis = rooftop_lattice(1, 2)
+    tab = _tab(grid, basis, 1, flags=FLAG_CHECK_FINITE)
+    g = tab.green(2.2, 0.0, 0.05)
+    spec = tab.spectra(torch.ones((1, basis.shape[0]), dtype=torch.complex128, device="cuda"))
+    z = tab.tabulate(spec, g, [(0, 0)])
+    assert torch.isfinite(torch.view_as_real(z)).all()
+    g[0, 3, 5] = complex(float("nan"), 0.0)
+    with pytest.raises(CfftError) as ei:
+        tab.tabulate(spec, g, [(0, 0)])
+    assert ei.value.status == 5
+    tab.close()
+
+
+def test_invalid_pairs_rejected_on_host():
+    _say("invalid pairs")
+    from paper_1404_7357_amd import CfftError
+    grid = Grid(32, 32, 8 * K0, 8 * K0, K0)
+    basis = rooftop_lattice(1, 2)
+    tab = _tab(grid, basis, 2)
+    g = tab.green(2.2, 0.0, 0.05)
+    spec = tab.spectra(torch.ones((2, basis.shape[0]), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(CfftError) as ei:
+        tab.tabulate(spec, g, [(0, 2)])
+    assert ei.value.status == 1
+    with pytest.raises(CfftError):
+        tab.green(float("nan"), 0.0, 0.05)
+    tab.close()
