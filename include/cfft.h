@@ -170,6 +170,18 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
                             const void* g, const void* spec, double* grad_sub, void* grad_q,
                             void* stream);
 
+/* Kernel timing (instrumentation).  While enabled, every kernel a plan
+ * launches is bracketed by HIP events on the caller's stream, per kernel
+ * class; cfft_profile_read waits for the recorded events and returns the
+ * summed duration (ms) and launch count of one class since the last read
+ * (the class's events are released).  Classes:
+ *   0 slab_green_eval  1 mbf_spectra tables+spectra  2 row pass  3 column pass
+ *   4 lookup  5 adjoint column pass  6 adjoint row pass  7 integrand adjoint
+ *   8 Green's function adjoint + reductions  9 spectra adjoint
+ * enable = 0 disables recording (pending events are kept until read). */
+cfft_status_t cfft_profile(cfft_plan_t plan, int32_t enable);
+cfft_status_t cfft_profile_read(cfft_plan_t plan, int32_t kernel_class, double* total_ms, int64_t* launches);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* cfft_last_error(void);
 

@@ -23,7 +23,11 @@ FP64, MIXED = 0, 1
 FLAG_CHECK_FINITE = 1
 
 ENTRY_POINTS = ("c_fft_plan", "c_fft_plan_destroy", "slab_green_eval", "mbf_spectra", "cfft_tabulate",
-                "cfft_lookup", "cfft_lookup_backward", "cfft_backward", "cfft_last_error", "cfft_version")
+                "cfft_lookup", "cfft_lookup_backward", "cfft_backward", "cfft_profile", "cfft_profile_read",
+                "cfft_last_error", "cfft_version")
+
+PROFILE_CLASSES = {"green": 0, "spectra": 1, "row_pass": 2, "col_pass": 3, "lookup": 4, "adj_col_pass": 5,
+                   "adj_row_pass": 6, "adj_integrand": 7, "adj_green": 8, "adj_spectra": 9}
 
 
 class GridDesc(ctypes.Structure):
@@ -68,6 +72,8 @@ def load(path: str = LIB_PATH):
     lib.cfft_lookup_backward.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_backward.argtypes = [vp, i32, vp, dbl, dbl, dbl, ctypes.POINTER(Basis), i32, vp, i32,
                                   ctypes.POINTER(ctypes.c_int32), i32, vp, vp, vp, vp, vp]
+    lib.cfft_profile.argtypes = [vp, i32]
+    lib.cfft_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in ENTRY_POINTS:
         fn = getattr(lib, name)
         fn.restype = ctypes.c_char_p if name in ("cfft_last_error", "cfft_version") else ctypes.c_int
@@ -174,6 +180,18 @@ def cfft_backward(plan: Plan, grid: int, dz, eps_r, tan_delta, h, basis, q, pair
     check(load().cfft_backward(plan.handle, grid, _ptr(dz), float(eps_r), float(tan_delta), float(h), b, len(b),
                                _ptr(q), int(q.shape[0]), pa, len(pa) // 2, _ptr(g), _ptr(spec), _ptr(grad_sub),
                                _ptr(grad_q), _stream(stream)))
+
+
+def profile(plan: Plan, enable: bool):
+    check(load().cfft_profile(plan.handle, 1 if enable else 0))
+
+
+def profile_read(plan: Plan, kernel: str):
+    """(total_ms, launches) of one kernel class since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    check(load().cfft_profile_read(plan.handle, PROFILE_CLASSES[kernel], ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def last_error() -> str:

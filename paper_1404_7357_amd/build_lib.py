@@ -1,6 +1,6 @@
 """Build the gfx950 shared library libcfft.so in-tree with hipcc.
 
-Usage: python -m paper_1404_7357_amd.build_lib   (or build() from Python)
+Usage: python paper_1404_7357_amd/build_lib.py   (or __graft_entry__.build())
 
 Every HIP translation unit is compiled for gfx950 only, with packed FP32
 instructions disabled, then linked into paper_1404_7357_amd/libcfft.so.

@@ -23,6 +23,8 @@
 
 using namespace cfft;
 
+constexpr int kProfClasses = 10;
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -169,6 +171,9 @@ struct cfft_plan_s {
   void* geo_mem = nullptr;
   int* flag_dev = nullptr;
   int* flag_host = nullptr;
+  // instrumentation: recorded (start, stop) event pairs per kernel class
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[kProfClasses];
 };
 
 namespace {
@@ -367,6 +372,28 @@ cfft_status_t check_finite(cfft_plan_s* plan, const void* data, size_t nreal, bo
   return CFFT_OK;
 }
 
+// Bracket a launch with events when profiling is on.
+struct ProfScope {
+  cfft_plan_s* plan;
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(cfft_plan_s* p, int c, hipStream_t st) : plan(p), cls(c), s(st) {
+    if (!plan->profiling) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      (void)hipGetLastError();
+      a = b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    plan->prof[cls].emplace_back(a, b);
+  }
+};
+
 void release_plan(cfft_plan_s* plan) {
   (void)hipSetDevice(plan->device);
   (void)hipDeviceSynchronize();
@@ -381,6 +408,11 @@ void release_plan(cfft_plan_s* plan) {
   if (plan->ws2) (void)hipFree(plan->ws2);
   if (plan->flag_dev) (void)hipFree(plan->flag_dev);
   if (plan->flag_host) (void)hipHostFree(plan->flag_host);
+  for (auto& v : plan->prof)
+    for (auto& pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
   free_geometry(plan);
   delete plan;
 }
@@ -390,6 +422,39 @@ void release_plan(cfft_plan_s* plan) {
 extern "C" {
 
 const char* cfft_last_error(void) { return g_last_error.c_str(); }
+
+cfft_status_t cfft_profile(cfft_plan_t plan, int32_t enable) {
+  g_last_error.clear();
+  if (!plan || !plan_live(plan)) return fail(CFFT_ERR_INVALID_ARG, "unknown or destroyed plan");
+  plan->profiling = enable != 0;
+  return CFFT_OK;
+}
+
+cfft_status_t cfft_profile_read(cfft_plan_t plan, int32_t kernel_class, double* total_ms, int64_t* launches) {
+  g_last_error.clear();
+  if (!plan || !plan_live(plan)) return fail(CFFT_ERR_INVALID_ARG, "unknown or destroyed plan");
+  if (kernel_class < 0 || kernel_class >= kProfClasses)
+    return fail(CFFT_ERR_INVALID_ARG, "kernel class %d outside [0, %d)", kernel_class, kProfClasses);
+  if (!total_ms || !launches) return fail(CFFT_ERR_INVALID_ARG, "total_ms or launches is NULL");
+  double acc = 0.0;
+  int64_t cnt = 0;
+  hipError_t err = hipSuccess;
+  for (auto& pr : plan->prof[kernel_class]) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess && err == hipSuccess) err = e;
+    acc += ms;
+    ++cnt;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  plan->prof[kernel_class].clear();
+  *total_ms = acc;
+  *launches = cnt;
+  if (err != hipSuccess) return hip_fail(err, "profile read");
+  return CFFT_OK;
+}
 
 const char* cfft_version(void) { return "cfft-mi355x 0.1 (gfx950)"; }
 
@@ -492,7 +557,11 @@ cfft_status_t slab_green_eval(cfft_plan_t plan, int32_t grid, double eps_r, doub
   GridState& gs = plan->grids[grid];
   GreenParams p{gs.x, gs.y, gs.d.gamma, gs.d.k0, eps_r, tan_delta, h};
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_green(p, (double2*)g, s);
+  hipError_t e;
+  {
+    ProfScope ps(plan, 0, s);
+    e = launch_green(p, (double2*)g, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "slab_green_eval launch");
   return check_finite(plan, g, (size_t)6 * gs.x.n * gs.y.n, false, s);
 }
@@ -511,8 +580,11 @@ cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* ba
   hipStream_t s = (hipStream_t)stream;
   st = ensure_geometry(plan, gs, basis, nbasis, s);
   if (st != CFFT_OK) return st;
-  hipError_t e = launch_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, (const double2*)q, nmbf,
-                                (double2*)spec, s);
+  hipError_t e;
+  {
+    ProfScope ps(plan, 1, s);
+    e = launch_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, (const double2*)q, nmbf, (double2*)spec, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "mbf_spectra launch");
   return check_finite(plan, spec, (size_t)8 * nmbf * gs.x.n * gs.y.n, false, s);
 }
@@ -549,10 +621,17 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   }
   for (int p0 = 0; p0 < npairs; p0 += (int)chunk) {
     const int np = (int)std::min<long long>(chunk, npairs - p0);
-    hipError_t e = launch_row_pass(pp, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np,
-                                   plan->ws, twx, s);
+    hipError_t e;
+    {
+      ProfScope ps(plan, 2, s);
+      e = launch_row_pass(pp, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np, plan->ws,
+                          twx, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "row pass launch");
-    e = launch_col_pass(pp, plan->ws, np, (char*)z + (size_t)p0 * n * cbytes, twy, s);
+    {
+      ProfScope ps(plan, 3, s);
+      e = launch_col_pass(pp, plan->ws, np, (char*)z + (size_t)p0 * n * cbytes, twy, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "column pass launch");
   }
   return check_finite(plan, z, 2 * n * (size_t)npairs, pp.precision != CFFT_FP64, s);
@@ -568,7 +647,11 @@ cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t
   if (npts < 1 || (long long)npts * npairs > (1LL << 31) - 1)
     return fail(CFFT_ERR_INVALID_ARG, "npts %d invalid", npts);
   GridState& gs = plan->grids[grid];
-  hipError_t e = launch_lookup(pass_params(gs), z, npairs, pts, npts, (double2*)out, (hipStream_t)stream);
+  hipError_t e;
+  {
+    ProfScope ps(plan, 4, (hipStream_t)stream);
+    e = launch_lookup(pass_params(gs), z, npairs, pts, npts, (double2*)out, (hipStream_t)stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "lookup launch");
   return CFFT_OK;
 }
@@ -643,18 +726,33 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   }
   for (int p0 = 0; p0 < npairs; p0 += (int)chunk) {
     const int np = (int)std::min<long long>(chunk, npairs - p0);
-    hipError_t e = launch_adj_col_pass(pp, (const double2*)dz + (size_t)p0 * n, np, inter, gs.tw64y, s);
-    if (e == hipSuccess) e = launch_adj_row_pass(pp, inter, np, gi, gs.tw64x, s);
-    if (e == hipSuccess)
+    hipError_t e;
+    {
+      ProfScope ps(plan, 5, s);
+      e = launch_adj_col_pass(pp, (const double2*)dz + (size_t)p0 * n, np, inter, gs.tw64y, s);
+    }
+    if (e == hipSuccess) {
+      ProfScope ps(plan, 6, s);
+      e = launch_adj_row_pass(pp, inter, np, gi, gs.tw64x, s);
+    }
+    if (e == hipSuccess) {
+      ProfScope ps(plan, 7, s);
       e = launch_adj_integrand(pp, gi, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np,
                                nmbf, gg, gspec, p0 > 0 ? 1 : 0, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
   }
   GreenParams gp{gs.x, gs.y, gs.d.gamma, gs.d.k0, eps_r, tan_delta, h};
-  hipError_t e = launch_adj_green(gp, gg, partial, green_blocks, s);
-  if (e == hipSuccess) e = launch_reduce_sum(partial, green_blocks, 2, grad_sub, s);
-  if (e == hipSuccess)
+  hipError_t e;
+  {
+    ProfScope ps(plan, 8, s);
+    e = launch_adj_green(gp, gg, partial, green_blocks, s);
+    if (e == hipSuccess) e = launch_reduce_sum(partial, green_blocks, 2, grad_sub, s);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps(plan, 9, s);
     e = launch_adj_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, gspec, nmbf, rowacc, (double2*)grad_q, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "adjoint reduction launch");
   return CFFT_OK;
 }

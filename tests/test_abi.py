@@ -13,10 +13,10 @@ HEADER = os.path.join(ROOT, "include", "cfft.h")
 
 def _lib():
     import torch  # noqa: F401  (binds the library to torch's HIP runtime)
-    from paper_1404_7357_amd import _lib as L
-    if not os.path.exists(L.LIB_PATH):
+    if not os.path.exists(os.path.join(ROOT, "paper_1404_7357_amd", "libcfft.so")):
         import __graft_entry__
         __graft_entry__.build()
+    from paper_1404_7357_amd import _lib as L
     return L, L.load()
 
 
