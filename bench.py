@@ -1,0 +1,317 @@
+#!/usr/bin/env python3
+"""Throughput of the contour-FFT tabulation on one MI355X.
+
+One step = the whole forward hot path for one antenna/substrate: the slab
+Green's function on the contour, the spectra of the M = 4 MBFs (B = 256
+rooftops each), and the C-FFT table of all 16 MBF pairs on a 512 x 512 grid
+(P = 3, gamma = 1/130), in FP64.  Inputs (basis geometry, coefficients,
+substrate) are resident before the timed region.
+
+Printed: one JSON line with the headline (table entries per second), the
+roofline of the dominant kernel (per-kernel HIP event timing), the CPU
+oracle timed on a bounded sample, and side measurements (mixed precision,
+adjoint/forward time on the 1024^2 differentiation workload).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _ensure_built():
+    if not os.path.exists(os.path.join(ROOT, "paper_1404_7357_amd", "libcfft.so")):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+def _source_hash():
+    h = hashlib.sha256()
+    for f in ("cfft_passes.hip", "cfft_device.h"):
+        with open(os.path.join(ROOT, "paper_1404_7357_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel, launch_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", "traffic_c2_fp64.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != _source_hash() or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel].get("hbm_bytes_per_launch")
+
+
+class Step:
+    """Resident inputs and one Tabulator for a workload grid."""
+
+    def __init__(self, wl, torch):
+        from paper_1404_7357_amd import FLAG_AUTOTUNE, Tabulator, _lib
+        self.torch = torch
+        self.wl = wl
+        self.grid = wl.grids[0]
+        self.sub = wl.substrates[0]
+        # the pair-chunk schedule is autotuned on the first (warm-up) call
+        self.tab = Tabulator(self.grid, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE)
+        self.q = torch.tensor(wl.q, device="cuda")
+        self.pairs = [tuple(int(v) for v in p) for p in wl.pairs]
+        gd = self.grid
+        dt = torch.complex128 if gd.precision == 0 else torch.complex64
+        self.g = torch.empty((3, gd.ny, gd.nx), dtype=torch.complex128, device="cuda")
+        self.spec = torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=torch.complex128, device="cuda")
+        self.z = torch.empty((len(self.pairs), gd.ny, gd.nx), dtype=dt, device="cuda")
+        self._lib = _lib
+
+    def run(self):
+        s = self.sub
+        self.tab.green(s.eps_r, s.tan_delta, s.h, out=self.g)
+        self.tab.spectra(self.q, out=self.spec)
+        self.tab.tabulate(self.spec, self.g, self.pairs, out=self.z)
+
+    def entries(self):
+        return self.grid.nx * self.grid.ny * len(self.pairs)
+
+
+def _time_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _kernel_times(st, steps):
+    """Average duration per launch (ms) of every kernel class, by HIP events on the launch stream."""
+    lib = st._lib
+    lib.profile(st.tab.plan, True)
+    for _ in range(steps):
+        st.run()
+    st.torch.cuda.synchronize()
+    lib.profile(st.tab.plan, False)
+    out = {}
+    for name in ("green", "spectra", "row_pass", "col_pass"):
+        ms, n = lib.profile_read(st.tab.plan, name)
+        if n:
+            out[name] = {"avg_ms": ms / n, "launches_per_step": n / steps}
+    return out
+
+
+def _cpu_baseline(wl, z_gpu, n_out, workers):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+
+    from oracle import cfft_oracle as co
+    grid, sub = wl.grids[0], wl.substrates[0]
+    rng = np.random.default_rng(2024)
+    idx = np.sort(rng.choice(grid.nx * grid.ny, n_out, replace=False))
+    idx[0] = (grid.ny // 2) * grid.nx + grid.nx // 2          # Delta = 0 (table maximum)
+    idx = np.unique(idx)
+    t0 = time.perf_counter()
+    ref = co.tabulate(grid, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=workers)
+    dt = time.perf_counter() - t0
+    entries = ref.size
+    zs = z_gpu.reshape(len(wl.pairs), -1)[:, idx]
+    err = float((np.abs(zs - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+    return {"value": entries / dt, "unit": "entries/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(idx)} output displacements x {len(wl.pairs)} pairs of the 512x512 table "
+                      f"(Green's function and spectra on all 262144 samples, direct sum per output), "
+                      f"{dt:.1f} s"}, err, (idx, ref)
+
+
+def _adjoint_ratio(torch, steps, warmup):
+    """Forward (table + lookup + loss) vs backward (lookup adjoint + cfft_backward) on 1024^2."""
+    from paper_1404_7357_amd import LookupFunction, TableFunction, Tabulator
+    from workloads import c5_gradient
+    wl = c5_gradient()
+    grid, sub = wl.grids[0], wl.substrates[0]
+    tab = Tabulator(grid, wl.basis, max_mbf=wl.M)
+    pairs = [tuple(int(v) for v in p) for p in wl.pairs]
+    pts = torch.tensor(wl.queries, device="cuda")
+    q = torch.tensor(wl.q, device="cuda", requires_grad=True)
+    eps = torch.tensor(sub.eps_r, dtype=torch.float64, device="cuda", requires_grad=True)
+    h = torch.tensor(sub.h, dtype=torch.float64, device="cuda", requires_grad=True)
+    zt = torch.zeros((len(pairs), pts.shape[0]), dtype=torch.complex128, device="cuda")
+
+    def fwd():
+        z = TableFunction.apply(eps, h, q, tab, sub.tan_delta, pairs, 0)
+        v = LookupFunction.apply(z, pts, tab, 0)
+        return (v - zt).abs().pow(2).sum()
+
+    def fwd_only():
+        with torch.no_grad():
+            fwd()
+
+    t_f = _time_steps(torch, fwd_only, steps, warmup)
+
+    def fwd_bwd():
+        eps.grad = h.grad = q.grad = None
+        loss = fwd()
+        loss.backward()
+
+    t_fb = _time_steps(torch, fwd_bwd, steps, warmup)
+    tab.close()
+    return {"workload": wl.name, "forward_ms": t_f * 1e3, "backward_ms": (t_fb - t_f) * 1e3,
+            "adjoint_forward_ratio": (t_fb - t_f) / t_f, "entries": grid.nx * grid.ny * len(pairs),
+            "queries": int(pts.shape[0])}
+
+
+def _sweep(torch, steps, warmup):
+    """Frequency sweep, 8 uneven grids x 16 pairs (mixed), eager and as one replayed HIP graph."""
+    from paper_1404_7357_amd import Tabulator
+    from workloads import c3_frequency_sweep
+    wl = c3_frequency_sweep()
+    tab = Tabulator(wl.grids, wl.basis, max_mbf=wl.M)
+    q = torch.tensor(wl.q, device="cuda")
+    pairs = [tuple(int(v) for v in p) for p in wl.pairs]
+    bufs = []
+    for gd in wl.grids:
+        bufs.append((torch.empty((3, gd.ny, gd.nx), dtype=torch.complex128, device="cuda"),
+                     torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=torch.complex128, device="cuda"),
+                     torch.empty((len(pairs), gd.ny, gd.nx), dtype=torch.complex64, device="cuda")))
+
+    def calls():
+        for i, (gd, sub) in enumerate(zip(wl.grids, wl.substrates)):
+            g, spec, z = bufs[i]
+            tab.green(sub.eps_r, sub.tan_delta, sub.h, grid=i, out=g)
+            tab.spectra(q, grid=i, out=spec)
+            tab.tabulate(spec, g, pairs, grid=i, out=z)
+
+    t_eager = _time_steps(torch, calls, steps, warmup)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        calls()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        calls()
+    t_graph = _time_steps(torch, graph.replay, steps, warmup)
+    entries = sum(gd.nx * gd.ny for gd in wl.grids) * len(pairs)
+    tab.close()
+    return {"workload": wl.name, "entries": entries, "value_graph": entries / t_graph,
+            "ms_graph": t_graph * 1e3, "value_eager": entries / t_eager, "ms_eager": t_eager * 1e3,
+            "dtype": "fp32 FFT / fp64 rest"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-outputs", type=int, default=1024, help="oracle sample size (outputs per pair)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and adjoint legs")
+    ap.add_argument("--copy-calibration", action="store_true", help="run one 256 MiB device copy (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    _ensure_built()
+    import numpy as np
+    import torch
+
+    from workloads import MIXED, c2_rooftop_512
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X (no device visible)", file=sys.stderr)
+        sys.exit(1)
+
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    wl = c2_rooftop_512()
+    _log(f"workload {wl.name}: warmup {args.warmup}, steps {args.steps}")
+    st = Step(wl, torch)
+    sec = _time_steps(torch, st.run, args.steps, args.warmup)
+    value = st.entries() / sec
+    _log(f"fp64 step {sec * 1e3:.3f} ms -> {value:.4e} entries/s")
+    kernels = _kernel_times(st, args.steps)
+    torch.cuda.synchronize()
+    z_fp64 = st.z.cpu().numpy()
+
+    # roofline of the dominant kernel (row or column pass)
+    n = wl.grids[0].nx * wl.grids[0].ny
+    P = wl.grids[0].order
+    npairs = len(wl.pairs)
+    s = 16
+    launch_bytes = {
+        "row_pass": (3 + 4 * wl.M) * n * 16 + (P + 1) * n * s * npairs,
+        "col_pass": (P + 1) * n * s * npairs + n * s * npairs,
+    }
+    dom = max(("row_pass", "col_pass"), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
+    avg_s = kernels[dom]["avg_ms"] * 1e-3
+    achieved = launch_bytes[dom] / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(dom, launch_bytes[dom]),
+                "algorithmic_bytes_per_launch": launch_bytes[dom]}
+    for k in ("row_pass", "col_pass"):
+        kernels[k]["achieved_GBs"] = launch_bytes[k] / (kernels[k]["avg_ms"] * 1e-3) / 1e9
+
+    out = {"metric": "MBF reaction terms tabulated/s at stated rel. error vs FP64; adjoint/forward time",
+           "value": value, "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": wl.name, "grid": "512x512", "pairs": npairs, "mbf": wl.M, "rooftops": wl.B,
+                      "order": P, "gamma": wl.grids[0].gamma, "eps_r": wl.substrates[0].eps_r,
+                      "tan_delta": wl.substrates[0].tan_delta, "h": wl.substrates[0].h,
+                      "precision": "fp64"},
+           "roofline": roofline, "kernels_ms": kernels}
+    st.tab.close()
+    del st
+
+    if not args.no_cpu_baseline:
+        workers = min(16, os.cpu_count() or 1)
+        _log(f"cpu oracle on {args.cpu_outputs} outputs x {npairs} pairs, {workers} threads")
+        base, err, sample = _cpu_baseline(wl, z_fp64, args.cpu_outputs, workers)
+        out["cpu_baseline"] = base
+        out["rel_err_vs_oracle"] = err
+    else:
+        sample = None
+
+    if not args.no_extras:
+        wlm = c2_rooftop_512(precision=MIXED)
+        stm = Step(wlm, torch)
+        secm = _time_steps(torch, stm.run, args.steps, args.warmup)
+        km = _kernel_times(stm, args.steps)
+        mixed = {"value": stm.entries() / secm, "ms_per_step": secm * 1e3, "dtype": "fp32 FFT / fp64 rest",
+                 "kernels_ms": km}
+        if sample is not None:
+            idx, ref = sample
+            zm = stm.z.cpu().numpy().reshape(npairs, -1)[:, idx]
+            mixed["rel_err_vs_oracle"] = float((np.abs(zm - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+        stm.tab.close()
+        del stm
+        out["mixed"] = mixed
+        _log("sweep leg (8 grids, one graph)")
+        out["sweep"] = _sweep(torch, max(3, args.steps // 5), 2)
+        _log("adjoint leg (1024^2, 16 pairs, 4096 lookups)")
+        out["adjoint"] = _adjoint_ratio(torch, max(3, args.steps // 5), 2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,7 +64,11 @@ typedef enum {
 enum { CFFT_CONTOUR_RAY = 0, CFFT_CONTOUR_PARABOLIC = 1 };
 enum { CFFT_FP64 = 0, CFFT_MIXED = 1 };
 enum { CFFT_ROOFTOP_X = 0, CFFT_ROOFTOP_Y = 1, CFFT_COSINE_X = 2, CFFT_COSINE_Y = 3 };
-enum { CFFT_FLAG_CHECK_FINITE = 1 };
+/* CHECK_FINITE: scan every output for NaN/Inf and report CFFT_ERR_NONFINITE
+ *   (makes the call synchronous).
+ * AUTOTUNE: the first cfft_tabulate per (grid, npairs) times the candidate
+ *   pair-chunk schedules (synchronously) and the plan keeps the fastest. */
+enum { CFFT_FLAG_CHECK_FINITE = 1, CFFT_FLAG_AUTOTUNE = 2 };
 
 /* One spectral grid.  64 bytes, natural alignment. */
 typedef struct {

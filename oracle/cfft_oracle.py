@@ -275,15 +275,24 @@ def direct_sum(integrands, kx, ky, dx, dy, gamma, order, dkx, dky, block=32, wor
     scale = dkx * dky / (4.0 * math.pi ** 2)
     out = np.zeros((integrands.shape[0], nq), dtype=np.complex128)
 
+    ns = kx.size
+    # the sum over samples is accumulated in slices of at most ~4M terms per
+    # output block so that huge grids fit in host memory
+    sstep = max(1, min(ns, (1 << 22) // max(1, block)))
+
     def one_block(q0):
         q1 = min(nq, q0 + block)
-        arg = np.outer(kx, dx[q0:q1]) + np.outer(ky, dy[q0:q1])   # k.Delta  [ns][nb]
-        kern = np.exp(-1j * arg)
-        if order >= 0:
-            kern *= taylor_poly(gamma * arg, order)
-        else:
-            kern *= np.exp(gamma * arg)
-        out[:, q0:q1] = scale * (integrands @ kern)
+        acc = np.zeros((integrands.shape[0], q1 - q0), dtype=np.complex128)
+        for s0 in range(0, ns, sstep):
+            s1 = min(ns, s0 + sstep)
+            arg = np.outer(kx[s0:s1], dx[q0:q1]) + np.outer(ky[s0:s1], dy[q0:q1])   # k.Delta
+            kern = np.exp(-1j * arg)
+            if order >= 0:
+                kern *= taylor_poly(gamma * arg, order)
+            else:
+                kern *= np.exp(gamma * arg)
+            acc += integrands[:, s0:s1] @ kern
+        out[:, q0:q1] = scale * acc
 
     starts = list(range(0, nq, block))
     if workers > 1:

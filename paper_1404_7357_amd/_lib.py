@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "ALLOC", 4: "HIP
 CONTOUR_RAY, CONTOUR_PARABOLIC = 0, 1
 FP64, MIXED = 0, 1
 FLAG_CHECK_FINITE = 1
+FLAG_AUTOTUNE = 2
 
 ENTRY_POINTS = ("c_fft_plan", "c_fft_plan_destroy", "slab_green_eval", "mbf_spectra", "cfft_tabulate",
                 "cfft_lookup", "cfft_lookup_backward", "cfft_backward", "cfft_profile", "cfft_profile_read",

@@ -173,6 +173,7 @@ struct cfft_plan_s {
   int* flag_host = nullptr;
   // instrumentation: recorded (start, stop) event pairs per kernel class
   bool profiling = false;
+  std::map<long long, long long> tuned;   // (grid, npairs) -> pair chunk
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[kProfClasses];
 };
 
@@ -466,7 +467,8 @@ cfft_status_t c_fft_plan(const cfft_grid_desc_t* grids, int32_t ngrids, int32_t 
   if (!grids) return fail(CFFT_ERR_INVALID_ARG, "grids is NULL");
   if (ngrids < 1 || ngrids > 64) return fail(CFFT_ERR_INVALID_ARG, "ngrids %d outside [1, 64]", ngrids);
   if (max_mbf < 1 || max_mbf > 16) return fail(CFFT_ERR_INVALID_ARG, "max_mbf %d outside [1, 16]", max_mbf);
-  if (flags & ~CFFT_FLAG_CHECK_FINITE) return fail(CFFT_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+  if (flags & ~(CFFT_FLAG_CHECK_FINITE | CFFT_FLAG_AUTOTUNE))
+    return fail(CFFT_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
   for (int i = 0; i < ngrids; ++i) {
     const cfft_grid_desc_t& g = grids[i];
     if (!pow2_in(g.nx, 16, 4096) || !pow2_in(g.ny, 16, 4096))
@@ -619,20 +621,65 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
     pm[i] = pairs[2 * i];
     pn[i] = pairs[2 * i + 1];
   }
-  for (int p0 = 0; p0 < npairs; p0 += (int)chunk) {
-    const int np = (int)std::min<long long>(chunk, npairs - p0);
-    hipError_t e;
-    {
-      ProfScope ps(plan, 2, s);
-      e = launch_row_pass(pp, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np, plan->ws,
-                          twx, s);
+  auto run_passes = [&](long long ck) -> hipError_t {
+    for (int p0 = 0; p0 < npairs; p0 += (int)ck) {
+      const int np = (int)std::min<long long>(ck, npairs - p0);
+      hipError_t e;
+      {
+        ProfScope ps(plan, 2, s);
+        e = launch_row_pass(pp, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np, plan->ws,
+                            twx, s);
+      }
+      if (e != hipSuccess) return e;
+      {
+        ProfScope ps(plan, 3, s);
+        e = launch_col_pass(pp, plan->ws, np, (char*)z + (size_t)p0 * n * cbytes, twy, s);
+      }
+      if (e != hipSuccess) return e;
     }
-    if (e != hipSuccess) return hip_fail(e, "row pass launch");
-    {
-      ProfScope ps(plan, 3, s);
-      e = launch_col_pass(pp, plan->ws, np, (char*)z + (size_t)p0 * n * cbytes, twy, s);
+    return hipSuccess;
+  };
+  // Pair-chunk schedule: smaller chunks keep the intermediates of a chunk
+  // resident in the memory-side cache between the two passes; with
+  // CFFT_FLAG_AUTOTUNE the first call per (grid, npairs) times the
+  // candidates (synchronously) and the plan keeps the fastest.
+  if ((plan->flags & CFFT_FLAG_AUTOTUNE) && forced <= 0) {
+    const long long key = (long long)grid * 1000003LL + npairs;
+    auto it = plan->tuned.find(key);
+    if (it == plan->tuned.end()) {
+      std::vector<long long> cands;
+      for (long long c : {chunk, 32LL, 16LL, 8LL, 4LL, 2LL, 1LL})
+        if (c <= chunk && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
+      hipEvent_t ea, eb;
+      hipError_t e = hipEventCreate(&ea);
+      if (e == hipSuccess) e = hipEventCreate(&eb);
+      if (e != hipSuccess) return hip_fail(e, "autotune events");
+      long long best = chunk;
+      float best_ms = 3.4e38f;
+      for (long long c : cands) {
+        e = run_passes(c);  // warm-up
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventRecord(ea, s);
+        if (e == hipSuccess) e = run_passes(c);
+        if (e == hipSuccess) e = hipEventRecord(eb, s);
+        if (e == hipSuccess) e = hipEventSynchronize(eb);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+        if (e != hipSuccess) break;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+      (void)hipEventDestroy(ea);
+      (void)hipEventDestroy(eb);
+      if (e != hipSuccess) return hip_fail(e, "autotune");
+      it = plan->tuned.emplace(key, best).first;
     }
-    if (e != hipSuccess) return hip_fail(e, "column pass launch");
+    chunk = it->second;
+  }
+  {
+    hipError_t e = run_passes(chunk);
+    if (e != hipSuccess) return hip_fail(e, "pass launch");
   }
   return check_finite(plan, z, 2 * n * (size_t)npairs, pp.precision != CFFT_FP64, s);
 }
@@ -703,6 +750,8 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   const long long limit_mb = env_ll("CFFT_WORKSPACE_MB", 16384);
   long long chunk = std::max<long long>(1, (limit_mb << 20) / (long long)per_pair);
   chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
+  const long long forced = env_ll("CFFT_PAIR_CHUNK", 0);
+  if (forced > 0) chunk = std::min<long long>(chunk, forced);
   const int green_blocks = 1024;
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   const size_t b_gg = al(3 * n * 16), b_gs = al((size_t)nmbf * 4 * n * 16);

@@ -192,10 +192,11 @@ __global__ void __launch_bounds__(C * (N / 8)) col_pass_kernel(ColArgs a) {
 }
 
 // Column tile width: as close to 128 B of contiguous row data as a 64 KiB
-// LDS tile and 1024 threads allow.
+// LDS tile and 512 threads allow (1024-thread blocks would cap the kernel at
+// 128 VGPRs and spill).
 __host__ __device__ constexpr int col_tile_c(int ny, int bytes) {
   int c = 128 / bytes;
-  while (c > 1 && (c * ny * bytes > 65536 || c * (ny / 8) > 1024)) c /= 2;
+  while (c > 1 && (c * ny * bytes > 65536 || c * (ny / 8) > 512)) c /= 2;
   return c;
 }
 

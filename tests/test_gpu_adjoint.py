@@ -1,0 +1,103 @@
+"""GPU adjoint (cfft_backward + lookup adjoint) against central finite
+differences of the GPU FP64 forward and against the oracle's gradient.
+
+Loss: L = sum_points sum_pairs |Z_mn(r_i) - Z_target|^2 with bilinear lookup,
+as in the differentiation workload; gradients w.r.t. eps_r, h and every MBF
+coefficient (d/dRe + i d/dIm convention, the one torch uses for complex
+leaves).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cfft_oracle as co
+from workloads import Grid, Substrate, gaussian_coefficients, rooftop_lattice
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+K0 = 2 * math.pi
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _problem(n=64, m=2, seed=41, npts=32):
+    rng = np.random.default_rng(seed)
+    grid = Grid(n, n, 6 * K0, 6 * K0, K0)
+    sub = Substrate(2.2, 0.0, 0.05)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, m, basis.shape[0])
+    pairs = [(a, b) for a in range(m) for b in range(m)]
+    dxa = co.displacement_axis(n, grid.kx_max)
+    pts = rng.uniform(dxa[1], dxa[-3], (npts, 2))
+    qt = q + 0.1 * gaussian_coefficients(rng, m, basis.shape[0])
+    zt = co.lookup_direct(grid, Substrate(2.3, 0.0, 0.05), basis, qt, np.array(pairs), pts)
+    return grid, sub, basis, q, pairs, pts, zt
+
+
+def _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt, eps=None, h=None, qv=None, need_grad=True):
+    from paper_1404_7357_amd import LookupFunction, TableFunction, Tabulator
+    tab = Tabulator(grid, basis, max_mbf=q.shape[0])
+    e = torch.tensor(sub.eps_r if eps is None else eps, dtype=torch.float64, device="cuda", requires_grad=True)
+    hh = torch.tensor(sub.h if h is None else h, dtype=torch.float64, device="cuda", requires_grad=True)
+    qq = torch.tensor(q if qv is None else qv, device="cuda", requires_grad=True)
+    z = TableFunction.apply(e, hh, qq, tab, sub.tan_delta, pairs, 0)
+    v = LookupFunction.apply(z, torch.tensor(pts, device="cuda"), tab, 0)
+    loss = (v - torch.tensor(zt, device="cuda")).abs().pow(2).sum()
+    out = [float(loss.item())]
+    if need_grad:
+        loss.backward()
+        out += [float(e.grad.item()), float(hh.grad.item()), qq.grad.cpu().numpy()]
+    tab.close()
+    return out
+
+
+def test_gradient_vs_central_differences():
+    _say("adjoint vs FD 64^2")
+    grid, sub, basis, q, pairs, pts, zt = _problem()
+    loss, de, dh, dq = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt)
+    step = 1e-6
+
+    def L(**kw):
+        return _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt, need_grad=False, **kw)[0]
+    fd_e = (L(eps=sub.eps_r + step) - L(eps=sub.eps_r - step)) / (2 * step)
+    fd_h = (L(h=sub.h + step) - L(h=sub.h - step)) / (2 * step)
+    assert abs(de - fd_e) < 1e-6 * max(1.0, abs(fd_e)), (de, fd_e)
+    assert abs(dh - fd_h) < 1e-6 * max(1.0, abs(fd_h)), (dh, fd_h)
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        m = int(rng.integers(q.shape[0]))
+        j = int(rng.integers(q.shape[1]))
+        d = np.zeros_like(q)
+        d[m, j] = step
+        fr = (L(qv=q + d) - L(qv=q - d)) / (2 * step)
+        fi = (L(qv=q + 1j * d) - L(qv=q - 1j * d)) / (2 * step)
+        assert abs(dq[m, j] - (fr + 1j * fi)) < 1e-6 * max(1.0, abs(dq).max()), (m, j, dq[m, j], fr, fi)
+
+
+def test_gradient_vs_oracle():
+    _say("adjoint vs oracle gradient 128^2")
+    grid, sub, basis, q, pairs, pts, zt = _problem(n=128, npts=64, seed=43)
+    loss, de, dh, dq = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt)
+    o_loss, o_de, o_dh, o_dq = co.loss_gradient(grid, sub, basis, q, np.array(pairs), pts, zt)
+    assert abs(loss - o_loss) < 1e-9 * abs(o_loss)
+    assert abs(de - o_de) < 1e-9 * max(abs(o_de), 1e-300), (de, o_de)
+    assert abs(dh - o_dh) < 1e-9 * max(abs(o_dh), 1e-300), (dh, o_dh)
+    assert np.abs(dq - o_dq).max() < 1e-9 * np.abs(o_dq).max()
+
+
+def test_backward_many_pairs_chunked(monkeypatch):
+    """Pair chunks accumulate the Green's and spectra gradients (ragged last chunk)."""
+    _say("adjoint chunked pairs")
+    grid, sub, basis, q, pairs, pts, zt = _problem(n=32, m=3, seed=47, npts=16)
+    full = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt)
+    monkeypatch.setenv("CFFT_PAIR_CHUNK", "2")        # 9 pairs -> chunks 2,2,2,2,1
+    chunked = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt)
+    assert abs(full[1] - chunked[1]) < 1e-12 * abs(full[1])
+    assert abs(full[2] - chunked[2]) < 1e-12 * abs(full[2])
+    assert np.abs(full[3] - chunked[3]).max() < 1e-12 * np.abs(full[3]).max()
