@@ -438,12 +438,17 @@ def _with_substrate(substrate, eps_r=None, h=None):
     return s
 
 
-def cauchy_derivative(f, z0, radius=1e-2, count=32):
+def cauchy_derivative(f, z0, radius=None, count=32):
     """f'(z0) of a holomorphic f by the trapezoidal Cauchy integral (Lyness-Moler).
 
     f'(z0) ~ 1/(K r) sum_k f(z0 + r e^{2 pi i k/K}) e^{-2 pi i k/K}; the error
-    decays like r^K for f analytic in a disc larger than r.
+    decays like (r/rho)^K for f analytic in a disc of radius rho > r.  The
+    table is analytic in eps_r and h only up to the substrate values at which
+    a surface-wave pole reaches a contour sample, which for a thin slab lies
+    within ~20 % of h; the default radius is therefore 0.2 % of |z0|.
     """
+    if radius is None:
+        radius = 2e-3 * max(abs(z0), 1e-3)
     acc = None
     for k in range(count):
         e = np.exp(2j * math.pi * k / count)

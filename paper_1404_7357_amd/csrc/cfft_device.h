@@ -194,7 +194,7 @@ __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* __res
 // it (it contains block barriers).
 template <typename V, int N, int R>
 __device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* __restrict__ tw, int t) {
-  static_assert(R == 8, "8 points per thread");
+  static_assert(R == 8 || R == 16, "8 or 16 points per thread");
   constexpr int LOG = ilog2c(N);
   constexpr int NR8 = LOG / 3;
   constexpr int REM = LOG % 3;

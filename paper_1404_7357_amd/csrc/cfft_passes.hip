@@ -117,86 +117,94 @@ struct ColArgs {
   double2 scale;   // K sigma W
 };
 
-template <int N, int C> struct ColCfg {
-  static constexpr int R = 8;
+// Column-pass block shape.  Thread tid works on column c = tid % C of the
+// tile at transform position t = tid / C, holding R points at stride
+// T = N/R.  A wave therefore covers 64/C consecutive rows of all C columns, so
+// every global load and store moves whole C*s-byte row segments (128 B when
+// C*s = 128) straight between HBM and registers; LDS is used only for the
+// FFT exchanges (one region of LDP entries per column).
+template <int N, int C, int R> struct ColCfg {
   static constexpr int T = N / R;
   static constexpr int THREADS = C * T;
   static constexpr int LDP = N + 2;
 };
 
-template <typename V, int N, int C>
-__global__ void __launch_bounds__(C * (N / 8)) col_pass_kernel(ColArgs a) {
-  using Cfg = ColCfg<N, C>;
-  constexpr int T = Cfg::T, R = Cfg::R, LDP = Cfg::LDP;
+template <typename V, int N, int C, int R>
+__global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
+  using Cfg = ColCfg<N, C, R>;
+  constexpr int T = Cfg::T, LDP = Cfg::LDP;
   using Rl = typename real_of<V>::type;
   __shared__ V lds[C * LDP];
   const int ntile = a.nx / C;
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = lid % ntile;
   const int pair = lid / ntile;
-  const int c = threadIdx.x / T;
-  const int t = threadIdx.x % T;
+  const int c = threadIdx.x % C;
+  const int t = threadIdx.x / C;
   const int j1 = tile * C + c;
   const V* tw = (const V*)a.tw;
-  const V* inter = (const V*)a.inter;
+  const size_t plane = (size_t)N * a.nx;
+  const V* col0 = (const V*)a.inter + (size_t)pair * (a.order + 1) * plane + j1;
 
   double2 Z[R];
-  double cf[R];
-  Rl pw[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    Z[r] = make_double2(0.0, 0.0);
-    cf[r] = 1.0;
-    const int n2 = t + T * r;
-    pw[r] = (n2 & 1) ? (Rl)-1 : (Rl)1;
+  for (int r = 0; r < R; ++r) Z[r] = make_double2(0.0, 0.0);
+  // term b reads S_{P-b}; the next term's column is fetched while this one
+  // is transformed.  The weights s(n2)(gamma ky)^b and Dy^b/b! are rebuilt
+  // per term (a few multiplies) rather than kept live in registers.
+  V nxt[R];
+  {
+    const V* src = col0 + (size_t)a.order * plane;
+#pragma unroll
+    for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
   }
   V* my_lds = lds + c * LDP;
   for (int b = 0; b <= a.order; ++b) {
-    const V* src = inter + (((size_t)pair * (a.order + 1) + (a.order - b)) * N) * a.nx + (size_t)tile * C;
-    for (int i = threadIdx.x; i < C * N; i += Cfg::THREADS) {
-      const int row = i / C, col = i % C;
-      lds[col * LDP + row] = src[(size_t)row * a.nx + col];
-    }
-    __syncthreads();
     V x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int n2 = t + T * r;
-      if (b > 0) pw[r] *= (Rl)(a.gamma * (a.ky0 + n2 * a.dky));
-      x[r] = cscale(my_lds[n2], pw[r]);
+      const Rl gk = (Rl)(a.gamma * (a.ky0 + n2 * a.dky));
+      Rl w = (n2 & 1) ? (Rl)-1 : (Rl)1;
+      for (int i = 0; i < b; ++i) w *= gk;
+      x[r] = cscale(nxt[r], w);
     }
-    __syncthreads();
+    if (b < a.order) {
+      const V* src = col0 + (size_t)(a.order - b - 1) * plane;
+#pragma unroll
+      for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
+    }
     fft_forward<V, N, R>(x, my_lds, tw, t);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j2 = t + T * r;
-      if (b > 0) cf[r] *= (a.y0 + j2 * a.ddy) / b;
+      const double dy = a.y0 + j2 * a.ddy;
+      double cf = 1.0;
+      for (int i = 1; i <= b; ++i) cf *= dy / i;
       const double2 xv = to_d(x[r]);
-      Z[r] = make_double2(Z[r].x + cf[r] * xv.x, Z[r].y + cf[r] * xv.y);
+      Z[r] = make_double2(Z[r].x + cf * xv.x, Z[r].y + cf * xv.y);
     }
   }
-  __syncthreads();
+  V* dst = (V*)a.z + (size_t)pair * plane + j1;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j2 = t + T * r;
     double2 v = cmul(Z[r], a.scale);
     if ((j1 + j2) & 1) v = make_double2(-v.x, -v.y);
-    my_lds[j2] = from_d<V>(v);
-  }
-  __syncthreads();
-  V* dst = (V*)a.z + (size_t)pair * N * a.nx + (size_t)tile * C;
-  for (int i = threadIdx.x; i < C * N; i += Cfg::THREADS) {
-    const int row = i / C, col = i % C;
-    dst[(size_t)row * a.nx + col] = lds[col * LDP + row];
+    dst[(size_t)j2 * a.nx] = from_d<V>(v);
   }
 }
 
-// Column tile width: as close to 128 B of contiguous row data as a 64 KiB
+// Points per thread of the column pass.
+__host__ __device__ constexpr int col_r(int) { return 8; }
+
+// Column tile width: as close to 128 B of contiguous row data as an 80 KiB
 // LDS tile and 512 threads allow (1024-thread blocks would cap the kernel at
 // 128 VGPRs and spill).
 __host__ __device__ constexpr int col_tile_c(int ny, int bytes) {
   int c = 128 / bytes;
-  while (c > 1 && (c * ny * bytes > 65536 || c * (ny / 8) > 512)) c /= 2;
+  const int r = col_r(bytes);
+  while (c > 1 && (c * (ny + 2) * bytes > 81920 || c * (ny / r) > 512)) c /= 2;
   return c;
 }
 
@@ -214,10 +222,11 @@ static hipError_t row_launch(const RowArgs& args, hipStream_t s) {
 template <typename V, int N>
 static hipError_t col_launch(const ColArgs& args, hipStream_t s) {
   constexpr int C = col_tile_c(N, sizeof(V));
-  using Cfg = ColCfg<N, C>;
+  constexpr int R = col_r(sizeof(V));
+  using Cfg = ColCfg<N, C, R>;
   if (args.nx % C != 0) return hipErrorInvalidValue;
   const int nblk = (args.nx / C) * args.npairs;
-  hipLaunchKernelGGL((col_pass_kernel<V, N, C>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
+  hipLaunchKernelGGL((col_pass_kernel<V, N, C, R>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
   return hipGetLastError();
 }
 
@@ -314,36 +323,32 @@ struct AdjColArgs {
 
 template <int N, int C>
 __global__ void __launch_bounds__(C * (N / 8)) adj_col_kernel(AdjColArgs a) {
-  using Cfg = ColCfg<N, C>;
-  constexpr int T = Cfg::T, R = Cfg::R, LDP = Cfg::LDP;
+  constexpr int R = 8;
+  using Cfg = ColCfg<N, C, R>;
+  constexpr int T = Cfg::T, LDP = Cfg::LDP;
   __shared__ double2 lds[C * LDP];
   const int ntile = a.nx / C;
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = lid % ntile;
   const int pair = lid / ntile;
-  const int c = threadIdx.x / T;
-  const int t = threadIdx.x % T;
+  const int c = threadIdx.x % C;
+  const int t = threadIdx.x / C;
   const int j1 = tile * C + c;
-  const double2* src = a.dz + (size_t)pair * N * a.nx + (size_t)tile * C;
-  for (int i = threadIdx.x; i < C * N; i += Cfg::THREADS) {
-    const int row = i / C, col = i % C;
-    lds[col * LDP + row] = src[(size_t)row * a.nx + col];
-  }
-  __syncthreads();
-  double2* my_lds = lds + c * LDP;
+  const size_t plane = (size_t)N * a.nx;
+  const double2* src = a.dz + (size_t)pair * plane + j1;
   double2 h0[R], acc[R];
   double cf[R], pw[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j2 = t + T * r;
-    double2 v = cmul(my_lds[j2], a.cscale);
+    double2 v = cmul(src[(size_t)j2 * a.nx], a.cscale);
     if ((j1 + j2) & 1) v = make_double2(-v.x, -v.y);
     h0[r] = v;
     acc[r] = make_double2(0.0, 0.0);
     cf[r] = 1.0;
     pw[r] = 1.0;
   }
-  __syncthreads();
+  double2* my_lds = lds + c * LDP;
   for (int b = 0; b <= a.order; ++b) {
     double2 x[R];
 #pragma unroll
@@ -353,20 +358,14 @@ __global__ void __launch_bounds__(C * (N / 8)) adj_col_kernel(AdjColArgs a) {
       x[r] = cscale(h0[r], cf[r]);
     }
     fft_inverse<double2, N, R>(x, my_lds, a.tw, t);
+    double2* dst = a.inter + ((size_t)pair * (a.order + 1) + b) * plane + j1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int n2 = t + T * r;
       if (b > 0) pw[r] *= a.gamma * (a.ky0 + n2 * a.dky);
       acc[r] = cadd(acc[r], cscale(x[r], pw[r]));
-      my_lds[n2] = acc[r];
+      dst[(size_t)n2 * a.nx] = acc[r];
     }
-    __syncthreads();
-    double2* dst = a.inter + (((size_t)pair * (a.order + 1) + b) * N) * a.nx + (size_t)tile * C;
-    for (int i = threadIdx.x; i < C * N; i += Cfg::THREADS) {
-      const int row = i / C, col = i % C;
-      dst[(size_t)row * a.nx + col] = lds[col * LDP + row];
-    }
-    __syncthreads();
   }
 }
 
@@ -431,7 +430,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
 template <int N>
 static hipError_t adj_col_launch(const AdjColArgs& args, hipStream_t s) {
   constexpr int C = col_tile_c(N, 16);
-  using Cfg = ColCfg<N, C>;
+  using Cfg = ColCfg<N, C, 8>;
   if (args.nx % C != 0) return hipErrorInvalidValue;
   const int nblk = (args.nx / C) * args.npairs;
   hipLaunchKernelGGL((adj_col_kernel<N, C>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
