@@ -313,7 +313,7 @@ cfft_status_t ensure_geometry(cfft_plan_s* plan, GridState& gs, const cfft_basis
     for (auto& g : plan->grids) g.utab_geo = 0;
   }
   if (gs.utab_geo != plan->geo_hash) {
-    const size_t need = sizeof(double2) * (size_t)(2 * plan->geo_dev.total_p + plan->geo_dev.ngroups) * gs.x.n;
+    const size_t need = sizeof(double2) * spectra_tables_len(gs.x, gs.y, plan->geo_dev);
     if (gs.utab_bytes < need) {
       if (gs.utab) {
         hipError_t e = hipStreamSynchronize(s);
@@ -326,7 +326,7 @@ cfft_status_t ensure_geometry(cfft_plan_s* plan, GridState& gs, const cfft_basis
       if (st != CFFT_OK) return st;
       gs.utab_bytes = need;
     }
-    hipError_t e = launch_spectra_tables(gs.x, gs.d.gamma, plan->geo_dev, gs.utab, s);
+    hipError_t e = launch_spectra_tables(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, s);
     if (e != hipSuccess) return hip_fail(e, "spectra tables launch");
     gs.utab_geo = plan->geo_hash;
   }

@@ -106,6 +106,14 @@ __device__ __forceinline__ double2 csinc(double2 z) {
 // ---------------------------------------------------------------- FFT
 __host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
+// LDS slot of exchange element i: one pad entry after every 8 elements.  A
+// radix-8 stage writes 8 consecutive elements per thread (stride 128 B for
+// complex128), which without padding puts every other thread on the same
+// banks; the pad spreads those writes over all 64 banks.
+__host__ __device__ constexpr int lds_slot(int i) { return i + (i >> 3); }
+// LDS entries needed by one length-N exchange buffer.
+__host__ __device__ constexpr int lds_len(int n) { return n + n / 8; }
+
 // In-register forward DFT of 2, 4 or 8 points (omega = exp(-2 pi i / n)).
 template <typename V> __device__ __forceinline__ void dft2(V& a, V& b) {
   const V t = a;
@@ -152,7 +160,7 @@ template <typename V, int RHO> __device__ __forceinline__ void dft_small(V* y) {
 // One Stockham stage of radix RHO on a length-N transform spread over
 // T = N/R threads, each holding R points at stride T (x[r] = data[t + T r]).
 // L is the length of the sub-transforms already done.  Non-final stages
-// exchange through `lds` (N entries); the final stage leaves the outputs in
+// exchange through `lds` (lds_len(N) entries, padded slots); the final stage leaves the outputs in
 // registers in the same stride-T order.
 template <typename V, int N, int R, int RHO, bool LAST>
 __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* __restrict__ tw, int t, int L) {
@@ -177,13 +185,13 @@ __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* __res
     } else {
       const int base = (i - k) * RHO + k;
 #pragma unroll
-      for (int q = 0; q < RHO; ++q) lds[base + q * L] = y[q];
+      for (int q = 0; q < RHO; ++q) lds[lds_slot(base + q * L)] = y[q];
     }
   }
   if constexpr (!LAST) {
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = lds[t + T * r];
+    for (int r = 0; r < R; ++r) x[r] = lds[lds_slot(t + T * r)];
     __syncthreads();
   }
 }

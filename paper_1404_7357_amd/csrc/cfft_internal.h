@@ -57,8 +57,9 @@ struct PassParams {
 // Launchers; all return hipSuccess or the launch error.
 hipError_t launch_green(const GreenParams& p, double2* g, hipStream_t s);
 
-hipError_t launch_spectra_tables(const Axis& x, double gamma, const GeomDevice& geo, double2* utab,
-                                 hipStream_t s);
+hipError_t launch_spectra_tables(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
+                                 double2* utab, hipStream_t s);
+size_t spectra_tables_len(const Axis& x, const Axis& y, const GeomDevice& geo);
 hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
                           const double2* utab, const double2* q, int nmbf, double2* spec,
                           hipStream_t s);

@@ -38,6 +38,7 @@ struct RowArgs {
   const void* tw;
   int nx, ny, order, npairs;
   double kx0, dkx, x0, ddx, gamma;
+  double rinv[kMaxOrder + 1];   // 1/i (the Taylor weights need no division)
   int pm[kMaxPairsPerLaunch];
   int pn[kMaxPairsPerLaunch];
 };
@@ -47,7 +48,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
   using Cfg = RowCfg<N>;
   constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
   using Rl = typename real_of<V>::type;
-  __shared__ V lds[ROWS * N];
+  __shared__ V lds[ROWS * lds_len(N)];
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int pair = lid % a.npairs;
   const int rb = lid / a.npairs;
@@ -84,14 +85,14 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
     S[r] = make_double2(0.0, 0.0);
     cf[r] = 1.0;
   }
-  V* my_lds = lds + grp * N;
+  V* my_lds = lds + grp * lds_len(N);
   for (int ao = 0; ao <= a.order; ++ao) {
     if (ao > 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int n1 = t + T * r;
         f[r] = cscale(f[r], (Rl)(a.gamma * (a.kx0 + n1 * a.dkx)));
-        cf[r] *= (a.x0 + n1 * a.ddx) / ao;
+        cf[r] *= (a.x0 + n1 * a.ddx) * a.rinv[ao];
       }
     }
     V x[R];
@@ -115,6 +116,7 @@ struct ColArgs {
   int nx, ny, order, npairs;
   double ky0, dky, y0, ddy, gamma;
   double2 scale;   // K sigma W
+  double rinv[kMaxOrder + 1];
 };
 
 // Column-pass block shape.  Thread tid works on column c = tid % C of the
@@ -126,7 +128,7 @@ struct ColArgs {
 template <int N, int C, int R> struct ColCfg {
   static constexpr int T = N / R;
   static constexpr int THREADS = C * T;
-  static constexpr int LDP = N + 2;
+  static constexpr int LDP = lds_len(N) + 2;
 };
 
 template <typename V, int N, int C, int R>
@@ -180,7 +182,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
       const int j2 = t + T * r;
       const double dy = a.y0 + j2 * a.ddy;
       double cf = 1.0;
-      for (int i = 1; i <= b; ++i) cf *= dy / i;
+      for (int i = 1; i <= b; ++i) cf *= dy * a.rinv[i];
       const double2 xv = to_d(x[r]);
       Z[r] = make_double2(Z[r].x + cf * xv.x, Z[r].y + cf * xv.y);
     }
@@ -204,13 +206,18 @@ __host__ __device__ constexpr int col_r(int) { return 8; }
 __host__ __device__ constexpr int col_tile_c(int ny, int bytes) {
   int c = 128 / bytes;
   const int r = col_r(bytes);
-  while (c > 1 && (c * (ny + 2) * bytes > 81920 || c * (ny / r) > 512)) c /= 2;
+  while (c > 1 && (c * (lds_len(ny) + 2) * bytes > 81920 || c * (ny / r) > 512)) c /= 2;
   return c;
 }
 
 int col_tile(int ny, int precision) { return col_tile_c(ny, precision == 0 ? 16 : 8); }
 
 // ------------------------------------------------ dispatch over sizes
+static void fill_rinv(double* r) {
+  r[0] = 1.0;
+  for (int i = 1; i <= kMaxOrder; ++i) r[i] = 1.0 / i;
+}
+
 template <typename V, int N>
 static hipError_t row_launch(const RowArgs& args, hipStream_t s) {
   using Cfg = RowCfg<N>;
@@ -266,6 +273,7 @@ hipError_t launch_row_pass(const PassParams& p, const double2* g, const double2*
   a.x0 = p.x.d_first;
   a.ddx = p.x.dd;
   a.gamma = p.gamma;
+  fill_rinv(a.rinv);
   for (int i = 0; i < kMaxPairsPerLaunch; ++i) {
     a.pm[i] = i < npairs ? pm[i] : 0;
     a.pn[i] = i < npairs ? pn[i] : 0;
@@ -301,6 +309,7 @@ hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, v
   a.ddy = p.y.dd;
   a.gamma = p.gamma;
   a.scale = table_scale(p);
+  fill_rinv(a.rinv);
   if (p.precision == 0) {
     CFFT_SIZE_SWITCH(p.y.n, col_fp64, a, s)
   }
@@ -319,6 +328,7 @@ struct AdjColArgs {
   int nx, ny, order, npairs;
   double ky0, dky, y0, ddy, gamma;
   double2 cscale;  // conj(K sigma W)
+  double rinv[kMaxOrder + 1];
 };
 
 template <int N, int C>
@@ -354,7 +364,7 @@ __global__ void __launch_bounds__(C * (N / 8)) adj_col_kernel(AdjColArgs a) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j2 = t + T * r;
-      if (b > 0) cf[r] *= (a.y0 + j2 * a.ddy) / b;
+      if (b > 0) cf[r] *= (a.y0 + j2 * a.ddy) * a.rinv[b];
       x[r] = cscale(h0[r], cf[r]);
     }
     fft_inverse<double2, N, R>(x, my_lds, a.tw, t);
@@ -375,13 +385,14 @@ struct AdjRowArgs {
   const double2* tw;
   int nx, ny, order, npairs;
   double kx0, dkx, x0, ddx, gamma;
+  double rinv[kMaxOrder + 1];
 };
 
 template <int N>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs a) {
   using Cfg = RowCfg<N>;
   constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
-  __shared__ double2 lds[ROWS * N];
+  __shared__ double2 lds[ROWS * lds_len(N)];
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int pair = lid % a.npairs;
   const int rb = lid / a.npairs;
@@ -397,7 +408,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
     cf[r] = 1.0;
     pw[r] = 1.0;
   }
-  double2* my_lds = lds + grp * N;
+  double2* my_lds = lds + grp * lds_len(N);
   for (int ao = 0; ao <= a.order; ++ao) {
     const double2* src =
         a.inter + (((size_t)pair * (a.order + 1) + (a.order - ao)) * a.ny + (valid ? n2 : 0)) * N;
@@ -405,7 +416,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j1 = t + T * r;
-      if (ao > 0) cf[r] *= (a.x0 + j1 * a.ddx) / ao;
+      if (ao > 0) cf[r] *= (a.x0 + j1 * a.ddx) * a.rinv[ao];
       x[r] = valid ? cscale(src[j1], cf[r]) : make_double2(0.0, 0.0);
     }
     fft_inverse<double2, N, R>(x, my_lds, a.tw, t);
@@ -462,6 +473,7 @@ hipError_t launch_adj_col_pass(const PassParams& p, const double2* dz, int npair
   a.gamma = p.gamma;
   const double2 sc = table_scale(p);
   a.cscale = make_double2(sc.x, -sc.y);
+  fill_rinv(a.rinv);
   CFFT_SIZE_SWITCH(p.y.n, adj_col_launch, a, s)
 }
 
@@ -480,6 +492,7 @@ hipError_t launch_adj_row_pass(const PassParams& p, const double2* inter, int np
   a.x0 = p.x.d_first;
   a.ddx = p.x.dd;
   a.gamma = p.gamma;
+  fill_rinv(a.rinv);
   CFFT_SIZE_SWITCH(p.x.n, adj_row_launch, a, s)
 }
 

@@ -42,43 +42,85 @@ __device__ __forceinline__ void phase_pair(double k, double gamma, double X, dou
   uh = make_double2(ei * c, ei * s);
 }
 
-// utab rows: [2 (uoff+p)] = U, [2 (uoff+p) + 1] = U#, [2 total_p + g] = SX_g.
-__global__ void spectra_tables_kernel(Axis x, double gamma, GeomDevice geo, double2* __restrict__ utab) {
-  const int n1 = blockIdx.x * blockDim.x + threadIdx.x;
+// Geometry tables of one grid (built once per grid and basis set):
+//   x part, rows of length nx: [2 (uoff+p)] = U, [2 (uoff+p) + 1] = U#,
+//                              [2 total_p + g] = SX_g
+//   y part (at vtab_offset), rows of length ny: [2 (yoff+r)] = V,
+//                              [2 (yoff+r) + 1] = V#, [2 total_r + g] = SY_g
+__host__ __device__ inline size_t vtab_offset(int nx, const GeomDevice& geo) {
+  return (size_t)(2 * geo.total_p + geo.ngroups) * nx;
+}
+
+__device__ __forceinline__ int group_of(const GeomDevice& geo, int row, bool by_r) {
+  int g = 0;
+  while (g + 1 < geo.ngroups && (by_r ? geo.groups[g + 1].yoff : geo.groups[g + 1].uoff) <= row) ++g;
+  return g;
+}
+
+__global__ void spectra_tables_kernel(Axis x, Axis y, double gamma, GeomDevice geo, double2* __restrict__ utab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int row = blockIdx.y;
-  if (n1 >= x.n) return;
-  const double kx = x.k_first + n1 * x.dk;
-  const double2 kcx = make_double2(kx, gamma * kx);
-  if (row < geo.total_p) {
-    // find the group owning this p row
-    int g = 0;
-    while (g + 1 < geo.ngroups && geo.groups[g + 1].uoff <= row) ++g;
-    const GeomGroup gr = geo.groups[g];
-    const double X = geo.xs[gr.xoff + (row - gr.uoff)];
-    double2 u, uh;
-    phase_pair(kx, gamma, X, u, uh);
-    utab[(size_t)(2 * row) * x.n + n1] = u;
-    utab[(size_t)(2 * row + 1) * x.n + n1] = uh;
+  const int nxrows = geo.total_p + geo.ngroups;
+  if (row < nxrows) {
+    if (i >= x.n) return;
+    const double k = x.k_first + i * x.dk;
+    if (row < geo.total_p) {
+      const GeomGroup gr = geo.groups[group_of(geo, row, false)];
+      double2 u, uh;
+      phase_pair(k, gamma, geo.xs[gr.xoff + (row - gr.uoff)], u, uh);
+      utab[(size_t)(2 * row) * x.n + i] = u;
+      utab[(size_t)(2 * row + 1) * x.n + i] = uh;
+    } else {
+      const int g = row - geo.total_p;
+      const GeomGroup gr = geo.groups[g];
+      const double2 kc = make_double2(k, gamma * k);
+      utab[(size_t)(2 * geo.total_p + g) * x.n + i] =
+          is_ydir(gr.kind) ? across_factor(gr.b, kc) : along_factor(gr.kind, gr.a, kc);
+    }
   } else {
-    const int g = row - geo.total_p;
-    const GeomGroup gr = geo.groups[g];
-    const double2 sx = is_ydir(gr.kind) ? across_factor(gr.b, kcx) : along_factor(gr.kind, gr.a, kcx);
-    utab[(size_t)(2 * geo.total_p + g) * x.n + n1] = sx;
+    if (i >= y.n) return;
+    double2* vtab = utab + vtab_offset(x.n, geo);
+    const int vr = row - nxrows;
+    const double k = y.k_first + i * y.dk;
+    if (vr < geo.total_r) {
+      const GeomGroup gr = geo.groups[group_of(geo, vr, true)];
+      double2 v, vh;
+      phase_pair(k, gamma, geo.ys[vr], v, vh);
+      vtab[(size_t)(2 * vr) * y.n + i] = v;
+      vtab[(size_t)(2 * vr + 1) * y.n + i] = vh;
+      (void)gr;
+    } else {
+      const int g = vr - geo.total_r;
+      const GeomGroup gr = geo.groups[g];
+      const double2 kc = make_double2(k, gamma * k);
+      vtab[(size_t)(2 * geo.total_r + g) * y.n + i] =
+          is_ydir(gr.kind) ? along_factor(gr.kind, gr.a, kc) : across_factor(gr.b, kc);
+    }
   }
 }
 
-hipError_t launch_spectra_tables(const Axis& x, double gamma, const GeomDevice& geo, double2* utab,
+size_t spectra_tables_len(const Axis& x, const Axis& y, const GeomDevice& geo) {
+  return (size_t)(2 * geo.total_p + geo.ngroups) * x.n + (size_t)(2 * geo.total_r + geo.ngroups) * y.n;
+}
+
+hipError_t launch_spectra_tables(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo, double2* utab,
                                  hipStream_t s) {
-  dim3 grid((x.n + 127) / 128, geo.total_p + geo.ngroups);
-  hipLaunchKernelGGL(spectra_tables_kernel, grid, dim3(128), 0, s, x, gamma, geo, utab);
+  const int nmax = x.n > y.n ? x.n : y.n;
+  dim3 grid((nmax + 127) / 128, geo.total_p + geo.total_r + 2 * geo.ngroups);
+  hipLaunchKernelGGL(spectra_tables_kernel, grid, dim3(128), 0, s, x, y, gamma, geo, utab);
   return hipGetLastError();
 }
 
 constexpr int kSpecThreads = 256;
 constexpr int kMaxGroups = 32;  // host refuses basis sets needing more
 constexpr int kMChunk = 4;
+constexpr int kPChunk = 8;
 
-// One block per row n2.  Dynamic LDS: w and w# = [nmbf][total_p] complex each.
+// Block = (256 consecutive samples of one row n2).  Prologue: the per-row
+// contraction over y-centres, w[m][uoff+p] = SY_g sum_r conj(q) V_gr and
+// w#[m][uoff+p] = SY_g sum_r q V#_gr, from the tables into LDS.  Main part:
+// one sample per thread, M_m = sum_g SX_g sum_p U_gp w[m][p], with the U loads
+// of a chunk of kPChunk centres issued together.
 __global__ void __launch_bounds__(kSpecThreads)
 spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __restrict__ utab,
                const double2* __restrict__ q, int nmbf, double2* __restrict__ spec) {
@@ -86,12 +128,11 @@ spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __re
   double2* w = sh;                              // [nmbf][total_p]
   double2* wh = sh + nmbf * geo.total_p;        // [nmbf][total_p]
   __shared__ GeomGroup grp[kMaxGroups];
-  const int n2 = blockIdx.x;
-  const double ky = y.k_first + n2 * y.dk;
-  const double2 kcy = make_double2(ky, gamma * ky);
+  const int n2 = blockIdx.y;
+  const int n1 = blockIdx.x * blockDim.x + threadIdx.x;
+  const double2* vtab = utab + vtab_offset(x.n, geo);
   if (threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
   __syncthreads();
-  // w[m][uoff+p] = SY_g sum_r conj(q) V_gr ; wh = SY_g sum_r q V#_gr
   const int nw = nmbf * geo.total_p;
   for (int e = threadIdx.x; e < nw; e += blockDim.x) {
     const int m = e / geo.total_p;
@@ -100,13 +141,13 @@ spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __re
     while (g + 1 < geo.ngroups && grp[g + 1].uoff <= prow) ++g;
     const GeomGroup gr = grp[g];
     const int p = prow - gr.uoff;
-    const double2 sy = is_ydir(gr.kind) ? along_factor(gr.kind, gr.a, kcy) : across_factor(gr.b, kcy);
+    const double2 sy = vtab[(size_t)(2 * geo.total_r + g) * y.n + n2];
     double2 acc = make_double2(0.0, 0.0), acch = make_double2(0.0, 0.0);
     for (int r = 0; r < gr.nr; ++r) {
       const int j = geo.index[gr.ioff + p * gr.nr + r];
       if (j < 0) continue;
-      double2 v, vh;
-      phase_pair(ky, gamma, geo.ys[gr.yoff + r], v, vh);
+      const double2 v = vtab[(size_t)(2 * (gr.yoff + r)) * y.n + n2];
+      const double2 vh = vtab[(size_t)(2 * (gr.yoff + r) + 1) * y.n + n2];
       const double2 qq = q[(size_t)m * geo.nbasis + j];
       acc = cadd(acc, cmulc(v, qq));      // conj(q) V
       acch = cadd(acch, cmul(qq, vh));    // q V#
@@ -115,46 +156,54 @@ spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __re
     wh[e] = cmul(acch, sy);
   }
   __syncthreads();
+  if (n1 >= x.n) return;
   const size_t plane = (size_t)x.n * y.n;
-  for (int n1 = threadIdx.x; n1 < x.n; n1 += blockDim.x) {
-    for (int m0 = 0; m0 < nmbf; m0 += kMChunk) {
-      double2 acc[kMChunk][4];
+  for (int m0 = 0; m0 < nmbf; m0 += kMChunk) {
+    double2 acc[kMChunk][4];
 #pragma unroll
-      for (int i = 0; i < kMChunk; ++i)
+    for (int i = 0; i < kMChunk; ++i)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[i][c] = make_double2(0.0, 0.0);
-      for (int g = 0; g < geo.ngroups; ++g) {
-        const GeomGroup gr = grp[g];
-        const int comp = is_ydir(gr.kind) ? 1 : 0;
-        const double2 sx = utab[(size_t)(2 * geo.total_p + g) * x.n + n1];
-        double2 sg[kMChunk], sgh[kMChunk];
+      for (int c = 0; c < 4; ++c) acc[i][c] = make_double2(0.0, 0.0);
+    for (int g = 0; g < geo.ngroups; ++g) {
+      const GeomGroup gr = grp[g];
+      const int comp = is_ydir(gr.kind) ? 1 : 0;
+      const double2 sx = utab[(size_t)(2 * geo.total_p + g) * x.n + n1];
+      double2 sg[kMChunk], sgh[kMChunk];
 #pragma unroll
-        for (int i = 0; i < kMChunk; ++i) sg[i] = sgh[i] = make_double2(0.0, 0.0);
-        for (int p = 0; p < gr.np; ++p) {
-          const int prow = gr.uoff + p;
-          const double2 u = utab[(size_t)(2 * prow) * x.n + n1];
-          const double2 uh = utab[(size_t)(2 * prow + 1) * x.n + n1];
+      for (int i = 0; i < kMChunk; ++i) sg[i] = sgh[i] = make_double2(0.0, 0.0);
+      for (int p0 = 0; p0 < gr.np; p0 += kPChunk) {
+        double2 u[kPChunk], uh[kPChunk];
 #pragma unroll
-          for (int i = 0; i < kMChunk; ++i) {
-            if (m0 + i < nmbf) {
-              sg[i] = cadd(sg[i], cmul(u, w[(m0 + i) * geo.total_p + prow]));
-              sgh[i] = cadd(sgh[i], cmul(uh, wh[(m0 + i) * geo.total_p + prow]));
-            }
-          }
+        for (int k = 0; k < kPChunk; ++k) {
+          const int prow = gr.uoff + (p0 + k < gr.np ? p0 + k : gr.np - 1);
+          u[k] = utab[(size_t)(2 * prow) * x.n + n1];
+          uh[k] = utab[(size_t)(2 * prow + 1) * x.n + n1];
         }
 #pragma unroll
-        for (int i = 0; i < kMChunk; ++i) {
-          acc[i][comp] = cadd(acc[i][comp], cmul(sg[i], sx));
-          acc[i][2 + comp] = cadd(acc[i][2 + comp], cmul(sgh[i], sx));
+        for (int k = 0; k < kPChunk; ++k) {
+          if (p0 + k < gr.np) {
+            const int prow = gr.uoff + p0 + k;
+#pragma unroll
+            for (int i = 0; i < kMChunk; ++i) {
+              if (m0 + i < nmbf) {
+                sg[i] = cadd(sg[i], cmul(u[k], w[(m0 + i) * geo.total_p + prow]));
+                sgh[i] = cadd(sgh[i], cmul(uh[k], wh[(m0 + i) * geo.total_p + prow]));
+              }
+            }
+          }
         }
       }
 #pragma unroll
       for (int i = 0; i < kMChunk; ++i) {
-        if (m0 + i < nmbf) {
+        acc[i][comp] = cadd(acc[i][comp], cmul(sg[i], sx));
+        acc[i][2 + comp] = cadd(acc[i][2 + comp], cmul(sgh[i], sx));
+      }
+    }
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            spec[((size_t)(m0 + i) * 4 + c) * plane + (size_t)n2 * x.n + n1] = acc[i][c];
-        }
+    for (int i = 0; i < kMChunk; ++i) {
+      if (m0 + i < nmbf) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) spec[((size_t)(m0 + i) * 4 + c) * plane + (size_t)n2 * x.n + n1] = acc[i][c];
       }
     }
   }
@@ -163,8 +212,8 @@ spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __re
 hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
                           const double2* utab, const double2* q, int nmbf, double2* spec, hipStream_t s) {
   const size_t lds = sizeof(double2) * 2 * (size_t)nmbf * geo.total_p;
-  hipLaunchKernelGGL(spectra_kernel, dim3(y.n), dim3(kSpecThreads), lds, s, x, y, gamma, geo, utab, q, nmbf,
-                     spec);
+  dim3 grid((x.n + kSpecThreads - 1) / kSpecThreads, y.n);
+  hipLaunchKernelGGL(spectra_kernel, grid, dim3(kSpecThreads), lds, s, x, y, gamma, geo, utab, q, nmbf, spec);
   return hipGetLastError();
 }
 
@@ -238,9 +287,10 @@ adj_spectra_rows_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const doub
     if (j < 0) continue;
     const int p = (li - gr.ioff) / gr.nr;
     const int r = (li - gr.ioff) % gr.nr;
-    const double2 sy = is_ydir(gr.kind) ? along_factor(gr.kind, gr.a, kcy) : across_factor(gr.b, kcy);
-    double2 v, vh;
-    phase_pair(ky, gamma, geo.ys[gr.yoff + r], v, vh);
+    const double2* vtab = utab + vtab_offset(x.n, geo);
+    const double2 sy = vtab[(size_t)(2 * geo.total_r + g) * y.n + n2];
+    const double2 v = vtab[(size_t)(2 * (gr.yoff + r)) * y.n + n2];
+    const double2 vh = vtab[(size_t)(2 * (gr.yoff + r) + 1) * y.n + n2];
     const double2 t1 = cmul(cmul(sy, v), a1[m * geo.total_p + gr.uoff + p]);
     const double2 t2 = cmulc(a2[m * geo.total_p + gr.uoff + p], cmul(sy, vh));
     rowacc[((size_t)n2 * nmbf + m) * geo.nbasis + j] = cadd(t1, t2);
