@@ -260,8 +260,17 @@ def main():
     npairs = len(wl.pairs)
     s = 16
     per_launch = {k: npairs / kernels[k]["launches_per_step"] for k in ("row_pass", "col_pass")}
+    # row pass inputs of one launch: G (3 arrays) plus the testing spectra
+    # (Mx, My) of the launch's distinct m and the reflected ones (Mx#, My#) of
+    # its distinct n, each read once
+    chunk = int(round(per_launch["row_pass"]))
+    plist = [tuple(p) for p in wl.pairs]
+    in_arrays = []
+    for c0 in range(0, npairs, chunk):
+        part = plist[c0:c0 + chunk]
+        in_arrays.append(3 + 2 * len({m for m, _ in part}) + 2 * len({q for _, q in part}))
     launch_bytes = {
-        "row_pass": (3 + 4 * wl.M) * n * 16 + (P + 1) * n * s * per_launch["row_pass"],
+        "row_pass": sum(in_arrays) / len(in_arrays) * n * 16 + (P + 1) * n * s * per_launch["row_pass"],
         "col_pass": (P + 1) * n * s * per_launch["col_pass"] + n * s * per_launch["col_pass"],
     }
     dom = max(("row_pass", "col_pass"), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])

@@ -163,6 +163,8 @@ struct cfft_plan_s {
   size_t ws_bytes = 0;
   void* ws2 = nullptr;
   size_t ws2_bytes = 0;
+  void* ws3 = nullptr;      // spectra scratch (gathered coefficients, per-row contractions)
+  size_t ws3_bytes = 0;
   // geometry cache (one basis set at a time)
   uint64_t geo_hash = 0;
   int geo_nbasis = 0;
@@ -407,6 +409,7 @@ void release_plan(cfft_plan_s* plan) {
   }
   if (plan->ws) (void)hipFree(plan->ws);
   if (plan->ws2) (void)hipFree(plan->ws2);
+  if (plan->ws3) (void)hipFree(plan->ws3);
   if (plan->flag_dev) (void)hipFree(plan->flag_dev);
   if (plan->flag_host) (void)hipHostFree(plan->flag_host);
   for (auto& v : plan->prof)
@@ -582,10 +585,14 @@ cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* ba
   hipStream_t s = (hipStream_t)stream;
   st = ensure_geometry(plan, gs, basis, nbasis, s);
   if (st != CFFT_OK) return st;
+  st = ensure_ws(&plan->ws3, &plan->ws3_bytes, sizeof(double2) * spectra_scratch_len(gs.y, plan->geo_dev, nmbf),
+                 "spectra scratch");
+  if (st != CFFT_OK) return st;
   hipError_t e;
   {
     ProfScope ps(plan, 1, s);
-    e = launch_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, (const double2*)q, nmbf, (double2*)spec, s);
+    e = launch_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, (const double2*)q, nmbf, (double2*)plan->ws3,
+                       (double2*)spec, s);
   }
   if (e != hipSuccess) return hip_fail(e, "mbf_spectra launch");
   return check_finite(plan, spec, (size_t)8 * nmbf * gs.x.n * gs.y.n, false, s);

@@ -157,13 +157,37 @@ template <typename V, int RHO> __device__ __forceinline__ void dft_small(V* y) {
   else dft8(y);
 }
 
+// Twiddles w(m) = exp(-2 pi i m / N) live in LDS as two short tables,
+// lo[j] = w(j) (j < 64) and hi[j] = w(64 j) (j < N/64), so that
+// w(m) = hi[m >> 6] lo[m & 63]: 64 + N/64 entries per block instead of N,
+// read through the LDS pipe instead of competing with the streaming global
+// loads and stores.
+template <int N> struct TwLds {
+  static constexpr int LO = N < 64 ? N : 64;
+  static constexpr int HI = N <= 64 ? 0 : N / 64;
+  static constexpr int LEN = LO + HI;
+};
+
+// Fill the LDS tables from the full global table w(0..N-1); all threads of
+// the block take part; a barrier must follow before the first use.
+template <typename V, int N>
+__device__ __forceinline__ void load_twiddles(V* ltw, const V* __restrict__ gtw, int tid, int nthreads) {
+  for (int i = tid; i < TwLds<N>::LEN; i += nthreads)
+    ltw[i] = i < TwLds<N>::LO ? gtw[i] : gtw[64 * (i - TwLds<N>::LO)];
+}
+
+template <typename V, int N> __device__ __forceinline__ V tw_at(const V* ltw, int m) {
+  if constexpr (N <= 64) return ltw[m];
+  else return cmul(ltw[TwLds<N>::LO + (m >> 6)], ltw[m & 63]);
+}
+
 // One Stockham stage of radix RHO on a length-N transform spread over
 // T = N/R threads, each holding R points at stride T (x[r] = data[t + T r]).
 // L is the length of the sub-transforms already done.  Non-final stages
 // exchange through `lds` (lds_len(N) entries, padded slots); the final stage leaves the outputs in
 // registers in the same stride-T order.
 template <typename V, int N, int R, int RHO, bool LAST>
-__device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* __restrict__ tw, int t, int L) {
+__device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* ltw, int t, int L) {
   constexpr int T = N / R;
   constexpr int BPT = R / RHO;
 #pragma unroll
@@ -176,7 +200,7 @@ __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* __res
     if (L > 1) {
       const int step = N / (L * RHO);
 #pragma unroll
-      for (int j = 1; j < RHO; ++j) y[j] = cmul(y[j], tw[j * k * step]);
+      for (int j = 1; j < RHO; ++j) y[j] = cmul(y[j], tw_at<V, N>(ltw, j * k * step));
     }
     dft_small<V, RHO>(y);
     if constexpr (LAST) {
@@ -201,37 +225,41 @@ __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* __res
 // multiple of 3, then radix-8 stages.  All threads of the block must call
 // it (it contains block barriers).
 template <typename V, int N, int R>
-__device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* __restrict__ tw, int t) {
+__device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* ltw, int t) {
   static_assert(R == 8 || R == 16, "8 or 16 points per thread");
+  // Keep the twiddle addressing inside the caller's term loop: without this
+  // the compiler hoists every stage's twiddle loads out of the loop and keeps
+  // them live across it, which costs ~60 VGPRs and halves occupancy.
+  asm volatile("" : "+v"(t));
   constexpr int LOG = ilog2c(N);
   constexpr int NR8 = LOG / 3;
   constexpr int REM = LOG % 3;
   int L = 1;
   if constexpr (REM == 1) {
-    stockham_stage<V, N, R, 2, NR8 == 0>(x, lds, tw, t, L);
+    stockham_stage<V, N, R, 2, NR8 == 0>(x, lds, ltw, t, L);
     L *= 2;
   } else if constexpr (REM == 2) {
-    stockham_stage<V, N, R, 4, NR8 == 0>(x, lds, tw, t, L);
+    stockham_stage<V, N, R, 4, NR8 == 0>(x, lds, ltw, t, L);
     L *= 4;
   }
   if constexpr (NR8 >= 1) {
     if constexpr (NR8 >= 2) {
 #pragma unroll
       for (int s = 0; s < NR8 - 1; ++s) {
-        stockham_stage<V, N, R, 8, false>(x, lds, tw, t, L);
+        stockham_stage<V, N, R, 8, false>(x, lds, ltw, t, L);
         L *= 8;
       }
     }
-    stockham_stage<V, N, R, 8, true>(x, lds, tw, t, L);
+    stockham_stage<V, N, R, 8, true>(x, lds, ltw, t, L);
   }
 }
 
 // Inverse (unnormalised) DFT: conj(DFT(conj x)).
 template <typename V, int N, int R>
-__device__ __forceinline__ void fft_inverse(V (&x)[R], V* lds, const V* __restrict__ tw, int t) {
+__device__ __forceinline__ void fft_inverse(V (&x)[R], V* lds, const V* ltw, int t) {
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = cconj(x[r]);
-  fft_forward<V, N, R>(x, lds, tw, t);
+  fft_forward<V, N, R>(x, lds, ltw, t);
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = cconj(x[r]);
 }

@@ -22,6 +22,19 @@
 #include "cfft_device.h"
 #include "cfft_internal.h"
 
+// Scheduling knobs (compile-time): minimum waves per SIMD requested from the
+// register allocator for the two passes (0 = compiler's choice), and the
+// widest FP64 column tile in bytes per row.
+#ifndef CFFT_ROW_MIN_WAVES
+#define CFFT_ROW_MIN_WAVES 0
+#endif
+#ifndef CFFT_COL_MIN_WAVES
+#define CFFT_COL_MIN_WAVES 0
+#endif
+#ifndef CFFT_COL_ROW_BYTES
+#define CFFT_COL_ROW_BYTES 64
+#endif
+
 namespace cfft {
 
 template <int N> struct RowCfg {
@@ -44,11 +57,17 @@ struct RowArgs {
 };
 
 template <typename V, int N>
+#if CFFT_ROW_MIN_WAVES > 0
+__global__ void __launch_bounds__(RowCfg<N>::THREADS, CFFT_ROW_MIN_WAVES) row_pass_kernel(RowArgs a) {
+#else
 __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a) {
+#endif
   using Cfg = RowCfg<N>;
   constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
   using Rl = typename real_of<V>::type;
   __shared__ V lds[ROWS * lds_len(N)];
+  __shared__ V ltw[TwLds<N>::LEN];
+  load_twiddles<V, N>(ltw, (const V*)a.tw, threadIdx.x, Cfg::THREADS);
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int pair = lid % a.npairs;
   const int rb = lid / a.npairs;
@@ -58,7 +77,6 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
   const bool valid = n2 < a.ny;
   const size_t plane = (size_t)a.nx * a.ny;
   const int m = a.pm[pair], n = a.pn[pair];
-  const V* tw = (const V*)a.tw;
   V* inter = (V*)a.inter;
 
   V f[R];
@@ -79,31 +97,31 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
     f[r] = from_d<V>(h);
   }
   double2 S[R];
-  double cf[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    S[r] = make_double2(0.0, 0.0);
-    cf[r] = 1.0;
-  }
+  for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
   V* my_lds = lds + grp * lds_len(N);
+  __syncthreads();   // twiddle tables ready
   for (int ao = 0; ao <= a.order; ++ao) {
     if (ao > 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int n1 = t + T * r;
         f[r] = cscale(f[r], (Rl)(a.gamma * (a.kx0 + n1 * a.dkx)));
-        cf[r] *= (a.x0 + n1 * a.ddx) * a.rinv[ao];
       }
     }
     V x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = f[r];
-    fft_forward<V, N, R>(x, my_lds, tw, t);
+    fft_forward<V, N, R>(x, my_lds, ltw, t);
     V* dst = inter + (((size_t)pair * (a.order + 1) + ao) * a.ny + (valid ? n2 : 0)) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+      // Dx(j1)^a / a!, rebuilt per term (cheaper than keeping it live)
+      const double dx = a.x0 + (t + T * r) * a.ddx;
+      double cf = 1.0;
+      for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
       const double2 xv = to_d(x[r]);
-      S[r] = make_double2(S[r].x + cf[r] * xv.x, S[r].y + cf[r] * xv.y);
+      S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
       if (valid) dst[t + T * r] = from_d<V>(S[r]);
     }
   }
@@ -132,11 +150,17 @@ template <int N, int C, int R> struct ColCfg {
 };
 
 template <typename V, int N, int C, int R>
+#if CFFT_COL_MIN_WAVES > 0
+__global__ void __launch_bounds__(C * (N / R), CFFT_COL_MIN_WAVES) col_pass_kernel(ColArgs a) {
+#else
 __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
+#endif
   using Cfg = ColCfg<N, C, R>;
   constexpr int T = Cfg::T, LDP = Cfg::LDP;
   using Rl = typename real_of<V>::type;
   __shared__ V lds[C * LDP];
+  __shared__ V ltw[TwLds<N>::LEN];
+  load_twiddles<V, N>(ltw, (const V*)a.tw, threadIdx.x, Cfg::THREADS);
   const int ntile = a.nx / C;
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = lid % ntile;
@@ -144,7 +168,6 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
   const int c = threadIdx.x % C;
   const int t = threadIdx.x / C;
   const int j1 = tile * C + c;
-  const V* tw = (const V*)a.tw;
   const size_t plane = (size_t)N * a.nx;
   const V* col0 = (const V*)a.inter + (size_t)pair * (a.order + 1) * plane + j1;
 
@@ -161,6 +184,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
     for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
   }
   V* my_lds = lds + c * LDP;
+  __syncthreads();   // twiddle tables ready
   for (int b = 0; b <= a.order; ++b) {
     V x[R];
 #pragma unroll
@@ -176,7 +200,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
 #pragma unroll
       for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
     }
-    fft_forward<V, N, R>(x, my_lds, tw, t);
+    fft_forward<V, N, R>(x, my_lds, ltw, t);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j2 = t + T * r;
@@ -204,7 +228,7 @@ __host__ __device__ constexpr int col_r(int) { return 8; }
 // LDS tile and 512 threads allow (1024-thread blocks would cap the kernel at
 // 128 VGPRs and spill).
 __host__ __device__ constexpr int col_tile_c(int ny, int bytes) {
-  int c = 128 / bytes;
+  int c = CFFT_COL_ROW_BYTES / bytes;
   const int r = col_r(bytes);
   while (c > 1 && (c * (lds_len(ny) + 2) * bytes > 81920 || c * (ny / r) > 512)) c /= 2;
   return c;
@@ -337,6 +361,8 @@ __global__ void __launch_bounds__(C * (N / 8)) adj_col_kernel(AdjColArgs a) {
   using Cfg = ColCfg<N, C, R>;
   constexpr int T = Cfg::T, LDP = Cfg::LDP;
   __shared__ double2 lds[C * LDP];
+  __shared__ double2 ltw[TwLds<N>::LEN];
+  load_twiddles<double2, N>(ltw, a.tw, threadIdx.x, Cfg::THREADS);
   const int ntile = a.nx / C;
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = lid % ntile;
@@ -359,6 +385,7 @@ __global__ void __launch_bounds__(C * (N / 8)) adj_col_kernel(AdjColArgs a) {
     pw[r] = 1.0;
   }
   double2* my_lds = lds + c * LDP;
+  __syncthreads();   // twiddle tables ready
   for (int b = 0; b <= a.order; ++b) {
     double2 x[R];
 #pragma unroll
@@ -367,7 +394,7 @@ __global__ void __launch_bounds__(C * (N / 8)) adj_col_kernel(AdjColArgs a) {
       if (b > 0) cf[r] *= (a.y0 + j2 * a.ddy) * a.rinv[b];
       x[r] = cscale(h0[r], cf[r]);
     }
-    fft_inverse<double2, N, R>(x, my_lds, a.tw, t);
+    fft_inverse<double2, N, R>(x, my_lds, ltw, t);
     double2* dst = a.inter + ((size_t)pair * (a.order + 1) + b) * plane + j1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -393,6 +420,8 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
   using Cfg = RowCfg<N>;
   constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
   __shared__ double2 lds[ROWS * lds_len(N)];
+  __shared__ double2 ltw[TwLds<N>::LEN];
+  load_twiddles<double2, N>(ltw, a.tw, threadIdx.x, Cfg::THREADS);
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int pair = lid % a.npairs;
   const int rb = lid / a.npairs;
@@ -409,6 +438,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
     pw[r] = 1.0;
   }
   double2* my_lds = lds + grp * lds_len(N);
+  __syncthreads();   // twiddle tables ready
   for (int ao = 0; ao <= a.order; ++ao) {
     const double2* src =
         a.inter + (((size_t)pair * (a.order + 1) + (a.order - ao)) * a.ny + (valid ? n2 : 0)) * N;
@@ -419,7 +449,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
       if (ao > 0) cf[r] *= (a.x0 + j1 * a.ddx) * a.rinv[ao];
       x[r] = valid ? cscale(src[j1], cf[r]) : make_double2(0.0, 0.0);
     }
-    fft_inverse<double2, N, R>(x, my_lds, a.tw, t);
+    fft_inverse<double2, N, R>(x, my_lds, ltw, t);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int n1 = t + T * r;

@@ -116,48 +116,82 @@ constexpr int kMaxGroups = 32;  // host refuses basis sets needing more
 constexpr int kMChunk = 4;
 constexpr int kPChunk = 8;
 
-// Block = (256 consecutive samples of one row n2).  Prologue: the per-row
-// contraction over y-centres, w[m][uoff+p] = SY_g sum_r conj(q) V_gr and
-// w#[m][uoff+p] = SY_g sum_r q V#_gr, from the tables into LDS.  Main part:
-// one sample per thread, M_m = sum_g SX_g sum_p U_gp w[m][p], with the U loads
-// of a chunk of kPChunk centres issued together.
-__global__ void __launch_bounds__(kSpecThreads)
-spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __restrict__ utab,
-               const double2* __restrict__ q, int nmbf, double2* __restrict__ spec) {
-  extern __shared__ double2 sh[];
-  double2* w = sh;                              // [nmbf][total_p]
-  double2* wh = sh + nmbf * geo.total_p;        // [nmbf][total_p]
-  __shared__ GeomGroup grp[kMaxGroups];
-  const int n2 = blockIdx.y;
-  const int n1 = blockIdx.x * blockDim.x + threadIdx.x;
+// Per-row contraction over y-centres, one thread per (n2, m, prow):
+//   w [n2][m][prow] = SY_g(n2) sum_r conj(q_m,j(g,p,r)) V_gr(n2)
+//   w#[n2][m][prow] = SY_g(n2) sum_r      q_m,j(g,p,r)  V#_gr(n2)
+// stored as wtab[n2][m][2][total_p].  The coefficients are first gathered
+// into the dense slot layout qd[m][slot] (0 for empty slots) so that the r
+// loop has no dependent index loads.
+__global__ void gather_q_kernel(GeomDevice geo, const double2* __restrict__ q, int nmbf, double2* __restrict__ qd) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nmbf * geo.total_idx) return;
+  const int m = e / geo.total_idx, li = e % geo.total_idx;
+  const int j = geo.index[li];
+  qd[e] = j < 0 ? make_double2(0.0, 0.0) : q[(size_t)m * geo.nbasis + j];
+}
+
+// One block per row n2: the row's V, V# and SY values are staged in LDS,
+// then each thread sums the entries (m, prow) it owns over the group's
+// y-centres, eight independent coefficient loads at a time.
+constexpr int kRowsThreads = 128;
+__global__ void __launch_bounds__(kRowsThreads)
+spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
+                    const double2* __restrict__ qd, int nmbf, double2* __restrict__ wtab) {
+  extern __shared__ double2 vs[];   // [2 total_r] V, V# interleaved by row, then [ngroups] SY
+  const int n2 = blockIdx.x;
   const double2* vtab = utab + vtab_offset(x.n, geo);
-  if (threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
+  const int nv = 2 * geo.total_r + geo.ngroups;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) vs[i] = vtab[(size_t)i * y.n + n2];
   __syncthreads();
-  const int nw = nmbf * geo.total_p;
-  for (int e = threadIdx.x; e < nw; e += blockDim.x) {
+  const int per_row = nmbf * geo.total_p;
+  double2* dst = wtab + (size_t)n2 * nmbf * 2 * geo.total_p;
+  for (int e = threadIdx.x; e < per_row; e += blockDim.x) {
     const int m = e / geo.total_p;
     const int prow = e % geo.total_p;
     int g = 0;
-    while (g + 1 < geo.ngroups && grp[g + 1].uoff <= prow) ++g;
-    const GeomGroup gr = grp[g];
+    while (g + 1 < geo.ngroups && geo.groups[g + 1].uoff <= prow) ++g;
+    const GeomGroup gr = geo.groups[g];
     const int p = prow - gr.uoff;
-    const double2 sy = vtab[(size_t)(2 * geo.total_r + g) * y.n + n2];
+    const double2* qrow = qd + (size_t)m * geo.total_idx + gr.ioff + (size_t)p * gr.nr;
     double2 acc = make_double2(0.0, 0.0), acch = make_double2(0.0, 0.0);
-    for (int r = 0; r < gr.nr; ++r) {
-      const int j = geo.index[gr.ioff + p * gr.nr + r];
-      if (j < 0) continue;
-      const double2 v = vtab[(size_t)(2 * (gr.yoff + r)) * y.n + n2];
-      const double2 vh = vtab[(size_t)(2 * (gr.yoff + r) + 1) * y.n + n2];
-      const double2 qq = q[(size_t)m * geo.nbasis + j];
-      acc = cadd(acc, cmulc(v, qq));      // conj(q) V
-      acch = cadd(acch, cmul(qq, vh));    // q V#
+    for (int r0 = 0; r0 < gr.nr; r0 += 8) {
+      double2 qq[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) qq[k] = r0 + k < gr.nr ? qrow[r0 + k] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (r0 + k < gr.nr) {
+          const int vr = gr.yoff + r0 + k;
+          acc = cadd(acc, cmulc(vs[2 * vr], qq[k]));       // conj(q) V
+          acch = cadd(acch, cmul(qq[k], vs[2 * vr + 1]));  // q V#
+        }
+      }
     }
-    w[e] = cmul(acc, sy);
-    wh[e] = cmul(acch, sy);
+    const double2 sy = vs[2 * geo.total_r + g];
+    dst[(size_t)m * 2 * geo.total_p + prow] = cmul(acc, sy);
+    dst[(size_t)m * 2 * geo.total_p + geo.total_p + prow] = cmul(acch, sy);
   }
+}
+
+// Block = 256 consecutive samples of one row n2, one sample per thread:
+//   M_m = sum_g SX_g sum_p U_gp w[m][p]   (and M# with U#, w#)
+// with the row's w loaded once into LDS and the U loads of a chunk of
+// kPChunk centres issued together.
+__global__ void __launch_bounds__(kSpecThreads)
+spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
+               const double2* __restrict__ wtab, int nmbf, double2* __restrict__ spec) {
+  extern __shared__ double2 sh[];   // [nmbf][2][total_p]
+  __shared__ GeomGroup grp[kMaxGroups];
+  const int n2 = blockIdx.y;
+  const int n1 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
+  const int nw = nmbf * 2 * geo.total_p;
+  const double2* src = wtab + (size_t)n2 * nw;
+  for (int e = threadIdx.x; e < nw; e += blockDim.x) sh[e] = src[e];
   __syncthreads();
   if (n1 >= x.n) return;
   const size_t plane = (size_t)x.n * y.n;
+  const int tp = geo.total_p;
   for (int m0 = 0; m0 < nmbf; m0 += kMChunk) {
     double2 acc[kMChunk][4];
 #pragma unroll
@@ -167,7 +201,7 @@ spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __re
     for (int g = 0; g < geo.ngroups; ++g) {
       const GeomGroup gr = grp[g];
       const int comp = is_ydir(gr.kind) ? 1 : 0;
-      const double2 sx = utab[(size_t)(2 * geo.total_p + g) * x.n + n1];
+      const double2 sx = utab[(size_t)(2 * tp + g) * x.n + n1];
       double2 sg[kMChunk], sgh[kMChunk];
 #pragma unroll
       for (int i = 0; i < kMChunk; ++i) sg[i] = sgh[i] = make_double2(0.0, 0.0);
@@ -186,8 +220,8 @@ spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __re
 #pragma unroll
             for (int i = 0; i < kMChunk; ++i) {
               if (m0 + i < nmbf) {
-                sg[i] = cadd(sg[i], cmul(u[k], w[(m0 + i) * geo.total_p + prow]));
-                sgh[i] = cadd(sgh[i], cmul(uh[k], wh[(m0 + i) * geo.total_p + prow]));
+                sg[i] = cadd(sg[i], cmul(u[k], sh[(m0 + i) * 2 * tp + prow]));
+                sgh[i] = cadd(sgh[i], cmul(uh[k], sh[(m0 + i) * 2 * tp + tp + prow]));
               }
             }
           }
@@ -209,11 +243,26 @@ spectra_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __re
   }
 }
 
-hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
-                          const double2* utab, const double2* q, int nmbf, double2* spec, hipStream_t s) {
+size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf) {
+  return (size_t)nmbf * geo.total_idx + (size_t)y.n * nmbf * 2 * geo.total_p;
+}
+
+hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo, const double2* utab,
+                          const double2* q, int nmbf, double2* scratch, double2* spec, hipStream_t s) {
+  (void)gamma;
+  double2* qd = scratch;
+  double2* wtab = scratch + (size_t)nmbf * geo.total_idx;
+  const int ng = nmbf * geo.total_idx;
+  hipLaunchKernelGGL(gather_q_kernel, dim3((ng + 255) / 256), dim3(256), 0, s, geo, q, nmbf, qd);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t vlds = sizeof(double2) * (size_t)(2 * geo.total_r + geo.ngroups);
+  hipLaunchKernelGGL(spectra_rows_kernel, dim3(y.n), dim3(kRowsThreads), vlds, s, x, y, geo, utab, qd, nmbf, wtab);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const size_t lds = sizeof(double2) * 2 * (size_t)nmbf * geo.total_p;
   dim3 grid((x.n + kSpecThreads - 1) / kSpecThreads, y.n);
-  hipLaunchKernelGGL(spectra_kernel, grid, dim3(kSpecThreads), lds, s, x, y, gamma, geo, utab, q, nmbf, spec);
+  hipLaunchKernelGGL(spectra_kernel, grid, dim3(kSpecThreads), lds, s, x, y, geo, utab, wtab, nmbf, spec);
   return hipGetLastError();
 }
 
