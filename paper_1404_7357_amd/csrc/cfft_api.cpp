@@ -175,7 +175,9 @@ struct cfft_plan_s {
   int* flag_host = nullptr;
   // instrumentation: recorded (start, stop) event pairs per kernel class
   bool profiling = false;
-  std::map<long long, long long> tuned;   // (grid, npairs) -> pair chunk
+  std::map<long long, std::pair<long long, int>> tuned;   // (grid, npairs) -> (pair chunk, lanes)
+  hipStream_t lane[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_row0 = nullptr, ev_join[2] = {nullptr, nullptr};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[kProfClasses];
 };
 
@@ -275,7 +277,10 @@ cfft_status_t ensure_geometry(cfft_plan_s* plan, GridState& gs, const cfft_basis
     GeomHost gh;
     if (!build_geometry(basis, nbasis, gh))
       return fail(CFFT_ERR_UNSUPPORTED, "basis set needs more than 32 shape groups");
-    if ((size_t)plan->max_mbf * gh.total_p * 2 * sizeof(double2) > 65536)
+    GeomDevice probe{};
+    probe.ngroups = (int)gh.groups.size();
+    probe.total_p = gh.total_p;
+    if (spectra_lds_bytes(probe, plan->max_mbf) > 65536)
       return fail(CFFT_ERR_UNSUPPORTED, "max_mbf * distinct x-centres (%d * %d) too large for the LDS tables",
                   plan->max_mbf, gh.total_p);
     hipError_t e = hipStreamSynchronize(s);
@@ -397,9 +402,27 @@ struct ProfScope {
   }
 };
 
+// Two plan-owned streams at default priority plus the fork/join events of the
+// two-lane schedule, created on first use.
+hipError_t ensure_lanes(cfft_plan_s* plan) {
+  if (plan->lane[0]) return hipSuccess;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&plan->lane[i], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_row0, hipEventDisableTiming);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&plan->ev_join[i], hipEventDisableTiming);
+  return e;
+}
+
 void release_plan(cfft_plan_s* plan) {
   (void)hipSetDevice(plan->device);
   (void)hipDeviceSynchronize();
+  for (int i = 0; i < 2; ++i)
+    if (plan->lane[i]) (void)hipStreamDestroy(plan->lane[i]);
+  if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+  if (plan->ev_row0) (void)hipEventDestroy(plan->ev_row0);
+  for (int i = 0; i < 2; ++i)
+    if (plan->ev_join[i]) (void)hipEventDestroy(plan->ev_join[i]);
   for (auto& g : plan->grids) {
     if (g.tw64x) (void)hipFree(g.tw64x);
     if (g.tw64y) (void)hipFree(g.tw64y);
@@ -628,46 +651,92 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
     pm[i] = pairs[2 * i];
     pn[i] = pairs[2 * i + 1];
   }
-  auto run_passes = [&](long long ck) -> hipError_t {
-    for (int p0 = 0; p0 < npairs; p0 += (int)ck) {
+  // Schedules: `ck` pairs per chunk; with two lanes, even chunks run on one
+  // plan-owned stream and odd chunks on the other, each with its own half of
+  // the workspace, so that one lane's column pass overlaps the other lane's
+  // row pass (the second lane starts once the first row pass is done).  The
+  // lanes fork from and join back into the caller's stream through events,
+  // which keeps the call capturable in a HIP graph.
+  auto run_passes = [&](long long ck, int lanes) -> hipError_t {
+    hipStream_t ls[2] = {s, s};
+    if (lanes == 2) {
+      hipError_t e = ensure_lanes(plan);
+      if (e != hipSuccess) return e;
+      ls[0] = plan->lane[0];
+      ls[1] = plan->lane[1];
+      e = hipEventRecord(plan->ev_fork, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ls[0], plan->ev_fork, 0);
+      if (e != hipSuccess) return e;
+    }
+    int chunk_id = 0;
+    for (int p0 = 0; p0 < npairs; p0 += (int)ck, ++chunk_id) {
       const int np = (int)std::min<long long>(ck, npairs - p0);
+      const int lane = lanes == 2 ? (chunk_id & 1) : 0;
+      hipStream_t st2 = ls[lane];
+      void* wsl = (char*)plan->ws + (size_t)lane * per_pair * (size_t)ck;
       hipError_t e;
       {
-        ProfScope ps(plan, 2, s);
-        e = launch_row_pass(pp, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np, plan->ws,
-                            twx, s);
+        ProfScope ps(plan, 2, st2);
+        e = launch_row_pass(pp, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np, wsl,
+                            twx, st2);
       }
       if (e != hipSuccess) return e;
-      {
-        ProfScope ps(plan, 3, s);
-        e = launch_col_pass(pp, plan->ws, np, (char*)z + (size_t)p0 * n * cbytes, twy, s);
+      if (lanes == 2 && chunk_id == 0) {
+        e = hipEventRecord(plan->ev_row0, st2);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ls[1], plan->ev_row0, 0);
+        if (e != hipSuccess) return e;
       }
+      {
+        ProfScope ps(plan, 3, st2);
+        e = launch_col_pass(pp, wsl, np, (char*)z + (size_t)p0 * n * cbytes, twy, st2);
+      }
+      if (e != hipSuccess) return e;
+    }
+    if (lanes == 2) {
+      hipError_t e = hipEventRecord(plan->ev_join[0], ls[0]);
+      if (e == hipSuccess) e = hipEventRecord(plan->ev_join[1], ls[1]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->ev_join[0], 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->ev_join[1], 0);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   };
-  // Pair-chunk schedule: smaller chunks keep the intermediates of a chunk
-  // resident in the memory-side cache between the two passes; with
-  // CFFT_FLAG_AUTOTUNE the first call per (grid, npairs) times the
-  // candidates (synchronously) and the plan keeps the fastest.
-  if ((plan->flags & CFFT_FLAG_AUTOTUNE) && forced <= 0) {
+  int lanes = 1;
+  const long long forced_lanes = env_ll("CFFT_LANES", 0);
+  if (forced_lanes == 1 || forced_lanes == 2) lanes = (int)forced_lanes;
+  auto lanes_ok = [&](long long ck) { return (npairs + ck - 1) / ck >= 2; };
+  // With CFFT_FLAG_AUTOTUNE the first call per (grid, npairs) times every
+  // (pair chunk, lanes) candidate (synchronously) and the plan keeps the
+  // fastest.  Smaller chunks keep a chunk's intermediates resident in the
+  // memory-side cache between the two passes.
+  if ((plan->flags & CFFT_FLAG_AUTOTUNE) && forced <= 0 && forced_lanes <= 0) {
     const long long key = (long long)grid * 1000003LL + npairs;
     auto it = plan->tuned.find(key);
     if (it == plan->tuned.end()) {
-      std::vector<long long> cands;
-      for (long long c : {chunk, 32LL, 16LL, 8LL, 4LL, 2LL, 1LL})
-        if (c <= chunk && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
+      std::vector<std::pair<long long, int>> cands;
+      for (long long c : {chunk, 32LL, 16LL, 8LL, 4LL, 2LL}) {
+        if (c > chunk) continue;
+        for (int l : {1, 2}) {
+          if (l == 2 && !lanes_ok(c)) continue;
+          if (l == 2 && per_pair * (size_t)c * 2 > plan->ws_bytes) {
+            st = ensure_ws(&plan->ws, &plan->ws_bytes, per_pair * (size_t)c * 2, "pass workspace");
+            if (st != CFFT_OK) return st;
+          }
+          if (std::find(cands.begin(), cands.end(), std::make_pair(c, l)) == cands.end()) cands.emplace_back(c, l);
+        }
+      }
       hipEvent_t ea, eb;
       hipError_t e = hipEventCreate(&ea);
       if (e == hipSuccess) e = hipEventCreate(&eb);
       if (e != hipSuccess) return hip_fail(e, "autotune events");
-      long long best = chunk;
+      std::pair<long long, int> best(chunk, 1);
       float best_ms = 3.4e38f;
-      for (long long c : cands) {
-        e = run_passes(c);  // warm-up
+      for (auto c : cands) {
+        e = run_passes(c.first, c.second);  // warm-up
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventRecord(ea, s);
-        if (e == hipSuccess) e = run_passes(c);
+        if (e == hipSuccess) e = run_passes(c.first, c.second);
+        if (e == hipSuccess) e = run_passes(c.first, c.second);
         if (e == hipSuccess) e = hipEventRecord(eb, s);
         if (e == hipSuccess) e = hipEventSynchronize(eb);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
@@ -682,10 +751,16 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
       if (e != hipSuccess) return hip_fail(e, "autotune");
       it = plan->tuned.emplace(key, best).first;
     }
-    chunk = it->second;
+    chunk = it->second.first;
+    lanes = it->second.second;
+  }
+  if (lanes == 2 && !lanes_ok(chunk)) lanes = 1;
+  if (lanes == 2) {
+    st = ensure_ws(&plan->ws, &plan->ws_bytes, per_pair * (size_t)chunk * 2, "pass workspace");
+    if (st != CFFT_OK) return st;
   }
   {
-    hipError_t e = run_passes(chunk);
+    hipError_t e = run_passes(chunk, lanes);
     if (e != hipSuccess) return hip_fail(e, "pass launch");
   }
   return check_finite(plan, z, 2 * n * (size_t)npairs, pp.precision != CFFT_FP64, s);

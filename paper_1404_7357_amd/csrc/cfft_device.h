@@ -31,6 +31,10 @@ template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
 }
 template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) { return mk(a.x * s, a.y * s); }
 template <typename V> __device__ __forceinline__ V cconj(V a) { return mk(a.x, -a.y); }
+// acc + a b with four fused multiply-adds
+template <typename V> __device__ __forceinline__ V cfma(V acc, V a, V b) {
+  return mk(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
+}
 // multiply by i, by -i
 template <typename V> __device__ __forceinline__ V cmul_i(V a) { return mk(-a.y, a.x); }
 template <typename V> __device__ __forceinline__ V cmul_mi(V a) { return mk(a.y, -a.x); }

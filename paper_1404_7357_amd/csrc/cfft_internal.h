@@ -64,6 +64,7 @@ hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const Geom
                           const double2* utab, const double2* q, int nmbf, double2* scratch,
                           double2* spec, hipStream_t s);
 size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf);
+size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf);
 
 // Row + column passes for one chunk of <= kMaxPairsPerLaunch pairs.
 hipError_t launch_row_pass(const PassParams& p, const double2* g, const double2* spec,

@@ -173,74 +173,93 @@ spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ 
   }
 }
 
-// Block = 256 consecutive samples of one row n2, one sample per thread:
-//   M_m = sum_g SX_g sum_p U_gp w[m][p]   (and M# with U#, w#)
-// with the row's w loaded once into LDS and the U loads of a chunk of
-// kPChunk centres issued together.
+// Block = 256 consecutive samples of one row n2 and one variant v (blockIdx.z:
+// 0 = testing spectra M with U and w, 1 = reflected spectra M# with U# and w#),
+// one sample per thread:  M_m = sum_g SX_g sum_p U_gp w[m][p].
+// The row's w table is copied to LDS zero-padded to whole chunks of kPChunk
+// centres per group and to a multiple of kMChunk MBFs, so the unrolled inner
+// loop has no bounds tests; padded entries multiply a clamped U by zero.
 __global__ void __launch_bounds__(kSpecThreads)
 spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
                const double2* __restrict__ wtab, int nmbf, double2* __restrict__ spec) {
-  extern __shared__ double2 sh[];   // [nmbf][2][total_p]
+  extern __shared__ double2 sh[];   // [mpad][ppad]
   __shared__ GeomGroup grp[kMaxGroups];
+  __shared__ int gpad[kMaxGroups + 1];   // padded offsets of each group's centres
   const int n2 = blockIdx.y;
+  const int v = blockIdx.z;
   const int n1 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tp = geo.total_p;
   if (threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
-  const int nw = nmbf * 2 * geo.total_p;
-  const double2* src = wtab + (size_t)n2 * nw;
-  for (int e = threadIdx.x; e < nw; e += blockDim.x) sh[e] = src[e];
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int g = 0; g < geo.ngroups; ++g) {
+      gpad[g] = acc;
+      acc += (geo.groups[g].np + kPChunk - 1) / kPChunk * kPChunk;
+    }
+    gpad[geo.ngroups] = acc;
+  }
+  __syncthreads();
+  const int ppad = gpad[geo.ngroups];
+  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
+  const double2* src = wtab + (size_t)n2 * nmbf * 2 * tp + (size_t)v * tp;
+  for (int e = threadIdx.x; e < mpad * ppad; e += blockDim.x) {
+    const int m = e / ppad;
+    const int pp = e % ppad;
+    int g = 0;
+    while (g + 1 < geo.ngroups && gpad[g + 1] <= pp) ++g;
+    const int p = pp - gpad[g];
+    double2 val = make_double2(0.0, 0.0);
+    if (m < nmbf && p < grp[g].np) val = src[(size_t)m * 2 * tp + grp[g].uoff + p];
+    sh[e] = val;
+  }
   __syncthreads();
   if (n1 >= x.n) return;
   const size_t plane = (size_t)x.n * y.n;
-  const int tp = geo.total_p;
-  for (int m0 = 0; m0 < nmbf; m0 += kMChunk) {
-    double2 acc[kMChunk][4];
+  const double2* ub = utab + n1;
+  const size_t rs = (size_t)x.n;
+  for (int m0 = 0; m0 < mpad; m0 += kMChunk) {
+    double2 acc[kMChunk][2];
 #pragma unroll
-    for (int i = 0; i < kMChunk; ++i)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[i][c] = make_double2(0.0, 0.0);
+    for (int i = 0; i < kMChunk; ++i) acc[i][0] = acc[i][1] = make_double2(0.0, 0.0);
     for (int g = 0; g < geo.ngroups; ++g) {
       const GeomGroup gr = grp[g];
       const int comp = is_ydir(gr.kind) ? 1 : 0;
-      const double2 sx = utab[(size_t)(2 * tp + g) * x.n + n1];
-      double2 sg[kMChunk], sgh[kMChunk];
+      const double2 sx = ub[(size_t)(2 * tp + g) * rs];
+      double2 sg[kMChunk];
 #pragma unroll
-      for (int i = 0; i < kMChunk; ++i) sg[i] = sgh[i] = make_double2(0.0, 0.0);
-      for (int p0 = 0; p0 < gr.np; p0 += kPChunk) {
-        double2 u[kPChunk], uh[kPChunk];
+      for (int i = 0; i < kMChunk; ++i) sg[i] = make_double2(0.0, 0.0);
+      const int pend = gpad[g + 1] - gpad[g];
+      for (int p0 = 0; p0 < pend; p0 += kPChunk) {
+        double2 u[kPChunk];
 #pragma unroll
         for (int k = 0; k < kPChunk; ++k) {
-          const int prow = gr.uoff + (p0 + k < gr.np ? p0 + k : gr.np - 1);
-          u[k] = utab[(size_t)(2 * prow) * x.n + n1];
-          uh[k] = utab[(size_t)(2 * prow + 1) * x.n + n1];
+          const int prow = gr.uoff + min(p0 + k, gr.np - 1);
+          u[k] = ub[(size_t)(2 * prow + v) * rs];
         }
+        const double2* wp = sh + gpad[g] + p0;
 #pragma unroll
         for (int k = 0; k < kPChunk; ++k) {
-          if (p0 + k < gr.np) {
-            const int prow = gr.uoff + p0 + k;
 #pragma unroll
-            for (int i = 0; i < kMChunk; ++i) {
-              if (m0 + i < nmbf) {
-                sg[i] = cadd(sg[i], cmul(u[k], sh[(m0 + i) * 2 * tp + prow]));
-                sgh[i] = cadd(sgh[i], cmul(uh[k], sh[(m0 + i) * 2 * tp + tp + prow]));
-              }
-            }
-          }
+          for (int i = 0; i < kMChunk; ++i) sg[i] = cfma(sg[i], u[k], wp[(m0 + i) * ppad + k]);
         }
       }
 #pragma unroll
-      for (int i = 0; i < kMChunk; ++i) {
-        acc[i][comp] = cadd(acc[i][comp], cmul(sg[i], sx));
-        acc[i][2 + comp] = cadd(acc[i][2 + comp], cmul(sgh[i], sx));
-      }
+      for (int i = 0; i < kMChunk; ++i) acc[i][comp] = cfma(acc[i][comp], sg[i], sx);
     }
 #pragma unroll
     for (int i = 0; i < kMChunk; ++i) {
       if (m0 + i < nmbf) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) spec[((size_t)(m0 + i) * 4 + c) * plane + (size_t)n2 * x.n + n1] = acc[i][c];
+        for (int c = 0; c < 2; ++c)
+          spec[((size_t)(m0 + i) * 4 + 2 * v + c) * plane + (size_t)n2 * x.n + n1] = acc[i][c];
       }
     }
   }
+}
+
+size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf) {
+  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
+  return sizeof(double2) * (size_t)mpad * (geo.total_p + geo.ngroups * (kPChunk - 1));
 }
 
 size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf) {
@@ -260,8 +279,11 @@ hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const Geom
   hipLaunchKernelGGL(spectra_rows_kernel, dim3(y.n), dim3(kRowsThreads), vlds, s, x, y, geo, utab, qd, nmbf, wtab);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = sizeof(double2) * 2 * (size_t)nmbf * geo.total_p;
-  dim3 grid((x.n + kSpecThreads - 1) / kSpecThreads, y.n);
+  // upper bound of the padded centre count (each group padded to kPChunk)
+  const int ppad = geo.total_p + geo.ngroups * (kPChunk - 1);
+  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
+  const size_t lds = sizeof(double2) * (size_t)mpad * ppad;
+  dim3 grid((x.n + kSpecThreads - 1) / kSpecThreads, y.n, 2);
   hipLaunchKernelGGL(spectra_kernel, grid, dim3(kSpecThreads), lds, s, x, y, geo, utab, wtab, nmbf, spec);
   return hipGetLastError();
 }
