@@ -19,6 +19,10 @@
 // the Appendix scale and writes the table through an LDS transpose.
 // The FFT precision is FP64 (CFFT_FP64) or FP32 (CFFT_MIXED); every
 // recombination weight and accumulator is FP64.
+#include <algorithm>
+#include <map>
+#include <vector>
+
 #include "cfft_device.h"
 #include "cfft_internal.h"
 
@@ -123,6 +127,110 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
       if (valid) dst[t + T * r] = from_d<V>(S[r]);
+    }
+  }
+}
+
+// Grouped row pass (N <= 1024): one block per (row, group of up to NPW pairs
+// sharing the testing MBF m), one transform of T = N/8 threads per pair.  The
+// block first forms, once for all its pairs,
+//   A_x = s(n1) (Mx_m Gxx + My_m Gxy),  A_y = s(n1) (Mx_m Gxy + My_m Gyy)
+// in LDS (FP64); each transform then needs only the reflected spectra of its
+// own basis MBF n, H = A_x Mx#_n + A_y My#_n.  That reads (5 + 2 NPW)/NPW
+// input arrays per pair instead of 7.
+struct RowGArgs {
+  const double2* g;
+  const double2* spec;
+  void* inter;
+  const void* tw;
+  int nx, ny, order, ngroups;
+  double kx0, dkx, x0, ddx, gamma;
+  double rinv[kMaxOrder + 1];
+  int gm[kMaxPairsPerLaunch];      // testing MBF of each group
+  int gfirst[kMaxPairsPerLaunch];  // first slot of the group in gpair
+  int gcnt[kMaxPairsPerLaunch];    // pairs in the group (<= NPW)
+  int gpair[kMaxPairsPerLaunch];   // pair index (position in the launch) per slot
+  int pn[kMaxPairsPerLaunch];      // basis MBF per pair index
+};
+
+template <int N, int NPW> struct RowGCfg {
+  static constexpr int R = 8;
+  static constexpr int T = N / R;
+  static constexpr int THREADS = NPW * T;
+};
+
+template <typename V, int N, int NPW>
+__global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArgs a) {
+  using Cfg = RowGCfg<N, NPW>;
+  constexpr int T = Cfg::T, R = Cfg::R;
+  using Rl = typename real_of<V>::type;
+  __shared__ double2 ax[N], ay[N];
+  __shared__ V lds[NPW * lds_len(N)];
+  __shared__ V ltw[TwLds<N>::LEN];
+  load_twiddles<V, N>(ltw, (const V*)a.tw, threadIdx.x, Cfg::THREADS);
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int grp = lid % a.ngroups;
+  const int n2 = lid / a.ngroups;
+  const int w = threadIdx.x / T;
+  const int t = threadIdx.x % T;
+  const size_t plane = (size_t)a.nx * a.ny;
+  const int m = a.gm[grp];
+  const size_t row = (size_t)n2 * N;
+  for (int i = threadIdx.x; i < N; i += Cfg::THREADS) {
+    const double2 gxx = a.g[row + i], gxy = a.g[plane + row + i], gyy = a.g[2 * plane + row + i];
+    const double2 mx = a.spec[((size_t)m * 4 + 0) * plane + row + i];
+    const double2 my = a.spec[((size_t)m * 4 + 1) * plane + row + i];
+    double2 vx = cfma(cmul(mx, gxx), my, gxy);
+    double2 vy = cfma(cmul(mx, gxy), my, gyy);
+    if (i & 1) {
+      vx = make_double2(-vx.x, -vx.y);
+      vy = make_double2(-vy.x, -vy.y);
+    }
+    ax[i] = vx;
+    ay[i] = vy;
+  }
+  __syncthreads();   // A tables and twiddle tables ready
+  const bool active = w < a.gcnt[grp];
+  const int pair = active ? a.gpair[a.gfirst[grp] + w] : 0;
+  const int n = a.pn[pair];
+  V f[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int n1 = t + T * r;
+    double2 h = make_double2(0.0, 0.0);
+    if (active) {
+      const double2 mxh = a.spec[((size_t)n * 4 + 2) * plane + row + n1];
+      const double2 myh = a.spec[((size_t)n * 4 + 3) * plane + row + n1];
+      h = cfma(cmul(ax[n1], mxh), ay[n1], myh);
+    }
+    f[r] = from_d<V>(h);
+  }
+  double2 S[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
+  V* my_lds = lds + w * lds_len(N);
+  V* inter = (V*)a.inter;
+  for (int ao = 0; ao <= a.order; ++ao) {
+    if (ao > 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int n1 = t + T * r;
+        f[r] = cscale(f[r], (Rl)(a.gamma * (a.kx0 + n1 * a.dkx)));
+      }
+    }
+    V x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = f[r];
+    fft_forward<V, N, R>(x, my_lds, ltw, t);
+    V* dst = inter + (((size_t)pair * (a.order + 1) + ao) * a.ny + n2) * N;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double dx = a.x0 + (t + T * r) * a.ddx;
+      double cf = 1.0;
+      for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
+      const double2 xv = to_d(x[r]);
+      S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
+      if (active) dst[t + T * r] = from_d<V>(S[r]);
     }
   }
 }
@@ -275,8 +383,66 @@ static hipError_t col_launch(const ColArgs& args, hipStream_t s) {
     default: return hipErrorInvalidValue;   \
   }
 
-template <int N> static hipError_t row_fp64(const RowArgs& a, hipStream_t s) { return row_launch<double2, N>(a, s); }
-template <int N> static hipError_t row_fp32(const RowArgs& a, hipStream_t s) { return row_launch<float2, N>(a, s); }
+// Grouped launch: pairs are grouped by testing MBF into groups of <= NPW
+// (4 when every MBF's pair count is a multiple of 4, else 2).
+template <typename V, int N>
+static hipError_t rowg_launch(const RowArgs& ra, hipStream_t s) {
+  RowGArgs a;
+  a.g = ra.g;
+  a.spec = ra.spec;
+  a.inter = ra.inter;
+  a.tw = ra.tw;
+  a.nx = ra.nx;
+  a.ny = ra.ny;
+  a.order = ra.order;
+  a.kx0 = ra.kx0;
+  a.dkx = ra.dkx;
+  a.x0 = ra.x0;
+  a.ddx = ra.ddx;
+  a.gamma = ra.gamma;
+  for (int i = 0; i <= kMaxOrder; ++i) a.rinv[i] = ra.rinv[i];
+  for (int i = 0; i < kMaxPairsPerLaunch; ++i) a.pn[i] = ra.pn[i];
+  // pair indices per testing MBF, in list order
+  std::map<int, std::vector<int>> by_m;
+  std::vector<int> order_m;
+  for (int i = 0; i < ra.npairs; ++i) {
+    if (!by_m.count(ra.pm[i])) order_m.push_back(ra.pm[i]);
+    by_m[ra.pm[i]].push_back(i);
+  }
+  bool all4 = true;
+  for (auto& kv : by_m) all4 = all4 && (kv.second.size() % 4 == 0);
+  const int npw = all4 ? 4 : 2;
+  int ng = 0, slot = 0;
+  for (int m : order_m) {
+    const auto& v = by_m[m];
+    for (size_t j = 0; j < v.size(); j += npw) {
+      a.gm[ng] = m;
+      a.gfirst[ng] = slot;
+      a.gcnt[ng] = (int)std::min<size_t>(npw, v.size() - j);
+      for (int k = 0; k < a.gcnt[ng]; ++k) a.gpair[slot++] = v[j + k];
+      ++ng;
+    }
+  }
+  for (int i = ng; i < kMaxPairsPerLaunch; ++i) a.gm[i] = a.gfirst[i] = a.gcnt[i] = 0;
+  for (int i = slot; i < kMaxPairsPerLaunch; ++i) a.gpair[i] = 0;
+  a.ngroups = ng;
+  const int nblk = ng * ra.ny;
+  if (npw == 4) {
+    hipLaunchKernelGGL((row_pass_grouped_kernel<V, N, 4>), dim3(nblk), dim3(RowGCfg<N, 4>::THREADS), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((row_pass_grouped_kernel<V, N, 2>), dim3(nblk), dim3(RowGCfg<N, 2>::THREADS), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <int N> static hipError_t row_fp64(const RowArgs& a, hipStream_t s) {
+  if constexpr (N >= 128 && N <= 1024) return rowg_launch<double2, N>(a, s);
+  else return row_launch<double2, N>(a, s);
+}
+template <int N> static hipError_t row_fp32(const RowArgs& a, hipStream_t s) {
+  if constexpr (N >= 128 && N <= 1024) return rowg_launch<float2, N>(a, s);
+  else return row_launch<float2, N>(a, s);
+}
 template <int N> static hipError_t col_fp64(const ColArgs& a, hipStream_t s) { return col_launch<double2, N>(a, s); }
 template <int N> static hipError_t col_fp32(const ColArgs& a, hipStream_t s) { return col_launch<float2, N>(a, s); }
 
