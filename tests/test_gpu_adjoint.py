@@ -101,3 +101,50 @@ def test_backward_many_pairs_chunked(monkeypatch):
     assert abs(full[1] - chunked[1]) < 1e-12 * abs(full[1])
     assert abs(full[2] - chunked[2]) < 1e-12 * abs(full[2])
     assert np.abs(full[3] - chunked[3]).max() < 1e-12 * np.abs(full[3]).max()
+
+
+def test_full_size_gradient_vs_central_differences():
+    """Differentiation workload at full size (1024^2, 16 pairs, 4096 lookups):
+    adjoint vs central differences of the GPU FP64 forward (relative 1e-6)."""
+    _say("adjoint full size 1024^2")
+    from paper_1404_7357_amd import LookupFunction, TableFunction, Tabulator
+    from workloads import c5_gradient
+    wl = c5_gradient()
+    gd, sub = wl.grids[0], wl.substrates[0]
+    tab = Tabulator(gd, wl.basis, max_mbf=wl.M)
+    pairs = [tuple(int(v) for v in p) for p in wl.pairs]
+    pts = torch.tensor(wl.queries, device="cuda")
+    # target: the table at eps_r 2.3 and perturbed coefficients, through the same path
+    with torch.no_grad():
+        zt = LookupFunction.apply(
+            TableFunction.apply(torch.tensor(wl.target_eps_r, dtype=torch.float64, device="cuda"),
+                                torch.tensor(sub.h, dtype=torch.float64, device="cuda"),
+                                torch.tensor(wl.target_q, device="cuda"), tab, sub.tan_delta, pairs, 0),
+            pts, tab, 0)
+
+    def loss_of(e, h, q, grad):
+        ee = torch.tensor(e, dtype=torch.float64, device="cuda", requires_grad=grad)
+        hh = torch.tensor(h, dtype=torch.float64, device="cuda", requires_grad=grad)
+        qq = torch.tensor(q, device="cuda", requires_grad=grad)
+        v = LookupFunction.apply(TableFunction.apply(ee, hh, qq, tab, sub.tan_delta, pairs, 0), pts, tab, 0)
+        loss = (v - zt).abs().pow(2).sum()
+        if not grad:
+            return float(loss.item())
+        loss.backward()
+        return float(loss.item()), float(ee.grad.item()), float(hh.grad.item()), qq.grad.cpu().numpy()
+
+    _, de, dh, dq = loss_of(sub.eps_r, sub.h, wl.q, True)
+    step = 1e-6
+    fd_e = (loss_of(sub.eps_r + step, sub.h, wl.q, False) - loss_of(sub.eps_r - step, sub.h, wl.q, False)) / (2 * step)
+    fd_h = (loss_of(sub.eps_r, sub.h + step, wl.q, False) - loss_of(sub.eps_r, sub.h - step, wl.q, False)) / (2 * step)
+    assert abs(de - fd_e) < 1e-6 * abs(fd_e), (de, fd_e)
+    assert abs(dh - fd_h) < 1e-6 * abs(fd_h), (dh, fd_h)
+    rng = np.random.default_rng(17)
+    for _ in range(3):
+        m, j = int(rng.integers(wl.M)), int(rng.integers(wl.B))
+        d = np.zeros_like(wl.q)
+        d[m, j] = step
+        fr = (loss_of(sub.eps_r, sub.h, wl.q + d, False) - loss_of(sub.eps_r, sub.h, wl.q - d, False)) / (2 * step)
+        fi = (loss_of(sub.eps_r, sub.h, wl.q + 1j * d, False) - loss_of(sub.eps_r, sub.h, wl.q - 1j * d, False)) / (2 * step)
+        assert abs(dq[m, j] - (fr + 1j * fi)) < 1e-6 * np.abs(dq).max(), (m, j)
+    tab.close()

@@ -154,3 +154,25 @@ def test_large_table_sampled(prec):
     tol = 1e-10 if prec == FP64 else 2e-4
     print(f"[gpu-case] c4 table prec={prec} err={err:.3e}", flush=True)
     assert err < tol, err
+
+
+def test_large_lookup_1e5_points():
+    """Bilinear lookup of 36 tables of 4096^2 (complex64) at the 10^5 query points of
+    the large workload, against the oracle's bilinear interpolation."""
+    from paper_1404_7357_amd import Tabulator
+    wl = c4_large()
+    gd = wl.grids[0]
+    _say("c4 lookup 1e5 points")
+    tab = Tabulator(gd, rooftop_lattice(1, 1), max_mbf=6)
+    z = torch.complex(torch.randn((36, gd.ny, gd.nx), device="cuda", dtype=torch.float32,
+                                  generator=torch.Generator(device="cuda").manual_seed(5)),
+                      torch.randn((36, gd.ny, gd.nx), device="cuda", dtype=torch.float32,
+                                  generator=torch.Generator(device="cuda").manual_seed(6)))
+    pts = torch.tensor(wl.queries, device="cuda")
+    out = tab.lookup(z, pts).cpu().numpy()
+    sel = [0, 17, 35]
+    zc = z[sel].cpu().numpy().astype(np.complex128)
+    tab.close()
+    ref = co.bilinear_lookup(gd, zc, wl.queries)
+    assert np.abs(out[sel] - ref).max() < 1e-12 * np.abs(ref).max()
+    assert np.isfinite(out).all()
