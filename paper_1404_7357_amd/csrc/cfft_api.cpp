@@ -76,7 +76,7 @@ struct GeomHost {
   std::vector<GeomGroup> groups;
   std::vector<double> xs, ys;
   std::vector<int> index;
-  int total_p = 0, total_r = 0, total_idx = 0;
+  int total_p = 0, total_r = 0, total_idx = 0, ppad = 0;
 };
 
 // Group bases by (kind, a, b); inside a group place each basis on the grid of
@@ -109,6 +109,7 @@ bool build_geometry(const cfft_basis_t* basis, int nb, GeomHost& out) {
       g.yoff = (int)out.ys.size();
       g.ioff = (int)out.index.size();
       g.uoff = out.total_p;
+      g.poff = out.ppad;
       std::vector<int> idx((size_t)g.np * g.nr, -1);
       for (int j : mem) {
         const int p = (int)(std::lower_bound(xs.begin(), xs.end(), basis[j].cx) - xs.begin());
@@ -121,6 +122,7 @@ bool build_geometry(const cfft_basis_t* basis, int nb, GeomHost& out) {
       out.ys.insert(out.ys.end(), ys.begin(), ys.end());
       out.index.insert(out.index.end(), idx.begin(), idx.end());
       out.total_p += g.np;
+      out.ppad += (g.np + kSpecPChunk - 1) / kSpecPChunk * kSpecPChunk;
       out.total_r += g.nr;
       out.total_idx += g.np * g.nr;
       out.groups.push_back(g);
@@ -163,7 +165,7 @@ struct cfft_plan_s {
   size_t ws_bytes = 0;
   void* ws2 = nullptr;
   size_t ws2_bytes = 0;
-  void* ws3 = nullptr;      // spectra scratch (gathered coefficients, per-row contractions)
+  void* ws3 = nullptr;      // spectra scratch (per-row contractions over y-centres)
   size_t ws3_bytes = 0;
   // geometry cache (one basis set at a time)
   uint64_t geo_hash = 0;
@@ -279,10 +281,9 @@ cfft_status_t ensure_geometry(cfft_plan_s* plan, GridState& gs, const cfft_basis
       return fail(CFFT_ERR_UNSUPPORTED, "basis set needs more than 32 shape groups");
     GeomDevice probe{};
     probe.ngroups = (int)gh.groups.size();
-    probe.total_p = gh.total_p;
+    probe.total_r = gh.total_r;
     if (spectra_lds_bytes(probe, plan->max_mbf) > 65536)
-      return fail(CFFT_ERR_UNSUPPORTED, "max_mbf * distinct x-centres (%d * %d) too large for the LDS tables",
-                  plan->max_mbf, gh.total_p);
+      return fail(CFFT_ERR_UNSUPPORTED, "%d distinct y-centres: too many for the per-row LDS tables", gh.total_r);
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "synchronise before geometry upload");
     free_geometry(plan);
@@ -301,6 +302,7 @@ cfft_status_t ensure_geometry(cfft_plan_s* plan, GridState& gs, const cfft_basis
     gd.total_p = gh.total_p;
     gd.total_r = gh.total_r;
     gd.total_idx = gh.total_idx;
+    gd.ppad = gh.ppad;
     gd.groups = (GeomGroup*)base;
     gd.xs = (double*)(base + al(bg));
     gd.ys = (double*)(base + al(bg) + al(bx));
@@ -834,7 +836,8 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
   const long long forced = env_ll("CFFT_PAIR_CHUNK", 0);
   if (forced > 0) chunk = std::min<long long>(chunk, forced);
-  const int green_blocks = 1024;
+  const GreenParams gp{gs.x, gs.y, gs.d.gamma, gs.d.k0, eps_r, tan_delta, h};
+  const int green_blocks = std::min(1024, (green_threads(gp) + 255) / 256);
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   const size_t b_gg = al(3 * n * 16), b_gs = al((size_t)nmbf * 4 * n * 16);
   const size_t b_row = al(adj_spectra_scratch(gs.y, plan->geo_dev, nmbf));
@@ -873,7 +876,6 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
     }
     if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
   }
-  GreenParams gp{gs.x, gs.y, gs.d.gamma, gs.d.k0, eps_r, tan_delta, h};
   hipError_t e;
   {
     ProfScope ps(plan, 8, s);

@@ -185,12 +185,27 @@ template <typename V, int N> __device__ __forceinline__ V tw_at(const V* ltw, in
   else return cmul(ltw[TwLds<N>::LO + (m >> 6)], ltw[m & 63]);
 }
 
+// Barrier between the LDS writes and reads of one exchange.  When every
+// thread of a transform sits in one wave (WAVE), no other wave touches its
+// LDS region and a wave's LDS instructions execute in issue order, so it is
+// enough to keep the compiler from moving LDS accesses across this point;
+// otherwise the whole block synchronises.
+template <bool WAVE> __device__ __forceinline__ void exchange_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage of radix RHO on a length-N transform spread over
 // T = N/R threads, each holding R points at stride T (x[r] = data[t + T r]).
 // L is the length of the sub-transforms already done.  Non-final stages
 // exchange through `lds` (lds_len(N) entries, padded slots); the final stage leaves the outputs in
 // registers in the same stride-T order.
-template <typename V, int N, int R, int RHO, bool LAST>
+template <typename V, int N, int R, int RHO, bool LAST, bool WAVE>
 __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* ltw, int t, int L) {
   constexpr int T = N / R;
   constexpr int BPT = R / RHO;
@@ -203,8 +218,30 @@ __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* ltw, 
     for (int j = 0; j < RHO; ++j) y[j] = x[mb + j * BPT];
     if (L > 1) {
       const int step = N / (L * RHO);
+      if constexpr (RHO == 8) {
+        // w^j for j = 1..7 from one table lookup w = w(k step): products of
+        // at most three factors after the lookup (w^2 = w w, w^3 = w^2 w,
+        // w^4 = w^2 w^2, w^5 = w^4 w, w^6 = w^3 w^3, w^7 = w^4 w^3), which
+        // replaces six LDS lookups per stage with the same number of complex
+        // products.  k step < N/8, so for N <= 512 the lookup is lo[] alone.
+        const int m = k * step;
+        V w1;
+        if constexpr (N / RHO <= 64) w1 = ltw[m];
+        else w1 = tw_at<V, N>(ltw, m);
+        const V w2 = cmul(w1, w1);
+        const V w4 = cmul(w2, w2);
+        const V w3 = cmul(w2, w1);
+        y[1] = cmul(y[1], w1);
+        y[2] = cmul(y[2], w2);
+        y[5] = cmul(y[5], cmul(w4, w1));
+        y[4] = cmul(y[4], w4);
+        y[3] = cmul(y[3], w3);
+        y[6] = cmul(y[6], cmul(w3, w3));
+        y[7] = cmul(y[7], cmul(w4, w3));
+      } else {
 #pragma unroll
-      for (int j = 1; j < RHO; ++j) y[j] = cmul(y[j], tw_at<V, N>(ltw, j * k * step));
+        for (int j = 1; j < RHO; ++j) y[j] = cmul(y[j], tw_at<V, N>(ltw, j * k * step));
+      }
     }
     dft_small<V, RHO>(y);
     if constexpr (LAST) {
@@ -217,20 +254,22 @@ __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* ltw, 
     }
   }
   if constexpr (!LAST) {
-    __syncthreads();
+    exchange_sync<WAVE>();
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = lds[lds_slot(t + T * r)];
-    __syncthreads();
+    exchange_sync<WAVE>();
   }
 }
 
 // Forward DFT X[j] = sum_n x[n] exp(-2 pi i n j / N), N = 2^m, 8 <= N.
 // Radices: one leading radix-2 or radix-4 stage when log2 N is not a
 // multiple of 3, then radix-8 stages.  All threads of the block must call
-// it (it contains block barriers).
-template <typename V, int N, int R>
+// it (it contains block barriers), unless WAVE: then the N/R threads of each
+// transform must be lanes of one wave, and only they synchronise.
+template <typename V, int N, int R, bool WAVE = false>
 __device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* ltw, int t) {
   static_assert(R == 8 || R == 16, "8 or 16 points per thread");
+  static_assert(!WAVE || N / R <= 64, "a wave-local transform needs at most 64 threads");
   // Keep the twiddle addressing inside the caller's term loop: without this
   // the compiler hoists every stage's twiddle loads out of the loop and keeps
   // them live across it, which costs ~60 VGPRs and halves occupancy.
@@ -240,30 +279,30 @@ __device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* ltw, int
   constexpr int REM = LOG % 3;
   int L = 1;
   if constexpr (REM == 1) {
-    stockham_stage<V, N, R, 2, NR8 == 0>(x, lds, ltw, t, L);
+    stockham_stage<V, N, R, 2, NR8 == 0, WAVE>(x, lds, ltw, t, L);
     L *= 2;
   } else if constexpr (REM == 2) {
-    stockham_stage<V, N, R, 4, NR8 == 0>(x, lds, ltw, t, L);
+    stockham_stage<V, N, R, 4, NR8 == 0, WAVE>(x, lds, ltw, t, L);
     L *= 4;
   }
   if constexpr (NR8 >= 1) {
     if constexpr (NR8 >= 2) {
 #pragma unroll
       for (int s = 0; s < NR8 - 1; ++s) {
-        stockham_stage<V, N, R, 8, false>(x, lds, ltw, t, L);
+        stockham_stage<V, N, R, 8, false, WAVE>(x, lds, ltw, t, L);
         L *= 8;
       }
     }
-    stockham_stage<V, N, R, 8, true>(x, lds, ltw, t, L);
+    stockham_stage<V, N, R, 8, true, WAVE>(x, lds, ltw, t, L);
   }
 }
 
 // Inverse (unnormalised) DFT: conj(DFT(conj x)).
-template <typename V, int N, int R>
+template <typename V, int N, int R, bool WAVE = false>
 __device__ __forceinline__ void fft_inverse(V (&x)[R], V* lds, const V* ltw, int t) {
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = cconj(x[r]);
-  fft_forward<V, N, R>(x, lds, ltw, t);
+  fft_forward<V, N, R, WAVE>(x, lds, ltw, t);
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = cconj(x[r]);
 }

@@ -1,7 +1,8 @@
 // Grounded-slab spectral dyadic Green's function minus the effective
 // homogeneous medium and its image (Sec. II, Sec. III-A of the paper), on
-// the ray contour k_c = (1 + i gamma) k, in FP64.  One thread per sample,
-// interleaved complex128 output [3][ny][nx] with x fastest (coalesced).
+// the ray contour k_c = (1 + i gamma) k, in FP64.  One thread per quadrant
+// sample, writing its mirror images; interleaved complex128 output
+// [3][ny][nx] with x fastest.
 //
 // The same templated evaluation runs on forward-mode dual numbers in the
 // adjoint, giving dG/d eps_r and dG/dh analytically.
@@ -146,25 +147,60 @@ __device__ __forceinline__ void green_dyadic(double kx, double ky, double gamma,
   gxy = o_rmul(o_sub(dtm, dte), -c * s);
 }
 
+// Mirror symmetry of the sample grid: k(N/2 + h) = h dk = -k(N/2 - h), and
+// index 0 (k = -k_max) is the mirror of h = N/2.  The immittances depend on
+// beta only; Gxx and Gyy are even and Gxy odd in each of kx and ky.  One
+// thread therefore evaluates the dyadic at (h1 dkx, h2 dky), h in [0, N/2],
+// and writes the up to four mirrored samples (n1, n2) = (N/2 +- h1, N/2 +- h2)
+// that exist, negating Gxy where exactly one of kx, ky changes sign (the
+// same value a direct evaluation at the negated wavenumber gives).
+__host__ __device__ int green_threads(const GreenParams& p) { return (p.x.n / 2 + 1) * (p.y.n / 2 + 1); }
+
+struct Mirror {
+  int h1, h2;
+};
+__device__ __forceinline__ bool mirror_of(const GreenParams& p, int idx, Mirror& m) {
+  const int hx = p.x.n / 2, hy = p.y.n / 2;
+  if (idx >= (hx + 1) * (hy + 1)) return false;
+  m.h1 = idx % (hx + 1);
+  m.h2 = idx / (hx + 1);
+  return true;
+}
+// Sample q (0..3) of the mirror set: bit 0 selects N/2 - h1, bit 1 N/2 - h2.
+// Returns the flat sample index, or -1 where that mirror does not exist.
+__device__ __forceinline__ int mirror_sample(const GreenParams& p, const Mirror& m, int q) {
+  const int hx = p.x.n / 2, hy = p.y.n / 2;
+  const bool fx = q & 1, fy = q & 2;
+  const int n1 = fx ? hx - m.h1 : hx + m.h1;
+  const int n2 = fy ? hy - m.h2 : hy + m.h2;
+  if (n1 >= p.x.n || n2 >= p.y.n) return -1;   // h = N/2 has only its minus mirror
+  if ((fx && m.h1 == 0) || (fy && m.h2 == 0)) return -1;   // h = 0 is its own mirror
+  return n2 * p.x.n + n1;
+}
+
 __global__ void __launch_bounds__(256) green_kernel(GreenParams p, double2* __restrict__ g) {
+  Mirror mr;
+  if (!mirror_of(p, blockIdx.x * blockDim.x + threadIdx.x, mr)) return;
   const int n = p.x.n * p.y.n;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  const int n1 = idx % p.x.n;
-  const int n2 = idx / p.x.n;
-  const double kx = p.x.k_first + n1 * p.x.dk;
-  const double ky = p.y.k_first + n2 * p.y.dk;
+  const double kx = mr.h1 * p.x.dk;
+  const double ky = mr.h2 * p.y.dk;
   const double2 eps = make_double2(p.eps_re, -p.eps_re * p.tan_delta);
   const double2 h = make_double2(p.h, 0.0);
   double2 gxx, gxy, gyy;
   green_dyadic(kx, ky, p.gamma, p.k0, eps, h, gxx, gxy, gyy);
-  g[idx] = gxx;
-  g[n + idx] = gxy;
-  g[2 * n + idx] = gyy;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = mirror_sample(p, mr, q);
+    if (i < 0) continue;
+    const bool odd = (q == 1) || (q == 2);
+    g[i] = gxx;
+    g[n + i] = odd ? make_double2(-gxy.x, -gxy.y) : gxy;
+    g[2 * n + i] = gyy;
+  }
 }
 
 hipError_t launch_green(const GreenParams& p, double2* g, hipStream_t s) {
-  const int n = p.x.n * p.y.n;
+  const int n = green_threads(p);
   hipLaunchKernelGGL(green_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, g);
   return hipGetLastError();
 }
@@ -176,12 +212,13 @@ __global__ void __launch_bounds__(256) adj_green_kernel(GreenParams p, const dou
                                                         double* __restrict__ partial) {
   __shared__ double red[2][256];
   const int n = p.x.n * p.y.n;
+  const int nq = green_threads(p);
   double acc0 = 0.0, acc1 = 0.0;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
-    const int n1 = idx % p.x.n;
-    const int n2 = idx / p.x.n;
-    const double kx = p.x.k_first + n1 * p.x.dk;
-    const double ky = p.y.k_first + n2 * p.y.dk;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nq; idx += gridDim.x * blockDim.x) {
+    Mirror mr;
+    mirror_of(p, idx, mr);
+    const double kx = mr.h1 * p.x.dk;
+    const double ky = mr.h2 * p.y.dk;
     dc<2> eps, h;
     eps.v = make_double2(p.eps_re, -p.eps_re * p.tan_delta);
     eps.d[0] = make_double2(1.0, -p.tan_delta);
@@ -191,12 +228,19 @@ __global__ void __launch_bounds__(256) adj_green_kernel(GreenParams p, const dou
     h.d[1] = make_double2(1.0, 0.0);
     dc<2> gxx, gxy, gyy;
     green_dyadic(kx, ky, p.gamma, p.k0, eps, h, gxx, gxy, gyy);
-    const double2 a = gg[idx], b = gg[n + idx], c = gg[2 * n + idx];
-    // Re(conj(a) d) = a.x d.x + a.y d.y
-    acc0 += a.x * gxx.d[0].x + a.y * gxx.d[0].y + b.x * gxy.d[0].x + b.y * gxy.d[0].y + c.x * gyy.d[0].x +
-            c.y * gyy.d[0].y;
-    acc1 += a.x * gxx.d[1].x + a.y * gxx.d[1].y + b.x * gxy.d[1].x + b.y * gxy.d[1].y + c.x * gyy.d[1].x +
-            c.y * gyy.d[1].y;
+    // the mirrored samples share dGxx, dGyy; dGxy flips sign with Gxy
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = mirror_sample(p, mr, q);
+      if (i < 0) continue;
+      const double sg = (q == 1 || q == 2) ? -1.0 : 1.0;
+      const double2 a = gg[i], b = gg[n + i], c = gg[2 * n + i];
+      // Re(conj(a) d) = a.x d.x + a.y d.y
+      acc0 += a.x * gxx.d[0].x + a.y * gxx.d[0].y + sg * (b.x * gxy.d[0].x + b.y * gxy.d[0].y) +
+              c.x * gyy.d[0].x + c.y * gyy.d[0].y;
+      acc1 += a.x * gxx.d[1].x + a.y * gxx.d[1].y + sg * (b.x * gxy.d[1].x + b.y * gxy.d[1].y) +
+              c.x * gyy.d[1].x + c.y * gyy.d[1].y;
+    }
   }
   red[0][threadIdx.x] = acc0;
   red[1][threadIdx.x] = acc1;

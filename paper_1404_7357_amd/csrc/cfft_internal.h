@@ -9,6 +9,10 @@ namespace cfft {
 
 constexpr int kMaxPairsPerLaunch = 64;
 constexpr int kMaxOrder = 7;
+#ifndef CFFT_SPEC_PCHUNK
+#define CFFT_SPEC_PCHUNK 4
+#endif
+constexpr int kSpecPChunk = CFFT_SPEC_PCHUNK;   // spectra kernel: centres per unrolled chunk
 
 // Sampling of one axis: k(n) = k0 + n dk, D(j) = d0 + j dd.
 struct Axis {
@@ -32,6 +36,8 @@ struct GeomGroup {
   int xoff, yoff;     // offsets into the x / y centre arrays
   int ioff;           // offset into the [np][nr] basis index array (-1 = empty slot)
   int uoff;           // row offset of this group's x tables (U rows)
+  int poff;           // offset of this group's centres in the per-row w tables,
+                      // each group padded to a multiple of kSpecPChunk
   double a, b;
 };
 
@@ -41,6 +47,7 @@ struct GeomDevice {
   int total_p;        // sum of np
   int total_r;        // sum of nr
   int total_idx;      // sum of np*nr
+  int ppad;           // sum of np rounded up per group to kSpecPChunk
   GeomGroup* groups;  // device copies
   double* xs;         // [total_p]
   double* ys;         // [total_r]
@@ -56,6 +63,7 @@ struct PassParams {
 
 // Launchers; all return hipSuccess or the launch error.
 hipError_t launch_green(const GreenParams& p, double2* g, hipStream_t s);
+__host__ __device__ int green_threads(const GreenParams& p);   // quadrant samples evaluated
 
 hipError_t launch_spectra_tables(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
                                  double2* utab, hipStream_t s);

@@ -27,10 +27,15 @@
 #include "cfft_internal.h"
 
 // Scheduling knobs (compile-time): minimum waves per SIMD requested from the
-// register allocator for the two passes (0 = compiler's choice), and the
-// widest FP64 column tile in bytes per row.
+// register allocator for the two passes (0 = compiler's choice), whether the
+// column pass fetches the next term's column while transforming the current
+// one (costs one register array), and the widest FP64 column tile in bytes
+// per row.
 #ifndef CFFT_ROW_MIN_WAVES
 #define CFFT_ROW_MIN_WAVES 0
+#endif
+#ifndef CFFT_COL_PREFETCH
+#define CFFT_COL_PREFETCH 0
 #endif
 #ifndef CFFT_COL_MIN_WAVES
 #define CFFT_COL_MIN_WAVES 0
@@ -116,7 +121,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
     V x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = f[r];
-    fft_forward<V, N, R>(x, my_lds, ltw, t);
+    fft_forward<V, N, R, (T <= 64)>(x, my_lds, ltw, t);
     V* dst = inter + (((size_t)pair * (a.order + 1) + ao) * a.ny + (valid ? n2 : 0)) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -160,7 +165,11 @@ template <int N, int NPW> struct RowGCfg {
 };
 
 template <typename V, int N, int NPW>
+#if CFFT_ROW_MIN_WAVES > 0
+__global__ void __launch_bounds__(NPW * (N / 8), CFFT_ROW_MIN_WAVES) row_pass_grouped_kernel(RowGArgs a) {
+#else
 __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArgs a) {
+#endif
   using Cfg = RowGCfg<N, NPW>;
   constexpr int T = Cfg::T, R = Cfg::R;
   using Rl = typename real_of<V>::type;
@@ -191,6 +200,9 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
   }
   __syncthreads();   // A tables and twiddle tables ready
   const bool active = w < a.gcnt[grp];
+  if constexpr (T <= 64) {
+    if (!active) return;   // transforms are wave-local: nothing left to wait for
+  }
   const int pair = active ? a.gpair[a.gfirst[grp] + w] : 0;
   const int n = a.pn[pair];
   V f[R];
@@ -221,7 +233,7 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
     V x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = f[r];
-    fft_forward<V, N, R>(x, my_lds, ltw, t);
+    fft_forward<V, N, R, (T <= 64)>(x, my_lds, ltw, t);
     V* dst = inter + (((size_t)pair * (a.order + 1) + ao) * a.ny + n2) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -286,7 +298,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
   // is transformed.  The weights s(n2)(gamma ky)^b and Dy^b/b! are rebuilt
   // per term (a few multiplies) rather than kept live in registers.
   V nxt[R];
-  {
+  if constexpr (CFFT_COL_PREFETCH) {
     const V* src = col0 + (size_t)a.order * plane;
 #pragma unroll
     for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
@@ -295,6 +307,11 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
   __syncthreads();   // twiddle tables ready
   for (int b = 0; b <= a.order; ++b) {
     V x[R];
+    if constexpr (!CFFT_COL_PREFETCH) {
+      const V* src = col0 + (size_t)(a.order - b) * plane;
+#pragma unroll
+      for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int n2 = t + T * r;
@@ -303,7 +320,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
       for (int i = 0; i < b; ++i) w *= gk;
       x[r] = cscale(nxt[r], w);
     }
-    if (b < a.order) {
+    if (CFFT_COL_PREFETCH && b < a.order) {
       const V* src = col0 + (size_t)(a.order - b - 1) * plane;
 #pragma unroll
       for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
@@ -615,7 +632,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
       if (ao > 0) cf[r] *= (a.x0 + j1 * a.ddx) * a.rinv[ao];
       x[r] = valid ? cscale(src[j1], cf[r]) : make_double2(0.0, 0.0);
     }
-    fft_inverse<double2, N, R>(x, my_lds, ltw, t);
+    fft_inverse<double2, N, R, (T <= 64)>(x, my_lds, ltw, t);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int n1 = t + T * r;

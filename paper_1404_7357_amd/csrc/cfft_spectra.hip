@@ -13,6 +13,10 @@
 
 namespace cfft {
 
+__device__ __forceinline__ double2 at_byte(const double2* row, unsigned byte_off) {
+  return *(const double2*)((const char*)row + byte_off);
+}
+
 __device__ __forceinline__ bool is_ydir(int kind) { return kind == 1 || kind == 3; }
 __device__ __forceinline__ bool is_cos(int kind) { return kind == 2 || kind == 3; }
 
@@ -111,180 +115,181 @@ hipError_t launch_spectra_tables(const Axis& x, const Axis& y, double gamma, con
   return hipGetLastError();
 }
 
-constexpr int kSpecThreads = 256;
+#ifndef CFFT_SPEC_THREADS
+#define CFFT_SPEC_THREADS 256
+#endif
+#ifndef CFFT_SPEC_SPT
+#define CFFT_SPEC_SPT 1
+#endif
+constexpr int kSpecThreads = CFFT_SPEC_THREADS;   // spectra kernel block size
+constexpr int kSpecSpt = CFFT_SPEC_SPT;           // samples per thread
 constexpr int kMaxGroups = 32;  // host refuses basis sets needing more
 constexpr int kMChunk = 4;
-constexpr int kPChunk = 8;
 
-// Per-row contraction over y-centres, one thread per (n2, m, prow):
-//   w [n2][m][prow] = SY_g(n2) sum_r conj(q_m,j(g,p,r)) V_gr(n2)
-//   w#[n2][m][prow] = SY_g(n2) sum_r      q_m,j(g,p,r)  V#_gr(n2)
-// stored as wtab[n2][m][2][total_p].  The coefficients are first gathered
-// into the dense slot layout qd[m][slot] (0 for empty slots) so that the r
-// loop has no dependent index loads.
-__global__ void gather_q_kernel(GeomDevice geo, const double2* __restrict__ q, int nmbf, double2* __restrict__ qd) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nmbf * geo.total_idx) return;
-  const int m = e / geo.total_idx, li = e % geo.total_idx;
-  const int j = geo.index[li];
-  qd[e] = j < 0 ? make_double2(0.0, 0.0) : q[(size_t)m * geo.nbasis + j];
-}
-
-// One block per row n2: the row's V, V# and SY values are staged in LDS,
-// then each thread sums the entries (m, prow) it owns over the group's
-// y-centres, eight independent coefficient loads at a time.
-constexpr int kRowsThreads = 128;
+// Per-row contraction over y-centres.  One block per row n2; the row's V, V#
+// and SY values are staged in LDS, then each thread owns entries (v, m, pp)
+// of the row's table
+//   v = 0:  w [n2][m][pp] = SY_g(n2) sum_r conj(q_m,j(g,p,r)) V_gr(n2)
+//   v = 1:  w#[n2][m][pp] = SY_g(n2) sum_r      q_m,j(g,p,r)  V#_gr(n2)
+// stored as wtab[n2][v][mpad][ppad] with pp = poff_g + p.  Slots past a
+// group's centre count and MBFs past nmbf hold zero, so the per-sample
+// kernel runs whole chunks without bounds tests.  Coefficients are fetched
+// through the slot index, eight independent loads at a time.
+constexpr int kRowsThreads = 256;
 __global__ void __launch_bounds__(kRowsThreads)
 spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
-                    const double2* __restrict__ qd, int nmbf, double2* __restrict__ wtab) {
+                    const double2* __restrict__ q, int nmbf, int mpad, double2* __restrict__ wtab) {
   extern __shared__ double2 vs[];   // [2 total_r] V, V# interleaved by row, then [ngroups] SY
   const int n2 = blockIdx.x;
   const double2* vtab = utab + vtab_offset(x.n, geo);
   const int nv = 2 * geo.total_r + geo.ngroups;
   for (int i = threadIdx.x; i < nv; i += blockDim.x) vs[i] = vtab[(size_t)i * y.n + n2];
   __syncthreads();
-  const int per_row = nmbf * geo.total_p;
-  double2* dst = wtab + (size_t)n2 * nmbf * 2 * geo.total_p;
-  for (int e = threadIdx.x; e < per_row; e += blockDim.x) {
-    const int m = e / geo.total_p;
-    const int prow = e % geo.total_p;
+  const int ppad = geo.ppad;
+  const int per_v = mpad * ppad;
+  double2* dst = wtab + (size_t)n2 * 2 * per_v;
+  for (int e = threadIdx.x; e < 2 * per_v; e += blockDim.x) {
+    const int v = e / per_v;
+    const int m = (e % per_v) / ppad;
+    const int pp = e % ppad;
     int g = 0;
-    while (g + 1 < geo.ngroups && geo.groups[g + 1].uoff <= prow) ++g;
+    while (g + 1 < geo.ngroups && geo.groups[g + 1].poff <= pp) ++g;
     const GeomGroup gr = geo.groups[g];
-    const int p = prow - gr.uoff;
-    const double2* qrow = qd + (size_t)m * geo.total_idx + gr.ioff + (size_t)p * gr.nr;
-    double2 acc = make_double2(0.0, 0.0), acch = make_double2(0.0, 0.0);
-    for (int r0 = 0; r0 < gr.nr; r0 += 8) {
-      double2 qq[8];
+    const int p = pp - gr.poff;
+    double2 acc = make_double2(0.0, 0.0);
+    if (m < nmbf && p < gr.np) {
+      const int* irow = geo.index + gr.ioff + (size_t)p * gr.nr;
+      const double2* qm = q + (size_t)m * geo.nbasis;
+      for (int r0 = 0; r0 < gr.nr; r0 += 8) {
+        int jj[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) qq[k] = r0 + k < gr.nr ? qrow[r0 + k] : make_double2(0.0, 0.0);
+        for (int k = 0; k < 8; ++k) jj[k] = r0 + k < gr.nr ? irow[r0 + k] : -1;
+        double2 qq[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        if (r0 + k < gr.nr) {
-          const int vr = gr.yoff + r0 + k;
-          acc = cadd(acc, cmulc(vs[2 * vr], qq[k]));       // conj(q) V
-          acch = cadd(acch, cmul(qq[k], vs[2 * vr + 1]));  // q V#
+        for (int k = 0; k < 8; ++k) qq[k] = jj[k] >= 0 ? qm[jj[k]] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (r0 + k < gr.nr) {
+            const double2 vv = vs[2 * (gr.yoff + r0 + k) + v];
+            acc = cadd(acc, v == 0 ? cmulc(vv, qq[k]) : cmul(qq[k], vv));   // conj(q) V  or  q V#
+          }
         }
       }
+      acc = cmul(acc, vs[2 * geo.total_r + g]);
     }
-    const double2 sy = vs[2 * geo.total_r + g];
-    dst[(size_t)m * 2 * geo.total_p + prow] = cmul(acc, sy);
-    dst[(size_t)m * 2 * geo.total_p + geo.total_p + prow] = cmul(acch, sy);
+    dst[e] = acc;
   }
 }
 
-// Block = 256 consecutive samples of one row n2 and one variant v (blockIdx.z:
-// 0 = testing spectra M with U and w, 1 = reflected spectra M# with U# and w#),
-// one sample per thread:  M_m = sum_g SX_g sum_p U_gp w[m][p].
-// The row's w table is copied to LDS zero-padded to whole chunks of kPChunk
-// centres per group and to a multiple of kMChunk MBFs, so the unrolled inner
-// loop has no bounds tests; padded entries multiply a clamped U by zero.
+// Block = kSpecThreads * kSpecSpt samples of one row n2 and one variant v
+// (blockIdx.z: 0 = testing spectra M with U and w, 1 = reflected spectra M#
+// with U# and w#); each thread owns kSpecSpt samples kSpecThreads apart:
+//   M_m = sum_g SX_g sum_p U_gp w[m][p].
+// Every thread of a block reads the same w entries and group records
+// (wave-uniform addresses, served by scalar loads); only U and SX are per
+// sample.  Padded centres use a clamped U times a zero w.
 __global__ void __launch_bounds__(kSpecThreads)
 spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
-               const double2* __restrict__ wtab, int nmbf, double2* __restrict__ spec) {
-  extern __shared__ double2 sh[];   // [mpad][ppad]
-  __shared__ GeomGroup grp[kMaxGroups];
-  __shared__ int gpad[kMaxGroups + 1];   // padded offsets of each group's centres
+               const double2* __restrict__ wtab, int nmbf, int mpad, double2* __restrict__ spec) {
+  constexpr int S = kSpecSpt;
   const int n2 = blockIdx.y;
   const int v = blockIdx.z;
-  const int n1 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n1_0 = blockIdx.x * (kSpecThreads * S) + threadIdx.x;
+  if (n1_0 >= x.n) return;
   const int tp = geo.total_p;
-  if (threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int g = 0; g < geo.ngroups; ++g) {
-      gpad[g] = acc;
-      acc += (geo.groups[g].np + kPChunk - 1) / kPChunk * kPChunk;
-    }
-    gpad[geo.ngroups] = acc;
-  }
-  __syncthreads();
-  const int ppad = gpad[geo.ngroups];
-  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
-  const double2* src = wtab + (size_t)n2 * nmbf * 2 * tp + (size_t)v * tp;
-  for (int e = threadIdx.x; e < mpad * ppad; e += blockDim.x) {
-    const int m = e / ppad;
-    const int pp = e % ppad;
-    int g = 0;
-    while (g + 1 < geo.ngroups && gpad[g + 1] <= pp) ++g;
-    const int p = pp - gpad[g];
-    double2 val = make_double2(0.0, 0.0);
-    if (m < nmbf && p < grp[g].np) val = src[(size_t)m * 2 * tp + grp[g].uoff + p];
-    sh[e] = val;
-  }
-  __syncthreads();
-  if (n1 >= x.n) return;
+  const int ppad = geo.ppad;
+  const double2* wrow = wtab + ((size_t)n2 * 2 + v) * mpad * ppad;
   const size_t plane = (size_t)x.n * y.n;
-  const double2* ub = utab + n1;
   const size_t rs = (size_t)x.n;
+  bool live[S];
+  int n1[S];
+  unsigned boff[S];   // byte offset of the sample in a table row (32-bit, so
+                      // loads take a scalar row base plus a vector offset)
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    n1[s] = n1_0 + s * kSpecThreads;
+    live[s] = n1[s] < x.n;
+    if (!live[s]) n1[s] = n1_0;   // clamp loads; stores are skipped
+    boff[s] = (unsigned)n1[s] * (unsigned)sizeof(double2);
+  }
   for (int m0 = 0; m0 < mpad; m0 += kMChunk) {
-    double2 acc[kMChunk][2];
+    double2 acc[S][kMChunk][2];
 #pragma unroll
-    for (int i = 0; i < kMChunk; ++i) acc[i][0] = acc[i][1] = make_double2(0.0, 0.0);
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int i = 0; i < kMChunk; ++i) acc[s][i][0] = acc[s][i][1] = make_double2(0.0, 0.0);
     for (int g = 0; g < geo.ngroups; ++g) {
-      const GeomGroup gr = grp[g];
+      const GeomGroup gr = geo.groups[g];
       const int comp = is_ydir(gr.kind) ? 1 : 0;
-      const double2 sx = ub[(size_t)(2 * tp + g) * rs];
-      double2 sg[kMChunk];
+      double2 sg[S][kMChunk];
 #pragma unroll
-      for (int i = 0; i < kMChunk; ++i) sg[i] = make_double2(0.0, 0.0);
-      const int pend = gpad[g + 1] - gpad[g];
-      for (int p0 = 0; p0 < pend; p0 += kPChunk) {
-        double2 u[kPChunk];
+      for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int k = 0; k < kPChunk; ++k) {
+        for (int i = 0; i < kMChunk; ++i) sg[s][i] = make_double2(0.0, 0.0);
+      const int pend = (gr.np + kSpecPChunk - 1) / kSpecPChunk * kSpecPChunk;
+      const double2* wg = wrow + (size_t)m0 * ppad + gr.poff;
+      for (int p0 = 0; p0 < pend; p0 += kSpecPChunk) {
+        double2 u[S][kSpecPChunk];
+#pragma unroll
+        for (int k = 0; k < kSpecPChunk; ++k) {
           const int prow = gr.uoff + min(p0 + k, gr.np - 1);
-          u[k] = ub[(size_t)(2 * prow + v) * rs];
+          const double2* urow = utab + (size_t)(2 * prow + v) * rs;   // wave-uniform row base
+#pragma unroll
+          for (int s = 0; s < S; ++s) u[s][k] = at_byte(urow, boff[s]);
         }
-        const double2* wp = sh + gpad[g] + p0;
 #pragma unroll
-        for (int k = 0; k < kPChunk; ++k) {
+        for (int k = 0; k < kSpecPChunk; ++k) {
 #pragma unroll
-          for (int i = 0; i < kMChunk; ++i) sg[i] = cfma(sg[i], u[k], wp[(m0 + i) * ppad + k]);
+          for (int i = 0; i < kMChunk; ++i) {
+            const double2 wv = wg[(size_t)i * ppad + p0 + k];
+#pragma unroll
+            for (int s = 0; s < S; ++s) sg[s][i] = cfma(sg[s][i], u[s][k], wv);
+          }
         }
       }
+      const double2* sxrow = utab + (size_t)(2 * tp + g) * rs;
 #pragma unroll
-      for (int i = 0; i < kMChunk; ++i) acc[i][comp] = cfma(acc[i][comp], sg[i], sx);
+      for (int s = 0; s < S; ++s) {
+        const double2 sx = at_byte(sxrow, boff[s]);
+#pragma unroll
+        for (int i = 0; i < kMChunk; ++i) acc[s][i][comp] = cfma(acc[s][i][comp], sg[s][i], sx);
+      }
     }
 #pragma unroll
-    for (int i = 0; i < kMChunk; ++i) {
-      if (m0 + i < nmbf) {
+    for (int s = 0; s < S; ++s) {
+      if (!live[s]) continue;
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-          spec[((size_t)(m0 + i) * 4 + 2 * v + c) * plane + (size_t)n2 * x.n + n1] = acc[i][c];
+      for (int i = 0; i < kMChunk; ++i) {
+        if (m0 + i < nmbf) {
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            spec[((size_t)(m0 + i) * 4 + 2 * v + c) * plane + (size_t)n2 * x.n + n1[s]] = acc[s][i][c];
+        }
       }
     }
   }
 }
 
 size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf) {
-  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
-  return sizeof(double2) * (size_t)mpad * (geo.total_p + geo.ngroups * (kPChunk - 1));
+  (void)nmbf;
+  return sizeof(double2) * (size_t)(2 * geo.total_r + geo.ngroups);
 }
 
 size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf) {
-  return (size_t)nmbf * geo.total_idx + (size_t)y.n * nmbf * 2 * geo.total_p;
+  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
+  return (size_t)y.n * 2 * mpad * geo.ppad;
 }
 
 hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo, const double2* utab,
                           const double2* q, int nmbf, double2* scratch, double2* spec, hipStream_t s) {
   (void)gamma;
-  double2* qd = scratch;
-  double2* wtab = scratch + (size_t)nmbf * geo.total_idx;
-  const int ng = nmbf * geo.total_idx;
-  hipLaunchKernelGGL(gather_q_kernel, dim3((ng + 255) / 256), dim3(256), 0, s, geo, q, nmbf, qd);
+  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
+  hipLaunchKernelGGL(spectra_rows_kernel, dim3(y.n), dim3(kRowsThreads), spectra_lds_bytes(geo, nmbf), s, x, y, geo,
+                     utab, q, nmbf, mpad, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t vlds = sizeof(double2) * (size_t)(2 * geo.total_r + geo.ngroups);
-  hipLaunchKernelGGL(spectra_rows_kernel, dim3(y.n), dim3(kRowsThreads), vlds, s, x, y, geo, utab, qd, nmbf, wtab);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // upper bound of the padded centre count (each group padded to kPChunk)
-  const int ppad = geo.total_p + geo.ngroups * (kPChunk - 1);
-  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
-  const size_t lds = sizeof(double2) * (size_t)mpad * ppad;
-  dim3 grid((x.n + kSpecThreads - 1) / kSpecThreads, y.n, 2);
-  hipLaunchKernelGGL(spectra_kernel, grid, dim3(kSpecThreads), lds, s, x, y, geo, utab, wtab, nmbf, spec);
+  dim3 grid((x.n + kSpecThreads * kSpecSpt - 1) / (kSpecThreads * kSpecSpt), y.n, 2);
+  hipLaunchKernelGGL(spectra_kernel, grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf, mpad, spec);
   return hipGetLastError();
 }
 
