@@ -25,7 +25,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 
 
 def _log(msg):
@@ -38,9 +39,9 @@ def _ensure_built():
         __graft_entry__.build()
 
 
-def _source_hash():
+def _source_hash(files=("cfft_passes.hip", "cfft_device.h")):
     h = hashlib.sha256()
-    for f in ("cfft_passes.hip", "cfft_device.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1404_7357_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -78,11 +79,20 @@ class Step:
         self.spec = torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=torch.complex128, device="cuda")
         self.z = torch.empty((len(self.pairs), gd.ny, gd.nx), dtype=dt, device="cuda")
         self._lib = _lib
+        # The Green's function and the spectra are independent: the Green's
+        # function (few waves, latency-bound) runs on a second stream of
+        # default priority beside the spectra.
+        self.side = torch.cuda.Stream()
 
     def run(self):
         s = self.sub
-        self.tab.green(s.eps_r, s.tan_delta, s.h, out=self.g)
+        torch = self.torch
+        main = torch.cuda.current_stream()
+        self.side.wait_stream(main)          # the previous step's passes are done with g
+        with torch.cuda.stream(self.side):
+            self.tab.green(s.eps_r, s.tan_delta, s.h, out=self.g)
         self.tab.spectra(self.q, out=self.spec)
+        main.wait_stream(self.side)
         self.tab.tabulate(self.spec, self.g, self.pairs, out=self.z)
 
     def entries(self):
@@ -114,6 +124,39 @@ def _kernel_times(st, steps):
         if n:
             out[name] = {"avg_ms": ms / n, "launches_per_step": n / steps}
     return out
+
+
+def _green_flops():
+    """FP64 flops of one Green's-function launch (512^2 grid) from the committed rocprofv3 counters, if current."""
+    path = os.path.join(ROOT, "profiles", "traffic_c2_fp64.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("green_source_hash") != _source_hash(("cfft_green.hip", "cfft_device.h")):
+        return None
+    return rec.get("green_fp64_flops_per_launch")
+
+
+def _green_alu(st, steps):
+    """Green's-function kernel alone on the launch stream (HIP events), against the FP64 vector peak."""
+    lib = st._lib
+    s = st.sub
+    lib.profile(st.tab.plan, True)
+    for _ in range(steps):
+        st.tab.green(s.eps_r, s.tan_delta, s.h, out=st.g)
+    st.torch.cuda.synchronize()
+    lib.profile(st.tab.plan, False)
+    ms, n = lib.profile_read(st.tab.plan, "green")
+    avg_ms = ms / n
+    flops = _green_flops()
+    achieved = flops / (avg_ms * 1e-3) / 1e12 if flops else None
+    gd = st.grid
+    return {"bound": "alu", "kernel": "green", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "avg_ms": avg_ms,
+            "fp64_flops_per_launch": flops, "samples_evaluated": (gd.nx // 2 + 1) * (gd.ny // 2 + 1),
+            "samples_written": gd.nx * gd.ny}
 
 
 def _cpu_baseline(wl, z_gpu, n_out, workers):
@@ -250,6 +293,7 @@ def main():
     value = st.entries() / sec
     _log(f"fp64 step {sec * 1e3:.3f} ms -> {value:.4e} entries/s")
     kernels = _kernel_times(st, args.steps)
+    green_alu = _green_alu(st, args.steps)
     torch.cuda.synchronize()
     z_fp64 = st.z.cpu().numpy()
 
@@ -292,7 +336,7 @@ def main():
                       "order": P, "gamma": wl.grids[0].gamma, "eps_r": wl.substrates[0].eps_r,
                       "tan_delta": wl.substrates[0].tan_delta, "h": wl.substrates[0].h,
                       "precision": "fp64"},
-           "roofline": roofline, "kernels_ms": kernels}
+           "roofline": roofline, "green_fp64": green_alu, "kernels_ms": kernels}
     st.tab.close()
     del st
 

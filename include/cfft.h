@@ -33,7 +33,11 @@
  *
  * Execution.  Entry points taking a `stream` (a hipStream_t, NULL = the
  * default stream) enqueue their kernels on it and return without waiting,
- * except where stated.  One plan must not be used from two streams at once.
+ * except where stated.  One plan must not be used from two streams at once,
+ * with one exception: slab_green_eval touches no plan workspace, so it may
+ * run on a second stream beside the other entry points of the same plan
+ * when the plan was made without CFFT_FLAG_CHECK_FINITE.  A plan is not
+ * thread-safe: issue its calls from one host thread at a time.
  *
  * Errors.  Every call returns a status.  Arguments are validated on the host
  * before anything is launched; on error nothing is enqueued and

@@ -76,7 +76,7 @@ struct GeomHost {
   std::vector<GeomGroup> groups;
   std::vector<double> xs, ys;
   std::vector<int> index;
-  int total_p = 0, total_r = 0, total_idx = 0, ppad = 0;
+  int total_p = 0, total_r = 0, total_idx = 0, ppad = 0, ngroups_x = 0;
 };
 
 // Group bases by (kind, a, b); inside a group place each basis on the grid of
@@ -108,8 +108,7 @@ bool build_geometry(const cfft_basis_t* basis, int nb, GeomHost& out) {
       g.xoff = (int)out.xs.size();
       g.yoff = (int)out.ys.size();
       g.ioff = (int)out.index.size();
-      g.uoff = out.total_p;
-      g.poff = out.ppad;
+      g.uoff = g.poff = 0;   // set below, once the group order is final
       std::vector<int> idx((size_t)g.np * g.nr, -1);
       for (int j : mem) {
         const int p = (int)(std::lower_bound(xs.begin(), xs.end(), basis[j].cx) - xs.begin());
@@ -121,14 +120,27 @@ bool build_geometry(const cfft_basis_t* basis, int nb, GeomHost& out) {
       out.xs.insert(out.xs.end(), xs.begin(), xs.end());
       out.ys.insert(out.ys.end(), ys.begin(), ys.end());
       out.index.insert(out.index.end(), idx.begin(), idx.end());
-      out.total_p += g.np;
-      out.ppad += (g.np + kSpecPChunk - 1) / kSpecPChunk * kSpecPChunk;
       out.total_r += g.nr;
       out.total_idx += g.np * g.nr;
       out.groups.push_back(g);
       if ((int)out.groups.size() > 32) return false;
     }
     pending.swap(overflow);
+  }
+  // x-directed groups first (the spectra kernel accumulates one current
+  // component at a time), then the per-group row offsets in that order.
+  std::stable_sort(out.groups.begin(), out.groups.end(), [](const GeomGroup& a, const GeomGroup& b) {
+    return (a.kind == CFFT_ROOFTOP_Y || a.kind == CFFT_COSINE_Y) < (b.kind == CFFT_ROOFTOP_Y || b.kind == CFFT_COSINE_Y);
+  });
+  out.total_p = 0;
+  out.ppad = 0;
+  out.ngroups_x = 0;
+  for (GeomGroup& g : out.groups) {
+    g.uoff = out.total_p;
+    g.poff = out.ppad;
+    out.total_p += g.np;
+    out.ppad += (g.np + kSpecPChunk - 1) / kSpecPChunk * kSpecPChunk;
+    if (!(g.kind == CFFT_ROOFTOP_Y || g.kind == CFFT_COSINE_Y)) ++out.ngroups_x;
   }
   return true;
 }
@@ -303,6 +315,7 @@ cfft_status_t ensure_geometry(cfft_plan_s* plan, GridState& gs, const cfft_basis
     gd.total_r = gh.total_r;
     gd.total_idx = gh.total_idx;
     gd.ppad = gh.ppad;
+    gd.ngroups_x = gh.ngroups_x;
     gd.groups = (GeomGroup*)base;
     gd.xs = (double*)(base + al(bg));
     gd.ys = (double*)(base + al(bg) + al(bx));

@@ -48,6 +48,7 @@ struct GeomDevice {
   int total_r;        // sum of nr
   int total_idx;      // sum of np*nr
   int ppad;           // sum of np rounded up per group to kSpecPChunk
+  int ngroups_x;      // groups [0, ngroups_x) carry x-directed current, the rest y
   GeomGroup* groups;  // device copies
   double* xs;         // [total_p]
   double* ys;         // [total_r]

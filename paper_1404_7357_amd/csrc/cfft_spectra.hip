@@ -47,7 +47,8 @@ __device__ __forceinline__ void phase_pair(double k, double gamma, double X, dou
 }
 
 // Geometry tables of one grid (built once per grid and basis set):
-//   x part, rows of length nx: [2 (uoff+p)] = U, [2 (uoff+p) + 1] = U#,
+//   x part, rows of length nx: [2 (uoff+p)] = SX_g U, [2 (uoff+p) + 1] = SX_g U#
+//                              (the x shape factors are even in k),
 //                              [2 total_p + g] = SX_g
 //   y part (at vtab_offset), rows of length ny: [2 (yoff+r)] = V,
 //                              [2 (yoff+r) + 1] = V#, [2 total_r + g] = SY_g
@@ -69,11 +70,14 @@ __global__ void spectra_tables_kernel(Axis x, Axis y, double gamma, GeomDevice g
     if (i >= x.n) return;
     const double k = x.k_first + i * x.dk;
     if (row < geo.total_p) {
-      const GeomGroup gr = geo.groups[group_of(geo, row, false)];
+      const int g = group_of(geo, row, false);
+      const GeomGroup gr = geo.groups[g];
       double2 u, uh;
       phase_pair(k, gamma, geo.xs[gr.xoff + (row - gr.uoff)], u, uh);
-      utab[(size_t)(2 * row) * x.n + i] = u;
-      utab[(size_t)(2 * row + 1) * x.n + i] = uh;
+      const double2 kc = make_double2(k, gamma * k);
+      const double2 sx = is_ydir(gr.kind) ? across_factor(gr.b, kc) : along_factor(gr.kind, gr.a, kc);
+      utab[(size_t)(2 * row) * x.n + i] = cmul(sx, u);
+      utab[(size_t)(2 * row + 1) * x.n + i] = cmul(sx, uh);
     } else {
       const int g = row - geo.total_p;
       const GeomGroup gr = geo.groups[g];
@@ -118,11 +122,11 @@ hipError_t launch_spectra_tables(const Axis& x, const Axis& y, double gamma, con
 #ifndef CFFT_SPEC_THREADS
 #define CFFT_SPEC_THREADS 256
 #endif
-#ifndef CFFT_SPEC_SPT
-#define CFFT_SPEC_SPT 1
+#ifndef CFFT_SPEC_ROWS
+#define CFFT_SPEC_ROWS 2
 #endif
 constexpr int kSpecThreads = CFFT_SPEC_THREADS;   // spectra kernel block size
-constexpr int kSpecSpt = CFFT_SPEC_SPT;           // samples per thread
+constexpr int kSpecRows = CFFT_SPEC_ROWS;         // rows per spectra block
 constexpr int kMaxGroups = 32;  // host refuses basis sets needing more
 constexpr int kMChunk = 4;
 
@@ -181,99 +185,86 @@ spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ 
   }
 }
 
-// Block = kSpecThreads * kSpecSpt samples of one row n2 and one variant v
-// (blockIdx.z: 0 = testing spectra M with U and w, 1 = reflected spectra M#
-// with U# and w#); each thread owns kSpecSpt samples kSpecThreads apart:
-//   M_m = sum_g SX_g sum_p U_gp w[m][p].
-// Every thread of a block reads the same w entries and group records
-// (wave-uniform addresses, served by scalar loads); only U and SX are per
-// sample.  Padded centres use a clamped U times a zero w.
-__global__ void __launch_bounds__(kSpecThreads)
-spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
-               const double2* __restrict__ wtab, int nmbf, int mpad, double2* __restrict__ spec) {
-  constexpr int S = kSpecSpt;
-  const int n2 = blockIdx.y;
-  const int v = blockIdx.z;
-  const int n1_0 = blockIdx.x * (kSpecThreads * S) + threadIdx.x;
-  if (n1_0 >= x.n) return;
-  const int tp = geo.total_p;
+// Per-sample sums of one block: thread = sample n1 (byte offset boff in a
+// table row), rows n2_0 .. n2_0 + RB - 1 with w tables wrow[r] ([mpad][ppad]):
+//   M_m^c(n1, n2) = sum_{g of component c} sum_p (SX_g U_gp)(n1) w[n2][m][p].
+// A U value is loaded once and used for every row.  Padded centres use a
+// clamped U times a zero w.
+template <int RB>
+__device__ __forceinline__ void spectra_block(const GeomDevice& geo, const double2* __restrict__ utab, size_t rs,
+                                              unsigned boff, const double2* const (&wrow)[RB], int v, int nmbf,
+                                              int mpad, int n1, int n2_0, int ny, double2* __restrict__ spec) {
   const int ppad = geo.ppad;
-  const double2* wrow = wtab + ((size_t)n2 * 2 + v) * mpad * ppad;
-  const size_t plane = (size_t)x.n * y.n;
-  const size_t rs = (size_t)x.n;
-  bool live[S];
-  int n1[S];
-  unsigned boff[S];   // byte offset of the sample in a table row (32-bit, so
-                      // loads take a scalar row base plus a vector offset)
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    n1[s] = n1_0 + s * kSpecThreads;
-    live[s] = n1[s] < x.n;
-    if (!live[s]) n1[s] = n1_0;   // clamp loads; stores are skipped
-    boff[s] = (unsigned)n1[s] * (unsigned)sizeof(double2);
-  }
+  const size_t plane = rs * (size_t)ny;
   for (int m0 = 0; m0 < mpad; m0 += kMChunk) {
-    double2 acc[S][kMChunk][2];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
+    for (int c = 0; c < 2; ++c) {
+      double2 acc[RB][kMChunk];
 #pragma unroll
-      for (int i = 0; i < kMChunk; ++i) acc[s][i][0] = acc[s][i][1] = make_double2(0.0, 0.0);
-    for (int g = 0; g < geo.ngroups; ++g) {
-      const GeomGroup gr = geo.groups[g];
-      const int comp = is_ydir(gr.kind) ? 1 : 0;
-      double2 sg[S][kMChunk];
+      for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int s = 0; s < S; ++s)
+        for (int i = 0; i < kMChunk; ++i) acc[r][i] = make_double2(0.0, 0.0);
+      const int g0 = c == 0 ? 0 : geo.ngroups_x;
+      const int g1 = c == 0 ? geo.ngroups_x : geo.ngroups;
+      for (int g = g0; g < g1; ++g) {
+        const GeomGroup gr = geo.groups[g];
+        const int pend = (gr.np + kSpecPChunk - 1) / kSpecPChunk * kSpecPChunk;
+        const size_t woff = (size_t)m0 * ppad + gr.poff;
+        for (int p0 = 0; p0 < pend; p0 += kSpecPChunk) {
+          double2 u[kSpecPChunk];
 #pragma unroll
-        for (int i = 0; i < kMChunk; ++i) sg[s][i] = make_double2(0.0, 0.0);
-      const int pend = (gr.np + kSpecPChunk - 1) / kSpecPChunk * kSpecPChunk;
-      const double2* wg = wrow + (size_t)m0 * ppad + gr.poff;
-      for (int p0 = 0; p0 < pend; p0 += kSpecPChunk) {
-        double2 u[S][kSpecPChunk];
+          for (int k = 0; k < kSpecPChunk; ++k) {
+            const int prow = gr.uoff + min(p0 + k, gr.np - 1);
+            u[k] = at_byte(utab + (size_t)(2 * prow + v) * rs, boff);
+          }
 #pragma unroll
-        for (int k = 0; k < kSpecPChunk; ++k) {
-          const int prow = gr.uoff + min(p0 + k, gr.np - 1);
-          const double2* urow = utab + (size_t)(2 * prow + v) * rs;   // wave-uniform row base
+          for (int r = 0; r < RB; ++r) {
+            const double2* wg = wrow[r] + woff + p0;
 #pragma unroll
-          for (int s = 0; s < S; ++s) u[s][k] = at_byte(urow, boff[s]);
-        }
+            for (int k = 0; k < kSpecPChunk; ++k) {
 #pragma unroll
-        for (int k = 0; k < kSpecPChunk; ++k) {
-#pragma unroll
-          for (int i = 0; i < kMChunk; ++i) {
-            const double2 wv = wg[(size_t)i * ppad + p0 + k];
-#pragma unroll
-            for (int s = 0; s < S; ++s) sg[s][i] = cfma(sg[s][i], u[s][k], wv);
+              for (int i = 0; i < kMChunk; ++i) acc[r][i] = cfma(acc[r][i], u[k], wg[(size_t)i * ppad + k]);
+            }
           }
         }
       }
-      const double2* sxrow = utab + (size_t)(2 * tp + g) * rs;
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const double2 sx = at_byte(sxrow, boff[s]);
+      for (int r = 0; r < RB; ++r) {
+        if (n2_0 + r >= ny) continue;
 #pragma unroll
-        for (int i = 0; i < kMChunk; ++i) acc[s][i][comp] = cfma(acc[s][i][comp], sg[s][i], sx);
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (!live[s]) continue;
-#pragma unroll
-      for (int i = 0; i < kMChunk; ++i) {
-        if (m0 + i < nmbf) {
-#pragma unroll
-          for (int c = 0; c < 2; ++c)
-            spec[((size_t)(m0 + i) * 4 + 2 * v + c) * plane + (size_t)n2 * x.n + n1[s]] = acc[s][i][c];
+        for (int i = 0; i < kMChunk; ++i) {
+          if (m0 + i < nmbf)
+            spec[((size_t)(m0 + i) * 4 + 2 * v + c) * plane + (size_t)(n2_0 + r) * rs + n1] = acc[r][i];
         }
       }
     }
   }
 }
 
+// w tables from spectra_rows_kernel; every thread of a block reads the same
+// entries (wave-uniform addresses, served by scalar loads).  Block =
+// kSpecThreads samples of kSpecRows rows and one variant v (blockIdx.z:
+// 0 = M with U and w, 1 = M# with U# and w#).
+__global__ void __launch_bounds__(kSpecThreads)
+spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
+               const double2* __restrict__ wtab, int nmbf, int mpad, double2* __restrict__ spec) {
+  constexpr int RB = kSpecRows;
+  const int n2_0 = blockIdx.y * RB;
+  const int v = blockIdx.z;
+  const int n1 = blockIdx.x * kSpecThreads + threadIdx.x;
+  if (n1 >= x.n) return;
+  const double2* wrow[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) wrow[r] = wtab + ((size_t)min(n2_0 + r, y.n - 1) * 2 + v) * mpad * geo.ppad;
+  spectra_block<RB>(geo, utab, (size_t)x.n, (unsigned)n1 * (unsigned)sizeof(double2), wrow, v, nmbf, mpad, n1, n2_0,
+                    y.n, spec);
+}
+
 size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf) {
   (void)nmbf;
   return sizeof(double2) * (size_t)(2 * geo.total_r + geo.ngroups);
 }
+
 
 size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf) {
   const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
@@ -284,11 +275,11 @@ hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const Geom
                           const double2* q, int nmbf, double2* scratch, double2* spec, hipStream_t s) {
   (void)gamma;
   const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
+  dim3 grid((x.n + kSpecThreads - 1) / kSpecThreads, (y.n + kSpecRows - 1) / kSpecRows, 2);
   hipLaunchKernelGGL(spectra_rows_kernel, dim3(y.n), dim3(kRowsThreads), spectra_lds_bytes(geo, nmbf), s, x, y, geo,
                      utab, q, nmbf, mpad, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dim3 grid((x.n + kSpecThreads * kSpecSpt - 1) / (kSpecThreads * kSpecSpt), y.n, 2);
   hipLaunchKernelGGL(spectra_kernel, grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf, mpad, spec);
   return hipGetLastError();
 }
@@ -325,13 +316,12 @@ adj_spectra_rows_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const doub
         const int prow = gr.uoff + p;
         double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
         for (int n1 = threadIdx.x; n1 < x.n; n1 += blockDim.x) {
-          const double2 sx = utab[(size_t)(2 * geo.total_p + g) * x.n + n1];
-          const double2 u = utab[(size_t)(2 * prow) * x.n + n1];
-          const double2 uh = utab[(size_t)(2 * prow + 1) * x.n + n1];
+          const double2 u = utab[(size_t)(2 * prow) * x.n + n1];        // SX U
+          const double2 uh = utab[(size_t)(2 * prow + 1) * x.n + n1];   // SX U#
           const double2 gm = gspec[((size_t)m * 4 + comp) * plane + (size_t)n2 * x.n + n1];
           const double2 gmh = gspec[((size_t)m * 4 + 2 + comp) * plane + (size_t)n2 * x.n + n1];
-          s1 = cadd(s1, cmulc(cmul(sx, u), gm));          // conj(gM) SX U  (conj applied below)
-          s2 = cadd(s2, cmulc(gmh, cmul(sx, uh)));        // gM# conj(SX U#)
+          s1 = cadd(s1, cmulc(u, gm));      // conj(gM) SX U  (conj applied below)
+          s2 = cadd(s2, cmulc(gmh, uh));    // gM# conj(SX U#)
         }
         red[0][threadIdx.x] = s1;
         red[1][threadIdx.x] = s2;
