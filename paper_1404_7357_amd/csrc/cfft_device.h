@@ -107,6 +107,22 @@ __device__ __forceinline__ double2 csinc(double2 z) {
   return cdiv(make_double2(s * ch, c * sh), z);
 }
 
+// Non-temporal (streaming) accesses for data touched once.
+template <typename V> __device__ __forceinline__ void store_nt(V* p, V v) {
+  using Rl = typename real_of<V>::type;
+  Rl* q = reinterpret_cast<Rl*>(p);
+  __builtin_nontemporal_store(v.x, q);
+  __builtin_nontemporal_store(v.y, q + 1);
+}
+template <typename V> __device__ __forceinline__ V load_nt(const V* p) {
+  using Rl = typename real_of<V>::type;
+  const Rl* q = reinterpret_cast<const Rl*>(p);
+  V v;
+  v.x = __builtin_nontemporal_load(q);
+  v.y = __builtin_nontemporal_load(q + 1);
+  return v;
+}
+
 // ---------------------------------------------------------------- FFT
 __host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 

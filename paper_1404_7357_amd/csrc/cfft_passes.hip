@@ -29,13 +29,23 @@
 // Scheduling knobs (compile-time): minimum waves per SIMD requested from the
 // register allocator for the two passes (0 = compiler's choice), whether the
 // column pass fetches the next term's column while transforming the current
-// one (costs one register array), and the widest FP64 column tile in bytes
-// per row.
+// one (costs one register array), whether it writes the table with
+// non-temporal stores (the table is not read again by this path, and keeping
+// it out of the caches leaves them to the intermediates and inputs), whether
+// it reads the intermediates with non-temporal loads (they then bypass the
+// memory-side cache that still holds them from the row pass: slower), and
+// the widest FP64 column tile in bytes per row.
 #ifndef CFFT_ROW_MIN_WAVES
 #define CFFT_ROW_MIN_WAVES 0
 #endif
 #ifndef CFFT_COL_PREFETCH
 #define CFFT_COL_PREFETCH 0
+#endif
+#ifndef CFFT_COL_NT_STORE
+#define CFFT_COL_NT_STORE 1
+#endif
+#ifndef CFFT_COL_NT_LOAD
+#define CFFT_COL_NT_LOAD 0
 #endif
 #ifndef CFFT_COL_MIN_WAVES
 #define CFFT_COL_MIN_WAVES 0
@@ -310,7 +320,10 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
     if constexpr (!CFFT_COL_PREFETCH) {
       const V* src = col0 + (size_t)(a.order - b) * plane;
 #pragma unroll
-      for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
+      for (int r = 0; r < R; ++r) {
+        if constexpr (CFFT_COL_NT_LOAD) nxt[r] = load_nt(src + (size_t)(t + T * r) * a.nx);
+        else nxt[r] = src[(size_t)(t + T * r) * a.nx];
+      }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -342,7 +355,8 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
     const int j2 = t + T * r;
     double2 v = cmul(Z[r], a.scale);
     if ((j1 + j2) & 1) v = make_double2(-v.x, -v.y);
-    dst[(size_t)j2 * a.nx] = from_d<V>(v);
+    if constexpr (CFFT_COL_NT_STORE) store_nt(dst + (size_t)j2 * a.nx, from_d<V>(v));
+    else dst[(size_t)j2 * a.nx] = from_d<V>(v);
   }
 }
 
