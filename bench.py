@@ -126,6 +126,23 @@ def _kernel_times(st, steps):
     return out
 
 
+def _copy_rate(torch, mib=1024, reps=20):
+    """Device-to-device copy (read + write) GB/s on this GPU: the practical ceiling for a streaming pass."""
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
 def _green_flops():
     """FP64 flops of one Green's-function launch (512^2 grid) from the committed rocprofv3 counters, if current."""
     path = os.path.join(ROOT, "profiles", "traffic_c2_fp64.json")
@@ -292,6 +309,9 @@ def main():
     sec = _time_steps(torch, st.run, args.steps, args.warmup)
     value = st.entries() / sec
     _log(f"fp64 step {sec * 1e3:.3f} ms -> {value:.4e} entries/s")
+    # the row and column passes alone (cfft_tabulate on resident G and spectra)
+    sec_tab = _time_steps(torch, lambda: st.tab.tabulate(st.spec, st.g, st.pairs, out=st.z), args.steps, 2)
+    passes_only = {"ms": sec_tab * 1e3, "value": st.entries() / sec_tab, "unit": "entries/s"}
     kernels = _kernel_times(st, args.steps)
     green_alu = _green_alu(st, args.steps)
     torch.cuda.synchronize()
@@ -320,9 +340,11 @@ def main():
     dom = max(("row_pass", "col_pass"), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
     avg_s = kernels[dom]["avg_ms"] * 1e-3
     achieved = launch_bytes[dom] / avg_s / 1e9
+    copy_gbs = _copy_rate(torch)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(dom, launch_bytes[dom]),
-                "algorithmic_bytes_per_launch": launch_bytes[dom]}
+                "algorithmic_bytes_per_launch": launch_bytes[dom],
+                "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
     for k in ("row_pass", "col_pass"):
         kernels[k]["pairs_per_launch"] = per_launch[k]
         kernels[k]["algorithmic_bytes_per_launch"] = launch_bytes[k]
@@ -336,7 +358,7 @@ def main():
                       "order": P, "gamma": wl.grids[0].gamma, "eps_r": wl.substrates[0].eps_r,
                       "tan_delta": wl.substrates[0].tan_delta, "h": wl.substrates[0].h,
                       "precision": "fp64"},
-           "roofline": roofline, "green_fp64": green_alu, "kernels_ms": kernels}
+           "roofline": roofline, "green_fp64": green_alu, "passes_only": passes_only, "kernels_ms": kernels}
     st.tab.close()
     del st
 
@@ -353,8 +375,10 @@ def main():
         wlm = c2_rooftop_512(precision=MIXED)
         stm = Step(wlm, torch)
         secm = _time_steps(torch, stm.run, args.steps, args.warmup)
+        secm_tab = _time_steps(torch, lambda: stm.tab.tabulate(stm.spec, stm.g, stm.pairs, out=stm.z), args.steps, 2)
         km = _kernel_times(stm, args.steps)
         mixed = {"value": stm.entries() / secm, "ms_per_step": secm * 1e3, "dtype": "fp32 FFT / fp64 rest",
+                 "passes_only": {"ms": secm_tab * 1e3, "value": stm.entries() / secm_tab, "unit": "entries/s"},
                  "kernels_ms": km}
         if sample is not None:
             idx, ref = sample

@@ -142,6 +142,27 @@ def test_shapes_fp64_and_mixed(nx, ny):
         _full_case(f"{nx}x{ny} prec={prec}", grid, Substrate(2.2, 0.0, 0.05), basis, q, pairs, tol)
 
 
+@pytest.mark.parametrize("nx,ny", [(2048, 16), (16, 2048), (1024, 32), (32, 1024)])
+def test_long_axes_sampled(nx, ny):
+    """Transform lengths 1024 and 2048 along either axis (block-wide exchanges,
+    two-level twiddle tables), FP64 and mixed, at sampled outputs including
+    the table corners and Delta = 0."""
+    rng = np.random.default_rng(nx * 3 + ny)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 1), (1, 1), (1, 0), (0, 0), (0, 1)]
+    idx = _sample_idx(nx, ny, 40, nx + ny)
+    for prec, tol in [(FP64, 1e-10), (MIXED, 1e-5)]:
+        grid = Grid(nx, ny, 8 * K0, 6 * K0, K0, precision=prec)
+        sub = Substrate(3.0, 0.001, 0.07)
+        _say(f"tabulate sampled {nx}x{ny} prec={prec}")
+        _, _, z = _run(grid, sub, basis, q, pairs)
+        ref = co.tabulate(grid, sub, basis, q, np.asarray(pairs), out_idx=idx, workers=8)
+        zs = z.reshape(len(pairs), -1)[:, idx]
+        err = (np.abs(zs - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
+        assert err < tol, (nx, ny, prec, err)
+
+
 def test_many_pairs_chunked(monkeypatch):
     """More pairs than one launch holds, with a forced small chunk (ragged last chunk)."""
     monkeypatch.setenv("CFFT_PAIR_CHUNK", "3")
