@@ -252,16 +252,19 @@ def taylor_poly(z, order):
 # --------------------------------------------------------------------------
 # The table: direct sum per output displacement (eqs. FFT, taylors, fftexp)
 # --------------------------------------------------------------------------
-def direct_sum(integrands, kx, ky, dx, dy, gamma, order, dkx, dky, block=32, workers=1):
+def direct_sum(integrands, kx, ky, dx, dy, gamma, order, dkx, dky, block=32, workers=1, truncation=0):
     """Z^(P)_p(Delta_q) for every integrand p and output displacement q.
 
     Rectangle-rule discretisation of eq. FFT with E_I replaced by its Taylor
     polynomial of order P (eqs. taylors, fftexp):
         Z(Delta) = dkx dky / (4 pi^2) * sum_n I(k_n) exp(-i k_n.Delta)
                                           * T_P(gamma k_n.Delta)
-    order < 0 means the untruncated exponential (E_I itself).  The sum over
-    samples is a matrix product with the [samples x outputs] kernel matrix,
-    built one block of outputs at a time.
+    order < 0 means the untruncated exponential (E_I itself).  truncation = 1
+    selects the tensor-product variant (not in the paper): on the ray contour
+    E_I = exp(gamma kx Dx) exp(gamma ky Dy) exactly, and each factor is
+    replaced by its own Taylor polynomial, T_P(gamma kx Dx) T_P(gamma ky Dy).
+    The sum over samples is a matrix product with the [samples x outputs]
+    kernel matrix, built one block of outputs at a time.
 
     integrands: [npairs][ns] complex; kx, ky: [ns] real sample coordinates;
     dx, dy: [nq] output displacements.  Returns [npairs][nq] complex128.
@@ -285,12 +288,16 @@ def direct_sum(integrands, kx, ky, dx, dy, gamma, order, dkx, dky, block=32, wor
         acc = np.zeros((integrands.shape[0], q1 - q0), dtype=np.complex128)
         for s0 in range(0, ns, sstep):
             s1 = min(ns, s0 + sstep)
-            arg = np.outer(kx[s0:s1], dx[q0:q1]) + np.outer(ky[s0:s1], dy[q0:q1])   # k.Delta
+            argx = np.outer(kx[s0:s1], dx[q0:q1])
+            argy = np.outer(ky[s0:s1], dy[q0:q1])
+            arg = argx + argy                                                       # k.Delta
             kern = np.exp(-1j * arg)
-            if order >= 0:
-                kern *= taylor_poly(gamma * arg, order)
-            else:
+            if order < 0:
                 kern *= np.exp(gamma * arg)
+            elif truncation == 1:
+                kern *= taylor_poly(gamma * argx, order) * taylor_poly(gamma * argy, order)
+            else:
+                kern *= taylor_poly(gamma * arg, order)
             acc += integrands[:, s0:s1] @ kern
         out[:, q0:q1] = scale * acc
 
@@ -344,7 +351,8 @@ def tabulate(grid, substrate, basis, q, pairs, out_idx=None, order=None, workers
         dx, dy = dx[out_idx], dy[out_idx]
     dkx = 2.0 * grid.kx_max / grid.nx
     dky = 2.0 * grid.ky_max / grid.ny
-    z = direct_sum(integ, kx, ky, dx, dy, grid.gamma, order, dkx, dky, workers=workers)
+    z = direct_sum(integ, kx, ky, dx, dy, grid.gamma, order, dkx, dky, workers=workers,
+                   truncation=getattr(grid, "truncation", 0))
     if out_idx is None:
         z = z.reshape(len(pairs), grid.ny, grid.nx)
     return z
@@ -368,7 +376,8 @@ def tabulate_from_factors(grid, pairs, g, mt, mh, out_idx=None, order=None, work
         dx, dy = dx[out_idx], dy[out_idx]
     dkx = 2.0 * grid.kx_max / grid.nx
     dky = 2.0 * grid.ky_max / grid.ny
-    z = direct_sum(integ, kx, ky, dx, dy, grid.gamma, order, dkx, dky, workers=workers)
+    z = direct_sum(integ, kx, ky, dx, dy, grid.gamma, order, dkx, dky, workers=workers,
+                   truncation=getattr(grid, "truncation", 0))
     if out_idx is None:
         z = z.reshape(len(pairs), grid.ny, grid.nx)
     return z
@@ -506,7 +515,8 @@ def loss_gradient(grid, substrate, basis, q, pairs, pts, z_target, workers=1):
     nq = len(pts)
 
     def lookup_of(integ):
-        zz = direct_sum(integ, kx, ky, dx, dy, grid.gamma, grid.order, dkx, dky, workers=workers)
+        zz = direct_sum(integ, kx, ky, dx, dy, grid.gamma, grid.order, dkx, dky, workers=workers,
+                        truncation=getattr(grid, "truncation", 0))
         out = np.zeros((integ.shape[0], nq), dtype=np.complex128)
         for i, (_, _, wgt) in enumerate(corners):
             out += wgt * zz[:, i * nq:(i + 1) * nq]

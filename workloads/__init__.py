@@ -33,6 +33,8 @@ CONTOUR_RAY = 0
 CONTOUR_PARABOLIC = 1
 FP64 = 0
 MIXED = 1
+TRUNC_TOTAL = 0    # terms a + b <= P of the Taylor series of E_I (eq. fftarry)
+TRUNC_TENSOR = 1   # terms a <= P and b <= P (product of per-axis polynomials)
 
 BASIS_DTYPE = np.dtype([("kind", np.int32), ("pad", np.int32), ("cx", np.float64),
                         ("cy", np.float64), ("a", np.float64), ("b", np.float64)])
@@ -100,6 +102,7 @@ class Grid:
     contour: int = CONTOUR_RAY
     beta_end: float = 0.0
     precision: int = FP64
+    truncation: int = TRUNC_TOTAL
 
 
 @dataclasses.dataclass
