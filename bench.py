@@ -235,6 +235,37 @@ def _adjoint_ratio(torch, steps, warmup):
             "queries": int(pts.shape[0])}
 
 
+def _tensor_leg(torch, steps, warmup, precision, n_out):
+    """The 512^2 workload with the tensor-product truncation (one intermediate
+    per pair; not in the paper), with its error against the oracle's tensor
+    mode on n_out sampled outputs per pair."""
+    import dataclasses
+
+    import numpy as np
+
+    from oracle import cfft_oracle as co
+    from workloads import TRUNC_TENSOR, c2_rooftop_512
+    wl = c2_rooftop_512(precision=precision)
+    wl = dataclasses.replace(wl, grids=[dataclasses.replace(wl.grids[0], truncation=TRUNC_TENSOR)])
+    st = Step(wl, torch)
+    sec = _time_steps(torch, st.run, steps, warmup)
+    sec_tab = _time_steps(torch, lambda: st.tab.tabulate(st.spec, st.g, st.pairs, out=st.z), steps, 2)
+    km = _kernel_times(st, steps)
+    torch.cuda.synchronize()
+    z = st.z.cpu().numpy().reshape(len(wl.pairs), -1)
+    st.tab.close()
+    grid, sub = wl.grids[0], wl.substrates[0]
+    rng = np.random.default_rng(77)
+    idx = np.unique(np.concatenate([rng.choice(grid.nx * grid.ny, n_out, replace=False),
+                                    [(grid.ny // 2) * grid.nx + grid.nx // 2]]))
+    ref = co.tabulate(grid, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=min(16, os.cpu_count() or 1))
+    err = float((np.abs(z[:, idx] - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+    return {"value": st.entries() / sec, "ms_per_step": sec * 1e3,
+            "passes_only": {"ms": sec_tab * 1e3, "value": st.entries() / sec_tab, "unit": "entries/s"},
+            "rel_err_vs_oracle": err, "oracle_sample": f"{len(idx)} outputs x {len(wl.pairs)} pairs",
+            "dtype": "f64" if precision == 0 else "fp32 FFT / fp64 rest", "kernels_ms": km}
+
+
 def _sweep(torch, steps, warmup):
     """Frequency sweep, 8 uneven grids x 16 pairs (mixed), eager and as one replayed HIP graph."""
     from paper_1404_7357_amd import Tabulator
@@ -387,6 +418,10 @@ def main():
         stm.tab.close()
         del stm
         out["mixed"] = mixed
+        _log("tensor-product truncation legs (FP64, mixed)")
+        n_out = 0 if args.no_cpu_baseline else 64
+        out["tensor"] = {"fp64": _tensor_leg(torch, args.steps, args.warmup, 0, max(n_out, 4)),
+                         "mixed": _tensor_leg(torch, args.steps, args.warmup, MIXED, max(n_out, 4))}
         _log("sweep leg (8 grids, one graph)")
         out["sweep"] = _sweep(torch, max(3, args.steps // 5), 2)
         _log("adjoint leg (1024^2, 16 pairs, 4096 lookups)")

@@ -66,6 +66,15 @@ typedef enum {
 } cfft_status_t;
 
 enum { CFFT_CONTOUR_RAY = 0, CFFT_CONTOUR_PARABOLIC = 1 };
+/* Truncation of the Taylor series of E_I (eq. taylors):
+ *   TOTAL : terms (gamma kx Dx)^a (gamma ky Dy)^b / (a! b!) with a + b <= P,
+ *           the N_t = (P+1)(P+2)/2 terms of eq. fftarry;
+ *   TENSOR: every term with a <= P and b <= P.  On the ray contour E_I is
+ *           exactly exp(gamma kx Dx) exp(gamma ky Dy), and this truncation is
+ *           the product of the two per-axis Taylor polynomials: a superset of
+ *           TOTAL's terms, and one intermediate array per pair between the
+ *           row and column passes instead of P+1.  Not in the paper. */
+enum { CFFT_TRUNC_TOTAL = 0, CFFT_TRUNC_TENSOR = 1 };
 enum { CFFT_FP64 = 0, CFFT_MIXED = 1 };
 enum { CFFT_ROOFTOP_X = 0, CFFT_ROOFTOP_Y = 1, CFFT_COSINE_X = 2, CFFT_COSINE_Y = 3 };
 /* CHECK_FINITE: scan every output for NaN/Inf and report CFFT_ERR_NONFINITE
@@ -81,10 +90,10 @@ typedef struct {
   double k0;             /* free-space wavenumber 2 pi f/f0, > 0 */
   double gamma;          /* contour height ratio beta_I/beta_R (eq. ratioNew), > 0 */
   int32_t contour;       /* CFFT_CONTOUR_RAY; PARABOLIC is rejected (UNSUPPORTED) */
-  int32_t order;         /* Taylor order P >= 0 of eq. taylors, total degree; P <= 7 */
+  int32_t order;         /* Taylor order P >= 0 of eq. taylors, 0 <= P <= 7 */
   double beta_end;       /* end of the parabolic deformation (unused for RAY) */
   int32_t precision;     /* CFFT_FP64 (complex128 everywhere) or CFFT_MIXED */
-  int32_t reserved;      /* must be 0 */
+  int32_t truncation;    /* CFFT_TRUNC_TOTAL (0, the paper's) or CFFT_TRUNC_TENSOR */
 } cfft_grid_desc_t;
 
 /* One elementary basis function (40 bytes).  Sec. III-A: rooftops with an

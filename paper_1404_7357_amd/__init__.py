@@ -18,7 +18,8 @@ import math
 import torch
 
 from . import _lib
-from ._lib import (CONTOUR_RAY, FLAG_AUTOTUNE, FLAG_CHECK_FINITE, FP64, MIXED, CfftError, Plan, cfft_backward,  # noqa: F401
+from ._lib import (CONTOUR_RAY, FLAG_AUTOTUNE, FLAG_CHECK_FINITE, FP64, MIXED, TRUNC_TENSOR, TRUNC_TOTAL,  # noqa: F401
+                   CfftError, Plan, cfft_backward,
                    cfft_lookup, cfft_lookup_backward, cfft_tabulate, mbf_spectra, slab_green_eval)
 
 _lib.load()

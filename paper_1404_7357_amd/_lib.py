@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "ALLOC", 4: "HIP
 
 CONTOUR_RAY, CONTOUR_PARABOLIC = 0, 1
 FP64, MIXED = 0, 1
+TRUNC_TOTAL, TRUNC_TENSOR = 0, 1
 FLAG_CHECK_FINITE = 1
 FLAG_AUTOTUNE = 2
 
@@ -38,7 +39,7 @@ class GridDesc(ctypes.Structure):
                 ("k0", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("contour", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("beta_end", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("truncation", ctypes.c_int32)]
 
 
 class Basis(ctypes.Structure):
@@ -110,7 +111,7 @@ def grid_desc(g) -> GridDesc:
     """GridDesc from any object with the cfft_grid_desc_t field names."""
     return GridDesc(int(g.nx), int(g.ny), float(g.kx_max), float(g.ky_max), float(g.k0), float(g.gamma),
                     int(getattr(g, "contour", CONTOUR_RAY)), int(g.order), float(getattr(g, "beta_end", 0.0)),
-                    int(g.precision), 0)
+                    int(g.precision), int(getattr(g, "truncation", TRUNC_TOTAL)))
 
 
 def basis_array(records):

@@ -248,6 +248,7 @@ PassParams pass_params(const GridState& gs) {
   p.y = gs.y;
   p.gamma = gs.d.gamma;
   p.order = gs.d.order;
+  p.tensor = gs.d.truncation == CFFT_TRUNC_TENSOR ? 1 : 0;
   p.precision = gs.d.precision;
   return p;
 }
@@ -522,7 +523,8 @@ cfft_status_t c_fft_plan(const cfft_grid_desc_t* grids, int32_t ngrids, int32_t 
       return fail(CFFT_ERR_INVALID_ARG, "grid %d: order %d outside [0, %d]", i, g.order, kMaxOrder);
     if (g.precision != CFFT_FP64 && g.precision != CFFT_MIXED)
       return fail(CFFT_ERR_INVALID_ARG, "grid %d: unknown precision %d", i, g.precision);
-    if (g.reserved != 0) return fail(CFFT_ERR_INVALID_ARG, "grid %d: reserved must be 0", i);
+    if (g.truncation != CFFT_TRUNC_TOTAL && g.truncation != CFFT_TRUNC_TENSOR)
+      return fail(CFFT_ERR_INVALID_ARG, "grid %d: truncation %d is neither TOTAL nor TENSOR", i, g.truncation);
     if (g.contour == CFFT_CONTOUR_PARABOLIC)
       return fail(CFFT_ERR_UNSUPPORTED, "grid %d: the parabolic contour is not implemented (use RAY)", i);
     if (g.contour != CFFT_CONTOUR_RAY) return fail(CFFT_ERR_INVALID_ARG, "grid %d: unknown contour %d", i, g.contour);
@@ -650,7 +652,7 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   const PassParams pp = pass_params(gs);
   const size_t n = (size_t)gs.x.n * gs.y.n;
   const size_t cbytes = pp.precision == CFFT_FP64 ? 16 : 8;
-  const size_t per_pair = (size_t)(pp.order + 1) * n * cbytes;
+  const size_t per_pair = (size_t)inter_slots(pp) * n * cbytes;
   const long long limit_mb = env_ll("CFFT_WORKSPACE_MB", 16384);
   long long chunk = std::max<long long>(1, (limit_mb << 20) / (long long)per_pair);
   chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
@@ -843,7 +845,7 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   if (st != CFFT_OK) return st;
   const PassParams pp = pass_params(gs);
   const size_t n = (size_t)gs.x.n * gs.y.n;
-  const size_t per_pair = (size_t)(pp.order + 1) * n * 16 + n * 16;   // intermediates + gH
+  const size_t per_pair = (size_t)inter_slots(pp) * n * 16 + n * 16;   // intermediates + gH
   const long long limit_mb = env_ll("CFFT_WORKSPACE_MB", 16384);
   long long chunk = std::max<long long>(1, (limit_mb << 20) / (long long)per_pair);
   chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
@@ -865,7 +867,7 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   double2* rowacc = (double2*)(w2 + b_gg + b_gs);
   double* partial = (double*)(w2 + b_gg + b_gs + b_row);
   double2* inter = (double2*)plan->ws;
-  double2* gi = (double2*)((char*)plan->ws + (size_t)(pp.order + 1) * n * 16 * chunk);
+  double2* gi = (double2*)((char*)plan->ws + (size_t)inter_slots(pp) * n * 16 * chunk);
   std::vector<int> pm(npairs), pn(npairs);
   for (int i = 0; i < npairs; ++i) {
     pm[i] = pairs[2 * i];

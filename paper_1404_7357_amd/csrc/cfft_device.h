@@ -126,13 +126,15 @@ template <typename V> __device__ __forceinline__ V load_nt(const V* p) {
 // ---------------------------------------------------------------- FFT
 __host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
-// LDS slot of exchange element i: one pad entry after every 8 elements.  A
+// LDS slot of exchange element i: one pad entry after every 2^S elements.  A
 // radix-8 stage writes 8 consecutive elements per thread (stride 128 B for
-// complex128), which without padding puts every other thread on the same
-// banks; the pad spreads those writes over all 64 banks.
-__host__ __device__ constexpr int lds_slot(int i) { return i + (i >> 3); }
+// complex128), which without padding puts many lanes of one LDS access on
+// the same banks; the pad spreads them.  The best S depends on how the lanes
+// of a transform sit in a wave (one transform per wave: S = 4; four
+// interleaved column transforms: S = 3 with a per-column offset).
+template <int S = 3> __host__ __device__ constexpr int lds_slot(int i) { return i + (i >> S); }
 // LDS entries needed by one length-N exchange buffer.
-__host__ __device__ constexpr int lds_len(int n) { return n + n / 8; }
+template <int S = 3> __host__ __device__ constexpr int lds_len(int n) { return n + (n >> S); }
 
 // In-register forward DFT of 2, 4 or 8 points (omega = exp(-2 pi i / n)).
 template <typename V> __device__ __forceinline__ void dft2(V& a, V& b) {
@@ -221,7 +223,7 @@ template <bool WAVE> __device__ __forceinline__ void exchange_sync() {
 // L is the length of the sub-transforms already done.  Non-final stages
 // exchange through `lds` (lds_len(N) entries, padded slots); the final stage leaves the outputs in
 // registers in the same stride-T order.
-template <typename V, int N, int R, int RHO, bool LAST, bool WAVE>
+template <typename V, int N, int R, int RHO, bool LAST, bool WAVE, int PS>
 __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* ltw, int t, int L) {
   constexpr int T = N / R;
   constexpr int BPT = R / RHO;
@@ -266,13 +268,13 @@ __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* ltw, 
     } else {
       const int base = (i - k) * RHO + k;
 #pragma unroll
-      for (int q = 0; q < RHO; ++q) lds[lds_slot(base + q * L)] = y[q];
+      for (int q = 0; q < RHO; ++q) lds[lds_slot<PS>(base + q * L)] = y[q];
     }
   }
   if constexpr (!LAST) {
     exchange_sync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = lds[lds_slot(t + T * r)];
+    for (int r = 0; r < R; ++r) x[r] = lds[lds_slot<PS>(t + T * r)];
     exchange_sync<WAVE>();
   }
 }
@@ -282,7 +284,7 @@ __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* ltw, 
 // multiple of 3, then radix-8 stages.  All threads of the block must call
 // it (it contains block barriers), unless WAVE: then the N/R threads of each
 // transform must be lanes of one wave, and only they synchronise.
-template <typename V, int N, int R, bool WAVE = false>
+template <typename V, int N, int R, bool WAVE = false, int PS = 3>
 __device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* ltw, int t) {
   static_assert(R == 8 || R == 16, "8 or 16 points per thread");
   static_assert(!WAVE || N / R <= 64, "a wave-local transform needs at most 64 threads");
@@ -295,30 +297,30 @@ __device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* ltw, int
   constexpr int REM = LOG % 3;
   int L = 1;
   if constexpr (REM == 1) {
-    stockham_stage<V, N, R, 2, NR8 == 0, WAVE>(x, lds, ltw, t, L);
+    stockham_stage<V, N, R, 2, NR8 == 0, WAVE, PS>(x, lds, ltw, t, L);
     L *= 2;
   } else if constexpr (REM == 2) {
-    stockham_stage<V, N, R, 4, NR8 == 0, WAVE>(x, lds, ltw, t, L);
+    stockham_stage<V, N, R, 4, NR8 == 0, WAVE, PS>(x, lds, ltw, t, L);
     L *= 4;
   }
   if constexpr (NR8 >= 1) {
     if constexpr (NR8 >= 2) {
 #pragma unroll
       for (int s = 0; s < NR8 - 1; ++s) {
-        stockham_stage<V, N, R, 8, false, WAVE>(x, lds, ltw, t, L);
+        stockham_stage<V, N, R, 8, false, WAVE, PS>(x, lds, ltw, t, L);
         L *= 8;
       }
     }
-    stockham_stage<V, N, R, 8, true, WAVE>(x, lds, ltw, t, L);
+    stockham_stage<V, N, R, 8, true, WAVE, PS>(x, lds, ltw, t, L);
   }
 }
 
 // Inverse (unnormalised) DFT: conj(DFT(conj x)).
-template <typename V, int N, int R, bool WAVE = false>
+template <typename V, int N, int R, bool WAVE = false, int PS = 3>
 __device__ __forceinline__ void fft_inverse(V (&x)[R], V* lds, const V* ltw, int t) {
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = cconj(x[r]);
-  fft_forward<V, N, R, WAVE>(x, lds, ltw, t);
+  fft_forward<V, N, R, WAVE, PS>(x, lds, ltw, t);
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = cconj(x[r]);
 }

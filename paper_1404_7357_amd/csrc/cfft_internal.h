@@ -60,7 +60,11 @@ struct PassParams {
   double gamma;
   int order;
   int precision;      // 0 FP64, 1 MIXED
+  int tensor;         // 1: tensor-product truncation (one intermediate per pair)
 };
+
+// Intermediate arrays per pair between the row and column passes.
+inline int inter_slots(const PassParams& p) { return p.tensor ? 1 : p.order + 1; }
 
 // Launchers; all return hipSuccess or the launch error.
 hipError_t launch_green(const GreenParams& p, double2* g, hipStream_t s);

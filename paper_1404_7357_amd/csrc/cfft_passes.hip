@@ -7,16 +7,18 @@
 //   S_c(j1,n2) = sum_{a<=c} Dx(j1)^a/a! DFT_n1[ s(n1) (gamma kx)^a H(n1,n2) ](j1)
 //   H = M_m . G . M#_n
 // which is the total-degree-P Taylor expansion of E_I with every
-// displacement factor moved outside its transform.
+// displacement factor moved outside its transform.  With the tensor-product
+// truncation (a <= P and b <= P, not in the paper) every column term reads
+// the full row sum S_P, so only S_P is stored.
 //
-// Row pass: one block handles one (row n2, pair) [or several short rows]; it
-// assembles H from G and the spectra (FP64), then for a = 0..P multiplies by
-// gamma kx, runs an in-register/LDS Stockham FFT along n1, folds the result
-// into the running partial sum S (FP64 accumulators) and writes S_a.
+// Row pass: a block assembles H of one row from G and the spectra (FP64),
+// then for a = 0..P multiplies by gamma kx, runs an in-register/LDS Stockham
+// FFT along n1, folds the result into the running partial sum S (FP64
+// accumulators) and writes S_a (S_P only, tensor truncation).
 // Column pass: one block handles a tile of C adjacent columns of one pair;
-// it stages each S_{P-b} tile through LDS (coalesced rows of C entries),
-// FFTs every column along n2, accumulates Dy^b/b! times the result, applies
-// the Appendix scale and writes the table through an LDS transpose.
+// each wave loads whole C-column row segments of S_{P-b} straight into
+// registers, FFTs every column along n2 (LDS exchanges), accumulates
+// Dy^b/b! times the result in FP64 and writes the scaled table.
 // The FFT precision is FP64 (CFFT_FP64) or FP32 (CFFT_MIXED); every
 // recombination weight and accumulator is FP64.
 #include <algorithm>
@@ -47,6 +49,12 @@
 #ifndef CFFT_COL_NT_LOAD
 #define CFFT_COL_NT_LOAD 0
 #endif
+#ifndef CFFT_ROW_PAD_SHIFT
+#define CFFT_ROW_PAD_SHIFT 0
+#endif
+#ifndef CFFT_COL_LDP_EXTRA
+#define CFFT_COL_LDP_EXTRA 4
+#endif
 #ifndef CFFT_COL_MIN_WAVES
 #define CFFT_COL_MIN_WAVES 0
 #endif
@@ -56,6 +64,12 @@
 
 namespace cfft {
 
+// LDS padding of the row transforms: one pad slot per 2^row_pad<V>() elements
+// (16-byte elements: every 16; 8-byte elements: every 8).
+template <typename V> __host__ __device__ constexpr int row_pad() {
+  return CFFT_ROW_PAD_SHIFT > 0 ? CFFT_ROW_PAD_SHIFT : (sizeof(V) == 16 ? 4 : 3);
+}
+
 template <int N> struct RowCfg {
   static constexpr int R = 8;
   static constexpr int T = N / R;
@@ -64,6 +78,7 @@ template <int N> struct RowCfg {
 };
 
 struct RowArgs {
+  int tensor;   // tensor-product truncation: only S_P is stored, in slot 0
   const double2* g;
   const double2* spec;
   void* inter;
@@ -84,7 +99,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
   using Cfg = RowCfg<N>;
   constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
   using Rl = typename real_of<V>::type;
-  __shared__ V lds[ROWS * lds_len(N)];
+  __shared__ V lds[ROWS * lds_len<row_pad<V>()>(N)];
   __shared__ V ltw[TwLds<N>::LEN];
   load_twiddles<V, N>(ltw, (const V*)a.tw, threadIdx.x, Cfg::THREADS);
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -118,7 +133,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
   double2 S[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
-  V* my_lds = lds + grp * lds_len(N);
+  V* my_lds = lds + grp * lds_len<row_pad<V>()>(N);
   __syncthreads();   // twiddle tables ready
   for (int ao = 0; ao <= a.order; ++ao) {
     if (ao > 0) {
@@ -131,8 +146,10 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
     V x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = f[r];
-    fft_forward<V, N, R, (T <= 64)>(x, my_lds, ltw, t);
-    V* dst = inter + (((size_t)pair * (a.order + 1) + ao) * a.ny + (valid ? n2 : 0)) * N;
+    fft_forward<V, N, R, (T <= 64), row_pad<V>()>(x, my_lds, ltw, t);
+    const bool keep = !a.tensor || ao == a.order;
+    const int nsl = a.tensor ? 1 : a.order + 1;
+    V* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + (valid ? n2 : 0)) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       // Dx(j1)^a / a!, rebuilt per term (cheaper than keeping it live)
@@ -141,7 +158,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
       for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
-      if (valid) dst[t + T * r] = from_d<V>(S[r]);
+      if (valid && keep) dst[t + T * r] = from_d<V>(S[r]);
     }
   }
 }
@@ -154,6 +171,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
 // own basis MBF n, H = A_x Mx#_n + A_y My#_n.  That reads (5 + 2 NPW)/NPW
 // input arrays per pair instead of 7.
 struct RowGArgs {
+  int tensor;
   const double2* g;
   const double2* spec;
   void* inter;
@@ -184,7 +202,7 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
   constexpr int T = Cfg::T, R = Cfg::R;
   using Rl = typename real_of<V>::type;
   __shared__ double2 ax[N], ay[N];
-  __shared__ V lds[NPW * lds_len(N)];
+  __shared__ V lds[NPW * lds_len<row_pad<V>()>(N)];
   __shared__ V ltw[TwLds<N>::LEN];
   load_twiddles<V, N>(ltw, (const V*)a.tw, threadIdx.x, Cfg::THREADS);
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -230,7 +248,7 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
   double2 S[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
-  V* my_lds = lds + w * lds_len(N);
+  V* my_lds = lds + w * lds_len<row_pad<V>()>(N);
   V* inter = (V*)a.inter;
   for (int ao = 0; ao <= a.order; ++ao) {
     if (ao > 0) {
@@ -243,8 +261,10 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
     V x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = f[r];
-    fft_forward<V, N, R, (T <= 64)>(x, my_lds, ltw, t);
-    V* dst = inter + (((size_t)pair * (a.order + 1) + ao) * a.ny + n2) * N;
+    fft_forward<V, N, R, (T <= 64), row_pad<V>()>(x, my_lds, ltw, t);
+    const bool keep = !a.tensor || ao == a.order;
+    const int nsl = a.tensor ? 1 : a.order + 1;
+    V* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + n2) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double dx = a.x0 + (t + T * r) * a.ddx;
@@ -252,12 +272,13 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
       for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
-      if (active) dst[t + T * r] = from_d<V>(S[r]);
+      if (active && keep) dst[t + T * r] = from_d<V>(S[r]);
     }
   }
 }
 
 struct ColArgs {
+  int tensor;   // every term reads slot 0 (the full row sum S_P)
   const void* inter;
   void* z;
   const void* tw;
@@ -276,7 +297,7 @@ struct ColArgs {
 template <int N, int C, int R> struct ColCfg {
   static constexpr int T = N / R;
   static constexpr int THREADS = C * T;
-  static constexpr int LDP = lds_len(N) + 2;
+  static constexpr int LDP = lds_len(N) + CFFT_COL_LDP_EXTRA;
 };
 
 template <typename V, int N, int C, int R>
@@ -299,7 +320,8 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
   const int t = threadIdx.x / C;
   const int j1 = tile * C + c;
   const size_t plane = (size_t)N * a.nx;
-  const V* col0 = (const V*)a.inter + (size_t)pair * (a.order + 1) * plane + j1;
+  const int nsl = a.tensor ? 1 : a.order + 1;
+  const V* col0 = (const V*)a.inter + (size_t)pair * nsl * plane + j1;
 
   double2 Z[R];
 #pragma unroll
@@ -309,7 +331,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
   // per term (a few multiplies) rather than kept live in registers.
   V nxt[R];
   if constexpr (CFFT_COL_PREFETCH) {
-    const V* src = col0 + (size_t)a.order * plane;
+    const V* src = col0 + (size_t)(a.tensor ? 0 : a.order) * plane;
 #pragma unroll
     for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
   }
@@ -318,7 +340,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
   for (int b = 0; b <= a.order; ++b) {
     V x[R];
     if constexpr (!CFFT_COL_PREFETCH) {
-      const V* src = col0 + (size_t)(a.order - b) * plane;
+      const V* src = col0 + (size_t)(a.tensor ? 0 : a.order - b) * plane;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (CFFT_COL_NT_LOAD) nxt[r] = load_nt(src + (size_t)(t + T * r) * a.nx);
@@ -334,7 +356,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
       x[r] = cscale(nxt[r], w);
     }
     if (CFFT_COL_PREFETCH && b < a.order) {
-      const V* src = col0 + (size_t)(a.order - b - 1) * plane;
+      const V* src = col0 + (size_t)(a.tensor ? 0 : a.order - b - 1) * plane;
 #pragma unroll
       for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
     }
@@ -369,7 +391,7 @@ __host__ __device__ constexpr int col_r(int) { return 8; }
 __host__ __device__ constexpr int col_tile_c(int ny, int bytes) {
   int c = CFFT_COL_ROW_BYTES / bytes;
   const int r = col_r(bytes);
-  while (c > 1 && (c * (lds_len(ny) + 2) * bytes > 81920 || c * (ny / r) > 512)) c /= 2;
+  while (c > 1 && (c * (lds_len(ny) + CFFT_COL_LDP_EXTRA) * bytes > 81920 || c * (ny / r) > 512)) c /= 2;
   return c;
 }
 
@@ -426,6 +448,7 @@ static hipError_t rowg_launch(const RowArgs& ra, hipStream_t s) {
   a.nx = ra.nx;
   a.ny = ra.ny;
   a.order = ra.order;
+  a.tensor = ra.tensor;
   a.kx0 = ra.kx0;
   a.dkx = ra.dkx;
   a.x0 = ra.x0;
@@ -488,6 +511,7 @@ hipError_t launch_row_pass(const PassParams& p, const double2* g, const double2*
   a.nx = p.x.n;
   a.ny = p.y.n;
   a.order = p.order;
+  a.tensor = p.tensor;
   a.npairs = npairs;
   a.kx0 = p.x.k_first;
   a.dkx = p.x.dk;
@@ -523,6 +547,7 @@ hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, v
   a.nx = p.x.n;
   a.ny = p.y.n;
   a.order = p.order;
+  a.tensor = p.tensor;
   a.npairs = npairs;
   a.ky0 = p.y.k_first;
   a.dky = p.y.dk;
@@ -541,8 +566,10 @@ hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, v
 // With h = conj(K sigma W) s(j1+j2) gZ, the adjoint of the table map is
 //   U_b(j1,n2) = IDFT_j2[ Dy^b/b! h ](n2),  V_c = sum_{b<=c} (gamma ky)^b U_b
 //   gH(n1,n2)  = s(n1+n2) sum_a (gamma kx)^a IDFT_j1[ Dx^a/a! V_{P-a} ](n1)
-// (unnormalised inverse DFTs; all weights are real).
+// (unnormalised inverse DFTs; all weights are real).  Tensor truncation:
+// V_{P-a} is replaced by V_P for every a, so only V_P is stored.
 struct AdjColArgs {
+  int tensor;   // only the full sum V_P is stored, in slot 0
   const double2* dz;
   double2* inter;
   const double2* tw;
@@ -592,18 +619,21 @@ __global__ void __launch_bounds__(C * (N / 8)) adj_col_kernel(AdjColArgs a) {
       x[r] = cscale(h0[r], cf[r]);
     }
     fft_inverse<double2, N, R>(x, my_lds, ltw, t);
-    double2* dst = a.inter + ((size_t)pair * (a.order + 1) + b) * plane + j1;
+    const bool keep = !a.tensor || b == a.order;
+    const int nsl = a.tensor ? 1 : a.order + 1;
+    double2* dst = a.inter + ((size_t)pair * nsl + (a.tensor ? 0 : b)) * plane + j1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int n2 = t + T * r;
       if (b > 0) pw[r] *= a.gamma * (a.ky0 + n2 * a.dky);
       acc[r] = cadd(acc[r], cscale(x[r], pw[r]));
-      dst[(size_t)n2 * a.nx] = acc[r];
+      if (keep) dst[(size_t)n2 * a.nx] = acc[r];
     }
   }
 }
 
 struct AdjRowArgs {
+  int tensor;
   const double2* inter;
   double2* gi;
   const double2* tw;
@@ -616,7 +646,7 @@ template <int N>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs a) {
   using Cfg = RowCfg<N>;
   constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
-  __shared__ double2 lds[ROWS * lds_len(N)];
+  __shared__ double2 lds[ROWS * lds_len<row_pad<double2>()>(N)];
   __shared__ double2 ltw[TwLds<N>::LEN];
   load_twiddles<double2, N>(ltw, a.tw, threadIdx.x, Cfg::THREADS);
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -634,11 +664,12 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
     cf[r] = 1.0;
     pw[r] = 1.0;
   }
-  double2* my_lds = lds + grp * lds_len(N);
+  double2* my_lds = lds + grp * lds_len<row_pad<double2>()>(N);
   __syncthreads();   // twiddle tables ready
   for (int ao = 0; ao <= a.order; ++ao) {
+    const int nsl = a.tensor ? 1 : a.order + 1;
     const double2* src =
-        a.inter + (((size_t)pair * (a.order + 1) + (a.order - ao)) * a.ny + (valid ? n2 : 0)) * N;
+        a.inter + (((size_t)pair * nsl + (a.tensor ? 0 : a.order - ao)) * a.ny + (valid ? n2 : 0)) * N;
     double2 x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -646,7 +677,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
       if (ao > 0) cf[r] *= (a.x0 + j1 * a.ddx) * a.rinv[ao];
       x[r] = valid ? cscale(src[j1], cf[r]) : make_double2(0.0, 0.0);
     }
-    fft_inverse<double2, N, R, (T <= 64)>(x, my_lds, ltw, t);
+    fft_inverse<double2, N, R, (T <= 64), row_pad<double2>()>(x, my_lds, ltw, t);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int n1 = t + T * r;
@@ -692,6 +723,7 @@ hipError_t launch_adj_col_pass(const PassParams& p, const double2* dz, int npair
   a.nx = p.x.n;
   a.ny = p.y.n;
   a.order = p.order;
+  a.tensor = p.tensor;
   a.npairs = npairs;
   a.ky0 = p.y.k_first;
   a.dky = p.y.dk;
@@ -713,6 +745,7 @@ hipError_t launch_adj_row_pass(const PassParams& p, const double2* inter, int np
   a.nx = p.x.n;
   a.ny = p.y.n;
   a.order = p.order;
+  a.tensor = p.tensor;
   a.npairs = npairs;
   a.kx0 = p.x.k_first;
   a.dkx = p.x.dk;

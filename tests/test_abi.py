@@ -40,6 +40,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.GridDesc) == 64
     assert ctypes.sizeof(L.Basis) == 40
     assert L.GridDesc.precision.offset == 56 and L.GridDesc.beta_end.offset == 48
+    assert L.GridDesc.truncation.offset == 60
     from workloads import BASIS_DTYPE
     assert BASIS_DTYPE.itemsize == 40
 
@@ -54,7 +55,7 @@ def _grid(**kw):
 
 @pytest.mark.parametrize("field,value", [("nx", 48), ("ny", 8), ("nx", 8192), ("gamma", 0.0), ("gamma", -1.0),
                                          ("order", -1), ("order", 8), ("kx_max", 0.0), ("k0", float("nan")),
-                                         ("precision", 7), ("contour", 9)])
+                                         ("precision", 7), ("contour", 9), ("truncation", 2), ("truncation", -1)])
 def test_plan_rejects_invalid_grids(field, value):
     L, lib = _lib()
     desc = (L.GridDesc * 1)(L.grid_desc(_grid(**{field: value})))

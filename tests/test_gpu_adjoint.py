@@ -26,9 +26,9 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _problem(n=64, m=2, seed=41, npts=32):
+def _problem(n=64, m=2, seed=41, npts=32, truncation=0):
     rng = np.random.default_rng(seed)
-    grid = Grid(n, n, 6 * K0, 6 * K0, K0)
+    grid = Grid(n, n, 6 * K0, 6 * K0, K0, truncation=truncation)
     sub = Substrate(2.2, 0.0, 0.05)
     basis = rooftop_lattice(2, 3)
     q = gaussian_coefficients(rng, m, basis.shape[0])
@@ -89,6 +89,26 @@ def test_gradient_vs_oracle():
     assert abs(de - o_de) < 1e-9 * max(abs(o_de), 1e-300), (de, o_de)
     assert abs(dh - o_dh) < 1e-9 * max(abs(o_dh), 1e-300), (dh, o_dh)
     assert np.abs(dq - o_dq).max() < 1e-9 * np.abs(o_dq).max()
+
+
+def test_tensor_truncation_gradient_vs_oracle_and_differences():
+    """Adjoint of the tensor-product truncation (one stored intermediate per
+    pair): against the oracle's gradient of the same mode and central
+    differences of the GPU forward."""
+    _say("adjoint tensor truncation 64^2")
+    grid, sub, basis, q, pairs, pts, zt = _problem(n=64, npts=24, seed=53, truncation=1)
+    loss, de, dh, dq = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt)
+    o_loss, o_de, o_dh, o_dq = co.loss_gradient(grid, sub, basis, q, np.array(pairs), pts, zt)
+    assert abs(loss - o_loss) < 1e-9 * abs(o_loss)
+    assert abs(de - o_de) < 1e-9 * abs(o_de), (de, o_de)
+    assert abs(dh - o_dh) < 1e-9 * abs(o_dh), (dh, o_dh)
+    assert np.abs(dq - o_dq).max() < 1e-9 * np.abs(o_dq).max()
+    step = 1e-6
+
+    def L(**kw):
+        return _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt, need_grad=False, **kw)[0]
+    fd_e = (L(eps=sub.eps_r + step) - L(eps=sub.eps_r - step)) / (2 * step)
+    assert abs(de - fd_e) < 1e-6 * abs(fd_e), (de, fd_e)
 
 
 def test_backward_many_pairs_chunked(monkeypatch):

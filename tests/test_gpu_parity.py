@@ -6,6 +6,7 @@ max|Z_oracle| per table (Sec. IV, error definition).  Bars: FP64 path
 recombination) 1e-5; Green's function and spectra 1e-12 (pure FP64
 evaluation, rounding only).
 """
+import dataclasses
 import math
 import sys
 
@@ -13,8 +14,8 @@ import numpy as np
 import pytest
 
 from oracle import cfft_oracle as co
-from workloads import (FP64, MIXED, Grid, Substrate, c1_single_cosine, c2_rooftop_512, gaussian_coefficients,
-                       rooftop_lattice)
+from workloads import (FP64, MIXED, TRUNC_TENSOR, Grid, Substrate, c1_single_cosine, c2_rooftop_512,
+                       gaussian_coefficients, rooftop_lattice)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -161,6 +162,39 @@ def test_long_axes_sampled(nx, ny):
         zs = z.reshape(len(pairs), -1)[:, idx]
         err = (np.abs(zs - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
         assert err < tol, (nx, ny, prec, err)
+
+
+@pytest.mark.parametrize("nx,ny,order", [(64, 32, 3), (16, 128, 2), (128, 16, 5), (32, 32, 0)])
+def test_tensor_truncation_full_grid(nx, ny, order):
+    """Tensor-product truncation (one intermediate per pair), FP64 and mixed,
+    whole table against the oracle's tensor mode."""
+    rng = np.random.default_rng(900 + nx + ny + order)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 1), (1, 0), (1, 1)]
+    for prec, tol in [(FP64, 1e-10), (MIXED, 1e-5)]:
+        grid = Grid(nx, ny, 9 * K0, 7 * K0, K0, order=order, precision=prec, truncation=TRUNC_TENSOR)
+        _full_case(f"tensor {nx}x{ny} P={order} prec={prec}", grid, Substrate(4.4, 0.002, 0.06), basis, q, pairs,
+                   tol)
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-10), (MIXED, 1e-5)])
+def test_tensor_truncation_c2_sampled(prec, tol):
+    """The 512^2 workload (16 pairs) with the tensor-product truncation, at
+    sampled outputs; the two truncations differ by far more than the tolerance."""
+    wl = c2_rooftop_512(precision=prec)
+    grid, sub = wl.grids[0], wl.substrates[0]
+    gt = dataclasses.replace(grid, truncation=TRUNC_TENSOR)
+    _say(f"c2 tensor prec={prec}")
+    _, _, z = _run(gt, sub, wl.basis, wl.q, wl.pairs.tolist())
+    idx = _sample_idx(grid.nx, grid.ny, 32, 12)
+    ref = co.tabulate(gt, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=8)
+    ref_total = co.tabulate(grid, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=8)
+    zs = z.reshape(len(wl.pairs), -1)[:, idx]
+    scale = np.abs(ref).max(axis=1)
+    err = (np.abs(zs - ref).max(axis=1) / scale).max()
+    assert err < tol, err
+    assert (np.abs(ref_total - ref).max(axis=1) / scale).max() > 10 * 1e-5   # modes told apart
 
 
 def test_many_pairs_chunked(monkeypatch):
