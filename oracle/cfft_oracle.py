@@ -7,7 +7,8 @@ design notes):
   * spatial Fourier transform F(k) = int f(r) exp(-i k.r) dr
   * displacement Delta = r_test - r_basis
   * free-space impedance eta0 = 1, lengths in lambda0, k0 = 2 pi f/f0
-  * ray contour: k_c = (1 + i gamma) k for every real sample k
+  * ray contour: k_c = (1 + i gamma) k for every real sample k; parabolic
+    contour: k_c = (1 + i g(beta)) k with g(beta) = gamma (1 - beta/beta_end)
 """
 from __future__ import annotations
 
@@ -54,6 +55,37 @@ def ray_contour(kx: np.ndarray, ky: np.ndarray, gamma: float):
     """
     s = 1.0 + 1j * gamma
     return s * kx, s * ky, s * s
+
+
+def parabolic_contour(kx: np.ndarray, ky: np.ndarray, gamma: float, beta_end: float):
+    """Parabolic deformation of the radial path (Sec. I and the caption of
+    Fig. 1: a parabolic contour whose height is set by gamma; Sec. II, eq.
+    spectral_contour: the path is beta_c = beta_R + i beta_I(beta_R)).
+
+    Reading: beta_I = gamma beta (1 - beta/beta_end) for beta < beta_end and
+    0 beyond (the path rejoins the real axis at beta_end, past every
+    surface-wave pole).  Each real sample k then moves to k_c = (1 + i g) k
+    with the local ratio g = beta_I/beta = gamma (1 - beta/beta_end) (eq.
+    ratioNew holds sample by sample), and the weight of eq. FFT is
+    W = (1 + i d beta_I/d beta)(1 + i g), which equals det(d k_c / d k).
+    Returns (kcx, kcy, W, g) with g per sample.
+    """
+    kx = np.asarray(kx, dtype=np.float64)
+    ky = np.asarray(ky, dtype=np.float64)
+    beta = np.hypot(kx, ky)
+    inside = beta < beta_end
+    g = np.where(inside, gamma * (1.0 - beta / beta_end), 0.0)
+    dbi = np.where(inside, gamma * (1.0 - 2.0 * beta / beta_end), 0.0)
+    s = 1.0 + 1j * g
+    return s * kx, s * ky, (1.0 + 1j * dbi) * s, g
+
+
+def grid_contour(kx, ky, grid):
+    """(kcx, kcy, W, g) of a grid's contour; g is gamma (ray) or per sample."""
+    if getattr(grid, "contour", 0) == 1:
+        return parabolic_contour(kx, ky, grid.gamma, grid.beta_end)
+    kcx, kcy, w = ray_contour(kx, ky, grid.gamma)
+    return kcx, kcy, w, grid.gamma
 
 
 def sqrt_radiating(z):
@@ -259,7 +291,9 @@ def direct_sum(integrands, kx, ky, dx, dy, gamma, order, dkx, dky, block=32, wor
     polynomial of order P (eqs. taylors, fftexp):
         Z(Delta) = dkx dky / (4 pi^2) * sum_n I(k_n) exp(-i k_n.Delta)
                                           * T_P(gamma k_n.Delta)
-    order < 0 means the untruncated exponential (E_I itself).  truncation = 1
+    order < 0 means the untruncated exponential (E_I itself).  gamma is one
+    value (ray contour) or one value per sample (parabolic contour, where the
+    ratio beta_I/beta_R varies along the path).  truncation = 1
     selects the tensor-product variant (not in the paper): on the ray contour
     E_I = exp(gamma kx Dx) exp(gamma ky Dy) exactly, and each factor is
     replaced by its own Taylor polynomial, T_P(gamma kx Dx) T_P(gamma ky Dy).
@@ -275,6 +309,8 @@ def direct_sum(integrands, kx, ky, dx, dy, gamma, order, dkx, dky, block=32, wor
     dx = np.asarray(dx, dtype=np.float64).ravel()
     dy = np.asarray(dy, dtype=np.float64).ravel()
     nq = dx.size
+    gam = np.asarray(gamma, dtype=np.float64)
+    gam = gam.ravel() if gam.ndim else gam       # per-sample contour ratio (parabolic) or one value (ray)
     scale = dkx * dky / (4.0 * math.pi ** 2)
     out = np.zeros((integrands.shape[0], nq), dtype=np.complex128)
 
@@ -291,13 +327,14 @@ def direct_sum(integrands, kx, ky, dx, dy, gamma, order, dkx, dky, block=32, wor
             argx = np.outer(kx[s0:s1], dx[q0:q1])
             argy = np.outer(ky[s0:s1], dy[q0:q1])
             arg = argx + argy                                                       # k.Delta
+            g = gam[s0:s1, None] if gam.ndim else gam
             kern = np.exp(-1j * arg)
             if order < 0:
-                kern *= np.exp(gamma * arg)
+                kern *= np.exp(g * arg)
             elif truncation == 1:
-                kern *= taylor_poly(gamma * argx, order) * taylor_poly(gamma * argy, order)
+                kern *= taylor_poly(g * argx, order) * taylor_poly(g * argy, order)
             else:
-                kern *= taylor_poly(gamma * arg, order)
+                kern *= taylor_poly(g * arg, order)
             acc += integrands[:, s0:s1] @ kern
         out[:, q0:q1] = scale * acc
 
@@ -322,8 +359,8 @@ def grid_samples(nx, ny, kx_max, ky_max):
 def sampled_factors(grid, substrate, basis, q):
     """G_s and the MBF spectra on every sample of one grid (flattened, x fastest)."""
     kx, ky = grid_samples(grid.nx, grid.ny, grid.kx_max, grid.ky_max)
-    kcx, kcy, w = ray_contour(kx, ky, grid.gamma)
-    g = green_remainder(kx, ky, grid.gamma, grid.k0, substrate.eps_r, substrate.tan_delta, substrate.h)
+    kcx, kcy, w, gam = grid_contour(kx, ky, grid)
+    g = green_remainder(kx, ky, gam, grid.k0, substrate.eps_r, substrate.tan_delta, substrate.h)
     mt, mh = mbf_spectra(basis, q, kcx, kcy)
     return kx, ky, w, g, mt, mh
 
@@ -351,7 +388,8 @@ def tabulate(grid, substrate, basis, q, pairs, out_idx=None, order=None, workers
         dx, dy = dx[out_idx], dy[out_idx]
     dkx = 2.0 * grid.kx_max / grid.nx
     dky = 2.0 * grid.ky_max / grid.ny
-    z = direct_sum(integ, kx, ky, dx, dy, grid.gamma, order, dkx, dky, workers=workers,
+    gam = grid_contour(kx, ky, grid)[3]
+    z = direct_sum(integ, kx, ky, dx, dy, gam, order, dkx, dky, workers=workers,
                    truncation=getattr(grid, "truncation", 0))
     if out_idx is None:
         z = z.reshape(len(pairs), grid.ny, grid.nx)
@@ -366,7 +404,7 @@ def tabulate_from_factors(grid, pairs, g, mt, mh, out_idx=None, order=None, work
     """
     order = grid.order if order is None else order
     kx, ky = grid_samples(grid.nx, grid.ny, grid.kx_max, grid.ky_max)
-    _, _, w = ray_contour(kx, ky, grid.gamma)
+    _, _, w, gam = grid_contour(kx, ky, grid)
     integ = pair_integrands(pairs, w, g, mt, mh)
     dxa = displacement_axis(grid.nx, grid.kx_max)
     dya = displacement_axis(grid.ny, grid.ky_max)
@@ -376,7 +414,7 @@ def tabulate_from_factors(grid, pairs, g, mt, mh, out_idx=None, order=None, work
         dx, dy = dx[out_idx], dy[out_idx]
     dkx = 2.0 * grid.kx_max / grid.nx
     dky = 2.0 * grid.ky_max / grid.ny
-    z = direct_sum(integ, kx, ky, dx, dy, grid.gamma, order, dkx, dky, workers=workers,
+    z = direct_sum(integ, kx, ky, dx, dy, gam, order, dkx, dky, workers=workers,
                    truncation=getattr(grid, "truncation", 0))
     if out_idx is None:
         z = z.reshape(len(pairs), grid.ny, grid.nx)
@@ -504,7 +542,8 @@ def loss_gradient(grid, substrate, basis, q, pairs, pts, z_target, workers=1):
     kx, ky, w, g, mt, mh = sampled_factors(grid, substrate, basis, q)
     eye = np.eye(b_count, dtype=np.complex128)
     # unit-coefficient spectra of each basis: testing side uses conj(1) = 1
-    ut, uh = mbf_spectra(basis, eye, *ray_contour(kx, ky, grid.gamma)[:2])
+    kcx, kcy, _, gam = grid_contour(kx, ky, grid)
+    ut, uh = mbf_spectra(basis, eye, kcx, kcy)
     dxa = displacement_axis(grid.nx, grid.kx_max)
     dya = displacement_axis(grid.ny, grid.ky_max)
     DX, DY = np.meshgrid(dxa, dya)
@@ -515,7 +554,7 @@ def loss_gradient(grid, substrate, basis, q, pairs, pts, z_target, workers=1):
     nq = len(pts)
 
     def lookup_of(integ):
-        zz = direct_sum(integ, kx, ky, dx, dy, grid.gamma, grid.order, dkx, dky, workers=workers,
+        zz = direct_sum(integ, kx, ky, dx, dy, gam, grid.order, dkx, dky, workers=workers,
                         truncation=getattr(grid, "truncation", 0))
         out = np.zeros((integ.shape[0], nq), dtype=np.complex128)
         for i, (_, _, wgt) in enumerate(corners):

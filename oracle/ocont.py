@@ -6,9 +6,10 @@ eq. polarcord writes the reaction in polar spectral coordinates; eq.
 spectral_contour deforms the radial path into the complex beta plane and
 integrates along it with the Jacobian of the path.  Here the radial path is
 the ray beta_c = (1 + i gamma) t, t in [0, B], closed back to the real axis by
-the vertical segment from B(1 + i gamma) to B, so that every path shares the
-same end point and (by Cauchy's theorem, the integrand being analytic between
-the paths) the same value.  gamma = 0 is the real axis itself.  The angle is
+the vertical segment from B(1 + i gamma) to B, or the parabolic path that
+returns to the real axis at beta_end, so that every path shares the same
+end point and (by Cauchy's theorem, the integrand being analytic between the
+paths) the same value.  gamma = 0 is the real axis itself.  The angle is
 integrated with the trapezoidal rule (periodic integrand), the radial path
 adaptively (scipy quad_vec), all in FP64.
 """
@@ -40,9 +41,25 @@ def _kernel(beta_c, dbeta, alphas, dx, dy, k0, eps_r, tan_delta, h, basis, q, m,
 
 
 def reaction_polar(dx, dy, gamma, beta_max, k0, eps_r, tan_delta, h, basis, q, m=0, n=0,
-                   n_alpha=64, green_one=False, epsabs=1e-13, epsrel=1e-11, points=None):
-    """Z_mn(Delta) = 1/(4 pi^2) int d alpha int_path beta_c d beta_c H(k_c) e^{-i k_c.Delta}."""
+                   n_alpha=64, green_one=False, epsabs=1e-13, epsrel=1e-11, points=None, beta_end=None):
+    """Z_mn(Delta) = 1/(4 pi^2) int d alpha int_path beta_c d beta_c H(k_c) e^{-i k_c.Delta}.
+
+    beta_end given: the parabolic path beta_c = t + i gamma t (1 - t/beta_end)
+    for t in [0, beta_end], then the real axis up to beta_max (no closing
+    segment is needed, the path already ends on the real axis)."""
     alphas = 2.0 * math.pi * np.arange(n_alpha) / n_alpha
+    if beta_end is not None:
+        def para(t):
+            bc = t + 1j * gamma * t * (1.0 - t / beta_end)
+            dbc = 1.0 + 1j * gamma * (1.0 - 2.0 * t / beta_end)
+            return _kernel(bc, dbc, alphas, dx, dy, k0, eps_r, tan_delta, h, basis, q, m, n, green_one)
+        total, _ = quad_vec(para, 0.0, beta_end, epsabs=epsabs, epsrel=epsrel)
+        if beta_max > beta_end:
+            def real(t):
+                return _kernel(t + 0j, 1.0, alphas, dx, dy, k0, eps_r, tan_delta, h, basis, q, m, n, green_one)
+            rest, _ = quad_vec(real, beta_end, beta_max, epsabs=epsabs, epsrel=epsrel)
+            total = total + rest
+        return np.sum(total) * (2.0 * math.pi / n_alpha) / (4.0 * math.pi ** 2)
     s = 1.0 + 1j * gamma
 
     def ray(t):
