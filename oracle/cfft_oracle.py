@@ -68,14 +68,19 @@ def parabolic_contour(kx: np.ndarray, ky: np.ndarray, gamma: float, beta_end: fl
     with the local ratio g = beta_I/beta = gamma (1 - beta/beta_end) (eq.
     ratioNew holds sample by sample), and the weight of eq. FFT is
     W = (1 + i d beta_I/d beta)(1 + i g), which equals det(d k_c / d k).
+    The slope d beta_I/d beta jumps from -gamma to 0 at beta_end; a sample
+    lying there (within a relative 1e-9, so that rounding of beta cannot
+    decide) takes the mean of the two one-sided slopes, -gamma/2.  g itself
+    is continuous (0 at beta_end).
     Returns (kcx, kcy, W, g) with g per sample.
     """
     kx = np.asarray(kx, dtype=np.float64)
     ky = np.asarray(ky, dtype=np.float64)
     beta = np.hypot(kx, ky)
     inside = beta < beta_end
+    at_end = np.abs(beta - beta_end) <= 1e-9 * beta_end
     g = np.where(inside, gamma * (1.0 - beta / beta_end), 0.0)
-    dbi = np.where(inside, gamma * (1.0 - 2.0 * beta / beta_end), 0.0)
+    dbi = np.where(at_end, -0.5 * gamma, np.where(inside, gamma * (1.0 - 2.0 * beta / beta_end), 0.0))
     s = 1.0 + 1j * g
     return s * kx, s * ky, (1.0 + 1j * dbi) * s, g
 

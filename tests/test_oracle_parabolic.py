@@ -33,6 +33,19 @@ def test_weight_is_the_jacobian_determinant():
         assert abs(np.linalg.det(J) - w) < 1e-8 * abs(w)
 
 
+def test_sample_at_the_end_of_the_deformation_takes_the_mean_slope():
+    """At beta = beta_end the slope jumps from -gamma to 0: the weight there is
+    (1 + i(-gamma/2)) (1 + 0i), whether beta rounds just below or above."""
+    gamma, be = 1 / 50, 4.5 * K0
+    for b in (be, be * (1 - 1e-15), be * (1 + 1e-15)):
+        _, _, w, g = co.parabolic_contour(np.array([b]), np.array([0.0]), gamma, be)
+        assert abs(g[0]) < 1e-14
+        assert abs(w[0] - (1 - 0.5j * gamma)) < 1e-14
+    w_in = co.parabolic_contour(np.array([be * 0.999]), np.array([0.0]), gamma, be)[2][0]
+    w_out = co.parabolic_contour(np.array([be * 1.001]), np.array([0.0]), gamma, be)[2][0]
+    assert abs(w_in.imag + gamma) < 1e-3 and w_out == 1.0
+
+
 def test_path_is_the_parabola():
     """k_c . k_c = beta_c^2 with Im beta_c = gamma beta (1 - beta/beta_end), and
     real beyond beta_end."""
