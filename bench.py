@@ -266,6 +266,40 @@ def _tensor_leg(torch, steps, warmup, precision, n_out):
             "dtype": "f64" if precision == 0 else "fp32 FFT / fp64 rest", "kernels_ms": km}
 
 
+def _parabolic_leg(torch, steps, warmup, n_out):
+    """The 512^2 workload on the parabolic contour (beta_end = 2 k0 sqrt(eps_r)):
+    per-sample spectra, (P+1)(P+2)/2 row transforms; FP64, error against the
+    oracle on n_out sampled outputs per pair."""
+    import dataclasses
+    import math as _m
+
+    import numpy as np
+
+    from oracle import cfft_oracle as co
+    from workloads import CONTOUR_PARABOLIC, c2_rooftop_512
+    wl = c2_rooftop_512()
+    sub = wl.substrates[0]
+    grid = dataclasses.replace(wl.grids[0], contour=CONTOUR_PARABOLIC,
+                               beta_end=2.0 * wl.grids[0].k0 * _m.sqrt(sub.eps_r))
+    wl = dataclasses.replace(wl, grids=[grid])
+    st = Step(wl, torch)
+    sec = _time_steps(torch, st.run, steps, warmup)
+    sec_tab = _time_steps(torch, lambda: st.tab.tabulate(st.spec, st.g, st.pairs, out=st.z), steps, 2)
+    km = _kernel_times(st, steps)
+    torch.cuda.synchronize()
+    z = st.z.cpu().numpy().reshape(len(wl.pairs), -1)
+    st.tab.close()
+    rng = np.random.default_rng(78)
+    idx = np.unique(np.concatenate([rng.choice(grid.nx * grid.ny, n_out, replace=False),
+                                    [(grid.ny // 2) * grid.nx + grid.nx // 2]]))
+    ref = co.tabulate(grid, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=min(16, os.cpu_count() or 1))
+    err = float((np.abs(z[:, idx] - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+    return {"value": st.entries() / sec, "ms_per_step": sec * 1e3, "beta_end": grid.beta_end,
+            "passes_only": {"ms": sec_tab * 1e3, "value": st.entries() / sec_tab, "unit": "entries/s"},
+            "rel_err_vs_oracle": err, "oracle_sample": f"{len(idx)} outputs x {len(wl.pairs)} pairs",
+            "dtype": "f64", "kernels_ms": km}
+
+
 def _sweep(torch, steps, warmup):
     """Frequency sweep, 8 uneven grids x 16 pairs (mixed), eager and as one replayed HIP graph."""
     from paper_1404_7357_amd import Tabulator
@@ -422,6 +456,8 @@ def main():
         n_out = 0 if args.no_cpu_baseline else 64
         out["tensor"] = {"fp64": _tensor_leg(torch, args.steps, args.warmup, 0, max(n_out, 4)),
                          "mixed": _tensor_leg(torch, args.steps, args.warmup, MIXED, max(n_out, 4))}
+        _log("parabolic-contour leg (FP64)")
+        out["parabolic"] = _parabolic_leg(torch, max(3, args.steps // 5), 2, max(n_out, 4))
         _log("sweep leg (8 grids, one graph)")
         out["sweep"] = _sweep(torch, max(3, args.steps // 5), 2)
         _log("adjoint leg (1024^2, 16 pairs, 4096 lookups)")

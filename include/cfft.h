@@ -7,8 +7,16 @@
  * Jha & Craeye, "Contour-FFT based Spectral Domain MBF Analysis of Large
  * Printed Antenna Arrays":
  *
- *   Z'_mn(Dx,Dy) = 1/(4 pi^2) sum_{n1,n2} I_mn(k) exp(-i k.D) T_P(gamma k.D) dkx dky
- *   I_mn(k)      = W * M_m(k_c) . G_s(k_c) . M#_n(k_c),   k_c = (1 + i gamma) k
+ *   Z'_mn(Dx,Dy) = 1/(4 pi^2) sum_{n1,n2} I_mn(k) exp(-i k.D) T_P(g k.D) dkx dky
+ *   I_mn(k)      = W * M_m(k_c) . G_s(k_c) . M#_n(k_c),   k_c = (1 + i g) k
+ *
+ * with g = beta_I/beta_R the contour ratio of eq. ratioNew and W = (1 + i
+ * d beta_I/d beta_R)(1 + i g) the weight of eq. FFT.  Ray contour: g = gamma
+ * everywhere, W = (1 + i gamma)^2.  Parabolic contour (the deformation the
+ * paper names, Sec. I and Fig. 1): beta_I = gamma beta (1 - beta/beta_end)
+ * below beta_end and 0 beyond, so g = gamma (1 - beta/beta_end) varies per
+ * sample, the per-axis factorisation of the Taylor terms is lost, and the row
+ * pass runs all (P+1)(P+2)/2 terms of eq. fftarry.
  *
  * (Sec. III-A eqs. spectral, MBF_mul, MBF_mul22, FTMBF; Sec. III-B.2 eqs.
  * complexbeta..ratioNew and FFT; Sec. III-B.3 eqs. taylors, fftexp, fftarry;
@@ -89,9 +97,10 @@ typedef struct {
   double kx_max, ky_max; /* spectral half-spans (rad per lambda0), > 0 */
   double k0;             /* free-space wavenumber 2 pi f/f0, > 0 */
   double gamma;          /* contour height ratio beta_I/beta_R (eq. ratioNew), > 0 */
-  int32_t contour;       /* CFFT_CONTOUR_RAY; PARABOLIC is rejected (UNSUPPORTED) */
+  int32_t contour;       /* CFFT_CONTOUR_RAY or CFFT_CONTOUR_PARABOLIC */
   int32_t order;         /* Taylor order P >= 0 of eq. taylors, 0 <= P <= 7 */
-  double beta_end;       /* end of the parabolic deformation (unused for RAY) */
+  double beta_end;       /* PARABOLIC: where the path rejoins the real axis (> every
+                            surface-wave pole), finite > 0; unused for RAY */
   int32_t precision;     /* CFFT_FP64 (complex128 everywhere) or CFFT_MIXED */
   int32_t truncation;    /* CFFT_TRUNC_TOTAL (0, the paper's) or CFFT_TRUNC_TENSOR */
 } cfft_grid_desc_t;
@@ -144,7 +153,8 @@ cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* ba
 
 /* The C-FFT table (eqs. FFT, fftexp, fftarry and the Appendix) for the
  * listed MBF pairs: integrand assembly, contour weight, P+1 row FFTs per row
- * with partial recombination, P+1 column FFTs per column with the per-output
+ * (ray contour; (P+1)(P+2)/2 on the parabolic contour) with partial
+ * recombination, P+1 column FFTs per column with the per-output
  * recombination and the Appendix scaling.
  *   spec  : device, output of mbf_spectra for nmbf MBFs
  *   g     : device, output of slab_green_eval
@@ -173,7 +183,8 @@ cfft_status_t cfft_lookup_backward(cfft_plan_t plan, int32_t grid, const void* d
                                    int32_t npairs, const double* pts, int32_t npts, void* dz,
                                    void* stream);
 
-/* Gradient of a real loss L through the whole table (FP64 grids only).
+/* Gradient of a real loss L through the whole table (FP64 grids on the ray
+ * contour; other grids return CFFT_ERR_UNSUPPORTED).
  *   dz       : device complex128 [npairs][ny][nx], dL/dRe z + i dL/dIm z
  *   eps_r, tan_delta, h, basis, nbasis, q, nmbf, pairs, npairs : the forward inputs
  *   g, spec  : device, the forward's sampled Green's function and spectra

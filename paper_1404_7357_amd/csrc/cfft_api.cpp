@@ -249,8 +249,15 @@ PassParams pass_params(const GridState& gs) {
   p.gamma = gs.d.gamma;
   p.order = gs.d.order;
   p.tensor = gs.d.truncation == CFFT_TRUNC_TENSOR ? 1 : 0;
+  p.parabolic = gs.d.contour == CFFT_CONTOUR_PARABOLIC ? 1 : 0;
+  p.beta_end = gs.d.beta_end;
   p.precision = gs.d.precision;
   return p;
+}
+
+GreenParams green_params(const GridState& gs, double eps_r, double tan_delta, double h) {
+  return GreenParams{gs.x, gs.y, gs.d.gamma, gs.d.k0, eps_r, tan_delta, h,
+                     gs.d.contour == CFFT_CONTOUR_PARABOLIC ? 1 : 0, gs.d.beta_end};
 }
 
 cfft_status_t ensure_ws(void** ws, size_t* have, size_t need, const char* what) {
@@ -525,9 +532,14 @@ cfft_status_t c_fft_plan(const cfft_grid_desc_t* grids, int32_t ngrids, int32_t 
       return fail(CFFT_ERR_INVALID_ARG, "grid %d: unknown precision %d", i, g.precision);
     if (g.truncation != CFFT_TRUNC_TOTAL && g.truncation != CFFT_TRUNC_TENSOR)
       return fail(CFFT_ERR_INVALID_ARG, "grid %d: truncation %d is neither TOTAL nor TENSOR", i, g.truncation);
-    if (g.contour == CFFT_CONTOUR_PARABOLIC)
-      return fail(CFFT_ERR_UNSUPPORTED, "grid %d: the parabolic contour is not implemented (use RAY)", i);
-    if (g.contour != CFFT_CONTOUR_RAY) return fail(CFFT_ERR_INVALID_ARG, "grid %d: unknown contour %d", i, g.contour);
+    if (g.contour != CFFT_CONTOUR_RAY && g.contour != CFFT_CONTOUR_PARABOLIC)
+      return fail(CFFT_ERR_INVALID_ARG, "grid %d: unknown contour %d", i, g.contour);
+    if (g.contour == CFFT_CONTOUR_PARABOLIC) {
+      if (!(std::isfinite(g.beta_end) && g.beta_end > 0.0))
+        return fail(CFFT_ERR_INVALID_ARG, "grid %d: the parabolic contour needs a finite beta_end > 0", i);
+      if (g.truncation == CFFT_TRUNC_TENSOR)
+        return fail(CFFT_ERR_UNSUPPORTED, "grid %d: tensor-product truncation needs the ray contour", i);
+    }
   }
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
@@ -600,7 +612,7 @@ cfft_status_t slab_green_eval(cfft_plan_t plan, int32_t grid, double eps_r, doub
     return fail(CFFT_ERR_INVALID_ARG, "tan_delta must be finite and >= 0");
   if (!(std::isfinite(h) && h > 0.0)) return fail(CFFT_ERR_INVALID_ARG, "h must be finite and > 0");
   GridState& gs = plan->grids[grid];
-  GreenParams p{gs.x, gs.y, gs.d.gamma, gs.d.k0, eps_r, tan_delta, h};
+  const GreenParams p = green_params(gs, eps_r, tan_delta, h);
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   {
@@ -625,11 +637,15 @@ cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* ba
   hipStream_t s = (hipStream_t)stream;
   st = ensure_geometry(plan, gs, basis, nbasis, s);
   if (st != CFFT_OK) return st;
-  st = ensure_ws(&plan->ws3, &plan->ws3_bytes, sizeof(double2) * spectra_scratch_len(gs.y, plan->geo_dev, nmbf),
-                 "spectra scratch");
-  if (st != CFFT_OK) return st;
   hipError_t e;
-  {
+  if (gs.d.contour == CFFT_CONTOUR_PARABOLIC) {
+    const Contour c{gs.d.gamma, 1, gs.d.beta_end};
+    ProfScope ps(plan, 1, s);
+    e = launch_spectra_direct(gs.x, gs.y, c, plan->geo_dev, (const double2*)q, nmbf, (double2*)spec, s);
+  } else {
+    st = ensure_ws(&plan->ws3, &plan->ws3_bytes, sizeof(double2) * spectra_scratch_len(gs.y, plan->geo_dev, nmbf),
+                   "spectra scratch");
+    if (st != CFFT_OK) return st;
     ProfScope ps(plan, 1, s);
     e = launch_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, (const double2*)q, nmbf, (double2*)plan->ws3,
                        (double2*)spec, s);
@@ -840,6 +856,7 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   if (st != CFFT_OK) return st;
   GridState& gs = plan->grids[grid];
   if (gs.d.precision != CFFT_FP64) return fail(CFFT_ERR_UNSUPPORTED, "the adjoint needs an FP64 grid");
+  if (gs.d.contour != CFFT_CONTOUR_RAY) return fail(CFFT_ERR_UNSUPPORTED, "the adjoint needs the ray contour");
   hipStream_t s = (hipStream_t)stream;
   st = ensure_geometry(plan, gs, basis, nbasis, s);
   if (st != CFFT_OK) return st;
@@ -851,7 +868,7 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
   const long long forced = env_ll("CFFT_PAIR_CHUNK", 0);
   if (forced > 0) chunk = std::min<long long>(chunk, forced);
-  const GreenParams gp{gs.x, gs.y, gs.d.gamma, gs.d.k0, eps_r, tan_delta, h};
+  const GreenParams gp = green_params(gs, eps_r, tan_delta, h);
   const int green_blocks = std::min(1024, (green_threads(gp) + 255) / 256);
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   const size_t b_gg = al(3 * n * 16), b_gs = al((size_t)nmbf * 4 * n * 16);

@@ -107,6 +107,23 @@ __device__ __forceinline__ double2 csinc(double2 z) {
   return cdiv(make_double2(s * ch, c * sh), z);
 }
 
+// Local contour ratio g = beta_I/beta at |k| = beta and the path slope
+// beta_I' = d beta_I/d beta: ray, g = beta_I' = gamma; parabolic (beta_I =
+// gamma beta (1 - beta/beta_end) below beta_end, real beyond),
+// g = gamma (1 - beta/beta_end), beta_I' = gamma (1 - 2 beta/beta_end).  The
+// slope jumps at beta_end; a sample there (within a relative 1e-9, so that
+// the rounding of beta does not decide) takes the mean slope -gamma/2.
+__device__ __forceinline__ void contour_ratio(double beta, double gamma, int parabolic, double beta_end,
+                                              double& g, double& slope) {
+  if (!parabolic) {
+    g = slope = gamma;
+    return;
+  }
+  g = beta < beta_end ? gamma * (1.0 - beta / beta_end) : 0.0;
+  if (fabs(beta - beta_end) <= 1e-9 * beta_end) slope = -0.5 * gamma;
+  else slope = beta < beta_end ? gamma * (1.0 - 2.0 * beta / beta_end) : 0.0;
+}
+
 // Non-temporal (streaming) accesses for data touched once.
 template <typename V> __device__ __forceinline__ void store_nt(V* p, V v) {
   using Rl = typename real_of<V>::type;

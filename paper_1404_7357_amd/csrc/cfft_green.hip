@@ -1,6 +1,7 @@
 // Grounded-slab spectral dyadic Green's function minus the effective
 // homogeneous medium and its image (Sec. II, Sec. III-A of the paper), on
-// the ray contour k_c = (1 + i gamma) k, in FP64.  One thread per quadrant
+// the contour k_c = (1 + i g) k (g = gamma on the ray, g = g(|k|) on the
+// parabolic contour), in FP64.  One thread per quadrant
 // sample, writing its mirror images; interleaved complex128 output
 // [3][ny][nx] with x fastest.
 //
@@ -186,8 +187,10 @@ __global__ void __launch_bounds__(256) green_kernel(GreenParams p, double2* __re
   const double ky = mr.h2 * p.y.dk;
   const double2 eps = make_double2(p.eps_re, -p.eps_re * p.tan_delta);
   const double2 h = make_double2(p.h, 0.0);
+  double ratio, slope;
+  contour_ratio(hypot(kx, ky), p.gamma, p.parabolic, p.beta_end, ratio, slope);
   double2 gxx, gxy, gyy;
-  green_dyadic(kx, ky, p.gamma, p.k0, eps, h, gxx, gxy, gyy);
+  green_dyadic(kx, ky, ratio, p.k0, eps, h, gxx, gxy, gyy);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int i = mirror_sample(p, mr, q);

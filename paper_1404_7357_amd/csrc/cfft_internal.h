@@ -21,10 +21,20 @@ struct Axis {
   double d_first, dd;   // output displacements
 };
 
+// Contour of a grid: ray (beta_I = gamma beta) or parabolic (beta_I =
+// gamma beta (1 - beta/beta_end) below beta_end, real beyond).
+struct Contour {
+  double gamma;
+  int parabolic;
+  double beta_end;
+};
+
 struct GreenParams {
   Axis x, y;
   double gamma, k0;
   double eps_re, tan_delta, h;
+  int parabolic;
+  double beta_end;
 };
 
 // Separable geometry of a basis set: bases sharing (kind, a, b) form a
@@ -61,6 +71,8 @@ struct PassParams {
   int order;
   int precision;      // 0 FP64, 1 MIXED
   int tensor;         // 1: tensor-product truncation (one intermediate per pair)
+  int parabolic;      // 1: parabolic contour (per-sample ratio; N_t row transforms)
+  double beta_end;
 };
 
 // Intermediate arrays per pair between the row and column passes.
@@ -76,6 +88,9 @@ size_t spectra_tables_len(const Axis& x, const Axis& y, const GeomDevice& geo);
 hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
                           const double2* utab, const double2* q, int nmbf, double2* scratch,
                           double2* spec, hipStream_t s);
+// Spectra on the parabolic contour (no per-axis separation): per sample.
+hipError_t launch_spectra_direct(const Axis& x, const Axis& y, const Contour& c, const GeomDevice& geo,
+                                 const double2* q, int nmbf, double2* spec, hipStream_t s);
 size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf);
 size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf);
 

@@ -79,6 +79,8 @@ template <int N> struct RowCfg {
 
 struct RowArgs {
   int tensor;   // tensor-product truncation: only S_P is stored, in slot 0
+  int parabolic;                // per-sample contour ratio (see row_terms_general)
+  double ky0, dky, beta_end;
   const double2* g;
   const double2* spec;
   void* inter;
@@ -89,6 +91,65 @@ struct RowArgs {
   int pm[kMaxPairsPerLaunch];
   int pn[kMaxPairsPerLaunch];
 };
+
+// Contour weight W = (1 + i g)(1 + i beta_I') at the sample (kx, ky).
+template <typename Args>
+__device__ __forceinline__ double2 contour_weight(const Args& a, double kx, double ky) {
+  double g, slope;
+  contour_ratio(hypot(kx, ky), a.gamma, a.parabolic, a.beta_end, g, slope);
+  return cmul(make_double2(1.0, g), make_double2(1.0, slope));
+}
+
+// Row terms when the contour ratio g varies per sample (parabolic contour):
+// (g ky)^b is no longer constant along a row, so for b = 0..P the row pass
+// forms S'_b = sum_{a <= P-b} Dx^a/a! DFT_n1[ (g kx)^a (g ky)^b f ] and
+// stores it in slot b; the column pass then applies no ky factor.  That is
+// (P+1)(P+2)/2 row transforms, the N_t of eq. fftarry.  f already carries
+// s(n1) and the contour weight.
+template <typename V, int N, int R, bool WAVE, int PS, typename Args>
+__device__ __forceinline__ void row_terms_general(const Args& a, const V (&f)[R], V* lds, const V* ltw, int t, int n2,
+                                                  V* dst0, size_t slot_stride, bool store) {
+  constexpr int T = N / R;
+  using Rl = typename real_of<V>::type;
+  const double ky = a.ky0 + n2 * a.dky;
+  double gkx[R], gky[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double kx = a.kx0 + (t + T * r) * a.dkx;
+    double g, slope;
+    contour_ratio(hypot(kx, ky), a.gamma, a.parabolic, a.beta_end, g, slope);
+    gkx[r] = g * kx;
+    gky[r] = g * ky;
+  }
+  for (int b = 0; b <= a.order; ++b) {
+    double2 S[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
+    for (int ao = 0; ao + b <= a.order; ++ao) {
+      V x[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double w = 1.0;
+        for (int i = 0; i < ao; ++i) w *= gkx[r];
+        for (int i = 0; i < b; ++i) w *= gky[r];
+        x[r] = cscale(f[r], (Rl)w);
+      }
+      fft_forward<V, N, R, WAVE, PS>(x, lds, ltw, t);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double dx = a.x0 + (t + T * r) * a.ddx;
+        double cf = 1.0;
+        for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
+        const double2 xv = to_d(x[r]);
+        S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
+      }
+    }
+    if (store) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst0[(size_t)b * slot_stride + t + T * r] = from_d<V>(S[r]);
+    }
+  }
+}
 
 template <typename V, int N>
 #if CFFT_ROW_MIN_WAVES > 0
@@ -127,14 +188,22 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
       const double2 myh = a.spec[((size_t)n * 4 + 3) * plane + idx];
       h = cadd(cmul(mx, cadd(cmul(gxx, mxh), cmul(gxy, myh))), cmul(my, cadd(cmul(gxy, mxh), cmul(gyy, myh))));
       if (n1 & 1) h = make_double2(-h.x, -h.y);
+      if (a.parabolic) h = cmul(h, contour_weight(a, a.kx0 + n1 * a.dkx, a.ky0 + n2 * a.dky));
     }
     f[r] = from_d<V>(h);
+  }
+  V* my_lds = lds + grp * lds_len<row_pad<V>()>(N);
+  __syncthreads();   // twiddle tables ready
+  if (a.parabolic) {
+    const size_t slot = (size_t)a.ny * N;
+    row_terms_general<V, N, R, (T <= 64), row_pad<V>()>(a, f, my_lds, ltw, t, valid ? n2 : 0,
+                                                         inter + ((size_t)pair * (a.order + 1) * a.ny + (valid ? n2 : 0)) * N,
+                                                         slot, valid);
+    return;
   }
   double2 S[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
-  V* my_lds = lds + grp * lds_len<row_pad<V>()>(N);
-  __syncthreads();   // twiddle tables ready
   for (int ao = 0; ao <= a.order; ++ao) {
     if (ao > 0) {
 #pragma unroll
@@ -172,6 +241,8 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
 // input arrays per pair instead of 7.
 struct RowGArgs {
   int tensor;
+  int parabolic;
+  double ky0, dky, beta_end;
   const double2* g;
   const double2* spec;
   void* inter;
@@ -223,6 +294,11 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
       vx = make_double2(-vx.x, -vx.y);
       vy = make_double2(-vy.x, -vy.y);
     }
+    if (a.parabolic) {
+      const double2 wc = contour_weight(a, a.kx0 + i * a.dkx, a.ky0 + n2 * a.dky);
+      vx = cmul(vx, wc);
+      vy = cmul(vy, wc);
+    }
     ax[i] = vx;
     ay[i] = vy;
   }
@@ -245,11 +321,17 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
     }
     f[r] = from_d<V>(h);
   }
+  V* my_lds = lds + w * lds_len<row_pad<V>()>(N);
+  V* inter = (V*)a.inter;
+  if (a.parabolic) {
+    row_terms_general<V, N, R, (T <= 64), row_pad<V>()>(a, f, my_lds, ltw, t, n2,
+                                                         inter + ((size_t)pair * (a.order + 1) * a.ny + n2) * N,
+                                                         (size_t)a.ny * N, active);
+    return;
+  }
   double2 S[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
-  V* my_lds = lds + w * lds_len<row_pad<V>()>(N);
-  V* inter = (V*)a.inter;
   for (int ao = 0; ao <= a.order; ++ao) {
     if (ao > 0) {
 #pragma unroll
@@ -279,6 +361,7 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
 
 struct ColArgs {
   int tensor;   // every term reads slot 0 (the full row sum S_P)
+  int parabolic;   // term b reads slot b and carries no (gamma ky)^b factor
   const void* inter;
   void* z;
   const void* tw;
@@ -331,7 +414,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
   // per term (a few multiplies) rather than kept live in registers.
   V nxt[R];
   if constexpr (CFFT_COL_PREFETCH) {
-    const V* src = col0 + (size_t)(a.tensor ? 0 : a.order) * plane;
+    const V* src = col0 + (size_t)(a.tensor || a.parabolic ? 0 : a.order) * plane;
 #pragma unroll
     for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
   }
@@ -340,7 +423,7 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
   for (int b = 0; b <= a.order; ++b) {
     V x[R];
     if constexpr (!CFFT_COL_PREFETCH) {
-      const V* src = col0 + (size_t)(a.tensor ? 0 : a.order - b) * plane;
+      const V* src = col0 + (size_t)(a.tensor ? 0 : a.parabolic ? b : a.order - b) * plane;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (CFFT_COL_NT_LOAD) nxt[r] = load_nt(src + (size_t)(t + T * r) * a.nx);
@@ -352,11 +435,12 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
       const int n2 = t + T * r;
       const Rl gk = (Rl)(a.gamma * (a.ky0 + n2 * a.dky));
       Rl w = (n2 & 1) ? (Rl)-1 : (Rl)1;
-      for (int i = 0; i < b; ++i) w *= gk;
+      if (!a.parabolic)
+        for (int i = 0; i < b; ++i) w *= gk;
       x[r] = cscale(nxt[r], w);
     }
     if (CFFT_COL_PREFETCH && b < a.order) {
-      const V* src = col0 + (size_t)(a.tensor ? 0 : a.order - b - 1) * plane;
+      const V* src = col0 + (size_t)(a.tensor ? 0 : a.parabolic ? b + 1 : a.order - b - 1) * plane;
 #pragma unroll
       for (int r = 0; r < R; ++r) nxt[r] = src[(size_t)(t + T * r) * a.nx];
     }
@@ -449,6 +533,10 @@ static hipError_t rowg_launch(const RowArgs& ra, hipStream_t s) {
   a.ny = ra.ny;
   a.order = ra.order;
   a.tensor = ra.tensor;
+  a.parabolic = ra.parabolic;
+  a.ky0 = ra.ky0;
+  a.dky = ra.dky;
+  a.beta_end = ra.beta_end;
   a.kx0 = ra.kx0;
   a.dkx = ra.dkx;
   a.x0 = ra.x0;
@@ -512,6 +600,10 @@ hipError_t launch_row_pass(const PassParams& p, const double2* g, const double2*
   a.ny = p.y.n;
   a.order = p.order;
   a.tensor = p.tensor;
+  a.parabolic = p.parabolic;
+  a.ky0 = p.y.k_first;
+  a.dky = p.y.dk;
+  a.beta_end = p.beta_end;
   a.npairs = npairs;
   a.kx0 = p.x.k_first;
   a.dkx = p.x.dk;
@@ -533,7 +625,9 @@ static double2 table_scale(const PassParams& p) {
   const double K = p.x.dk * p.y.dk / (4.0 * M_PI * M_PI);
   const int half = (p.x.n + p.y.n) / 2;
   const double sigma = (half & 1) ? -1.0 : 1.0;
-  // W = (1 + i gamma)^2
+  // ray: W = (1 + i gamma)^2 is constant and applied here; parabolic: W
+  // varies per sample and the row pass has applied it
+  if (p.parabolic) return make_double2(K * sigma, 0.0);
   const double wr = 1.0 - p.gamma * p.gamma, wi = 2.0 * p.gamma;
   return make_double2(K * sigma * wr, K * sigma * wi);
 }
@@ -548,6 +642,7 @@ hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, v
   a.ny = p.y.n;
   a.order = p.order;
   a.tensor = p.tensor;
+  a.parabolic = p.parabolic;
   a.npairs = npairs;
   a.ky0 = p.y.k_first;
   a.dky = p.y.dk;

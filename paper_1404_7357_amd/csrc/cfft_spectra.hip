@@ -284,6 +284,83 @@ hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const Geom
   return hipGetLastError();
 }
 
+// ------------------------------------------------ parabolic contour
+// On the parabolic contour k_c = (1 + i g(|k|)) k couples kx and ky, so the
+// transforms no longer split into x and y tables: each sample sums its bases
+// directly, F_j(k_c) = SX(kcx) SY(kcy) exp(-i k_c . c_j) with
+// exp(-i k_c . c) = exp(g k.c) (cos k.c - i sin k.c) and, for the reflected
+// spectrum, exp(+i k_c . c) = exp(-g k.c) (cos k.c + i sin k.c) (the shape
+// factors are even).  One thread per sample; the coefficients of a basis are
+// the same for every thread (wave-uniform loads); MBFs in chunks of kMChunk.
+constexpr int kDirectThreads = 256;
+__global__ void __launch_bounds__(kDirectThreads)
+spectra_direct_kernel(Axis x, Axis y, Contour cont, GeomDevice geo, const double2* __restrict__ q, int nmbf,
+                      double2* __restrict__ spec) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= x.n * y.n) return;
+  const int n1 = idx % x.n, n2 = idx / x.n;
+  const double kx = x.k_first + n1 * x.dk;
+  const double ky = y.k_first + n2 * y.dk;
+  double g, slope;
+  contour_ratio(hypot(kx, ky), cont.gamma, cont.parabolic, cont.beta_end, g, slope);
+  const double2 kcx = make_double2(kx, g * kx), kcy = make_double2(ky, g * ky);
+  const size_t plane = (size_t)x.n * y.n;
+  for (int m0 = 0; m0 < nmbf; m0 += kMChunk) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double2 acc[kMChunk], acch[kMChunk];
+#pragma unroll
+      for (int i = 0; i < kMChunk; ++i) acc[i] = acch[i] = make_double2(0.0, 0.0);
+      const int g0 = c == 0 ? 0 : geo.ngroups_x;
+      const int g1 = c == 0 ? geo.ngroups_x : geo.ngroups;
+      for (int gi = g0; gi < g1; ++gi) {
+        const GeomGroup gr = geo.groups[gi];
+        const double2 sx = is_ydir(gr.kind) ? across_factor(gr.b, kcx) : along_factor(gr.kind, gr.a, kcx);
+        const double2 sy = is_ydir(gr.kind) ? along_factor(gr.kind, gr.a, kcy) : across_factor(gr.b, kcy);
+        const double2 shape = cmul(sx, sy);
+        for (int p = 0; p < gr.np; ++p) {
+          const double xc = geo.xs[gr.xoff + p];
+          for (int r = 0; r < gr.nr; ++r) {
+            const int j = geo.index[gr.ioff + p * gr.nr + r];
+            if (j < 0) continue;
+            const double kd = kx * xc + ky * geo.ys[gr.yoff + r];
+            double sn, cs;
+            sincos(kd, &sn, &cs);
+            const double e = exp(g * kd);
+            const double ei = 1.0 / e;
+            const double2 f = cmul(shape, make_double2(e * cs, -e * sn));
+            const double2 fh = cmul(shape, make_double2(ei * cs, ei * sn));
+#pragma unroll
+            for (int i = 0; i < kMChunk; ++i) {
+              if (m0 + i < nmbf) {
+                const double2 qv = q[(size_t)(m0 + i) * geo.nbasis + j];
+                acc[i] = cfma(acc[i], f, make_double2(qv.x, -qv.y));   // conj(q) F
+                acch[i] = cfma(acch[i], fh, qv);                       // q F#
+              }
+            }
+          }
+        }
+      }
+      const size_t o = (size_t)n2 * x.n + n1;
+#pragma unroll
+      for (int i = 0; i < kMChunk; ++i) {
+        if (m0 + i < nmbf) {
+          spec[((size_t)(m0 + i) * 4 + c) * plane + o] = acc[i];
+          spec[((size_t)(m0 + i) * 4 + 2 + c) * plane + o] = acch[i];
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_spectra_direct(const Axis& x, const Axis& y, const Contour& c, const GeomDevice& geo,
+                                 const double2* q, int nmbf, double2* spec, hipStream_t s) {
+  const int n = x.n * y.n;
+  hipLaunchKernelGGL(spectra_direct_kernel, dim3((n + kDirectThreads - 1) / kDirectThreads), dim3(kDirectThreads), 0,
+                     s, x, y, c, geo, q, nmbf, spec);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ adjoint
 // Gradient of L w.r.t. q from the gradient w.r.t. the spectra (gspec, same
 // layout as spec, in the d/dRe + i d/dIm convention):

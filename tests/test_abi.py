@@ -66,10 +66,16 @@ def test_plan_rejects_invalid_grids(field, value):
     assert not h.value
 
 
-def test_plan_rejects_unsupported_parabolic_contour():
+def test_plan_checks_parabolic_contour_arguments():
+    """The parabolic contour needs a finite beta_end > 0 (INVALID_ARG) and
+    excludes the tensor-product truncation (UNSUPPORTED); both are caught on
+    the host before any device call."""
     L, lib = _lib()
-    desc = (L.GridDesc * 1)(L.grid_desc(_grid(contour=1)))
     h = ctypes.c_void_p()
+    for bad in (0.0, -1.0, float("inf")):
+        desc = (L.GridDesc * 1)(L.grid_desc(_grid(contour=1, beta_end=bad)))
+        assert lib.c_fft_plan(desc, 1, 4, 0, ctypes.byref(h)) == 1
+    desc = (L.GridDesc * 1)(L.grid_desc(_grid(contour=1, beta_end=20.0, truncation=1)))
     assert lib.c_fft_plan(desc, 1, 4, 0, ctypes.byref(h)) == 2
 
 

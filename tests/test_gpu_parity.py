@@ -14,8 +14,8 @@ import numpy as np
 import pytest
 
 from oracle import cfft_oracle as co
-from workloads import (FP64, MIXED, TRUNC_TENSOR, Grid, Substrate, c1_single_cosine, c2_rooftop_512,
-                       gaussian_coefficients, rooftop_lattice)
+from workloads import (CONTOUR_PARABOLIC, COSINE_X, FP64, MIXED, TRUNC_TENSOR, Grid, Substrate, basis_array,
+                       c1_single_cosine, c2_rooftop_512, gaussian_coefficients, rooftop_lattice)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -195,6 +195,70 @@ def test_tensor_truncation_c2_sampled(prec, tol):
     err = (np.abs(zs - ref).max(axis=1) / scale).max()
     assert err < tol, err
     assert (np.abs(ref_total - ref).max(axis=1) / scale).max() > 10 * 1e-5   # modes told apart
+
+
+def _para(grid, beta_end):
+    return dataclasses.replace(grid, contour=CONTOUR_PARABOLIC, beta_end=beta_end)
+
+
+def test_parabolic_green_and_spectra():
+    """Green's function (quadrant mirrored, per-sample ratio) and the direct
+    per-sample spectra on the parabolic contour vs the oracle."""
+    grid = _para(Grid(64, 32, 9 * K0, 7 * K0, K0, gamma=1 / 60), 4.0 * K0)
+    sub = Substrate(4.4, 0.002, 0.06)
+    rng = np.random.default_rng(31)
+    basis = np.concatenate([rooftop_lattice(2, 3), basis_array([(COSINE_X, 0.05, -0.1, 0.3, 0.02)])])
+    q = gaussian_coefficients(rng, 3, basis.shape[0])
+    _say("parabolic green + spectra 64x32")
+    tab = _tab(grid, basis, 3)
+    g = tab.green(sub.eps_r, sub.tan_delta, sub.h).cpu().numpy().reshape(3, -1)
+    spec = tab.spectra(torch.tensor(q, device="cuda")).cpu().numpy().reshape(3, 4, -1)
+    tab.close()
+    kx, ky = co.grid_samples(grid.nx, grid.ny, grid.kx_max, grid.ky_max)
+    kcx, kcy, _, gam = co.grid_contour(kx, ky, grid)
+    ref_g = np.stack(co.green_remainder(kx, ky, gam, grid.k0, sub.eps_r, sub.tan_delta, sub.h))
+    assert _err(g, ref_g) < 1e-12
+    mt, mh = co.mbf_spectra(basis, q, kcx, kcy)
+    assert _err(spec, np.concatenate([mt, mh], axis=1)) < 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,order", [(64, 32, 3), (32, 64, 2), (16, 128, 1), (256, 16, 3)])
+def test_parabolic_full_grid(nx, ny, order):
+    """Tables on the parabolic contour ((P+1)(P+2)/2 row transforms, no ky
+    factor in the column pass, per-sample weight), FP64 and mixed."""
+    rng = np.random.default_rng(700 + nx + ny + order)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 1), (1, 0), (1, 1)]
+    for prec, tol in [(FP64, 1e-10), (MIXED, 1e-5)]:
+        grid = _para(Grid(nx, ny, 9 * K0, 7 * K0, K0, gamma=1 / 50, order=order, precision=prec), 4.5 * K0)
+        _full_case(f"parabolic {nx}x{ny} P={order} prec={prec}", grid, Substrate(4.4, 0.002, 0.06), basis, q, pairs,
+                   tol)
+
+
+def test_parabolic_c2_sampled():
+    """The 512^2 workload on a parabolic contour (beta_end = 2 k0 sqrt(eps_r)),
+    FP64, at sampled outputs; the adjoint of a parabolic grid is refused."""
+    from paper_1404_7357_amd import CfftError, cfft_backward
+    wl = c2_rooftop_512()
+    sub = wl.substrates[0]
+    grid = _para(wl.grids[0], 2.0 * K0 * math.sqrt(sub.eps_r))
+    _say("c2 parabolic")
+    tab = _tab(grid, wl.basis, wl.M)
+    q = torch.tensor(wl.q, device="cuda")
+    g = tab.green(sub.eps_r, sub.tan_delta, sub.h)
+    spec = tab.spectra(q)
+    z = tab.tabulate(spec, g, [tuple(int(v) for v in p) for p in wl.pairs]).cpu().numpy()
+    idx = _sample_idx(grid.nx, grid.ny, 24, 21)
+    ref = co.tabulate(grid, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=8)
+    zs = z.reshape(len(wl.pairs), -1)[:, idx]
+    err = (np.abs(zs - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
+    assert err < 1e-10, err
+    dz = torch.zeros((len(wl.pairs), grid.ny, grid.nx), dtype=torch.complex128, device="cuda")
+    with pytest.raises(CfftError):
+        cfft_backward(tab.plan, 0, dz, sub.eps_r, sub.tan_delta, sub.h, tab.basis, q, wl.pairs.tolist(), g, spec,
+                      torch.empty(2, dtype=torch.float64, device="cuda"), torch.empty_like(q))
+    tab.close()
 
 
 def test_many_pairs_chunked(monkeypatch):
