@@ -109,6 +109,15 @@ bool build_geometry(const cfft_basis_t* basis, int nb, GeomHost& out) {
       g.yoff = (int)out.ys.size();
       g.ioff = (int)out.index.size();
       g.uoff = g.poff = 0;   // set below, once the group order is final
+      auto spacing = [](const std::vector<double>& v, double& step) {
+        step = v.size() > 1 ? (v.back() - v.front()) / (double)(v.size() - 1) : 0.0;
+        const double tol = 1e-12 * std::max(std::fabs(v.front()) + std::fabs(v.back()), std::fabs(step));
+        for (size_t i = 0; i < v.size(); ++i)
+          if (std::fabs(v[i] - (v.front() + (double)i * step)) > tol) return false;
+        return true;
+      };
+      const bool ux = spacing(xs, g.dxc), uy = spacing(ys, g.dyc);
+      g.uniform = ux && uy ? 1 : 0;
       std::vector<int> idx((size_t)g.np * g.nr, -1);
       for (int j : mem) {
         const int p = (int)(std::lower_bound(xs.begin(), xs.end(), basis[j].cx) - xs.begin());
@@ -639,9 +648,13 @@ cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* ba
   if (st != CFFT_OK) return st;
   hipError_t e;
   if (gs.d.contour == CFFT_CONTOUR_PARABOLIC) {
+    st = ensure_ws(&plan->ws3, &plan->ws3_bytes, sizeof(double2) * spectra_direct_scratch_len(plan->geo_dev, nmbf),
+                   "spectra scratch");
+    if (st != CFFT_OK) return st;
     const Contour c{gs.d.gamma, 1, gs.d.beta_end};
     ProfScope ps(plan, 1, s);
-    e = launch_spectra_direct(gs.x, gs.y, c, plan->geo_dev, (const double2*)q, nmbf, (double2*)spec, s);
+    e = launch_spectra_direct(gs.x, gs.y, c, plan->geo_dev, (const double2*)q, nmbf, (double2*)plan->ws3,
+                              (double2*)spec, s);
   } else {
     st = ensure_ws(&plan->ws3, &plan->ws3_bytes, sizeof(double2) * spectra_scratch_len(gs.y, plan->geo_dev, nmbf),
                    "spectra scratch");

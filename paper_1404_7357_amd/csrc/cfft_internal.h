@@ -48,7 +48,9 @@ struct GeomGroup {
   int uoff;           // row offset of this group's x tables (U rows)
   int poff;           // offset of this group's centres in the per-row w tables,
                       // each group padded to a multiple of kSpecPChunk
+  int uniform;        // 1: x-centres and y-centres are each equally spaced
   double a, b;
+  double dxc, dyc;    // centre spacings when uniform (0 for a single centre)
 };
 
 struct GeomDevice {
@@ -90,7 +92,8 @@ hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const Geom
                           double2* spec, hipStream_t s);
 // Spectra on the parabolic contour (no per-axis separation): per sample.
 hipError_t launch_spectra_direct(const Axis& x, const Axis& y, const Contour& c, const GeomDevice& geo,
-                                 const double2* q, int nmbf, double2* spec, hipStream_t s);
+                                 const double2* q, int nmbf, double2* scratch, double2* spec, hipStream_t s);
+size_t spectra_direct_scratch_len(const GeomDevice& geo, int nmbf);
 size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf);
 size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf);
 

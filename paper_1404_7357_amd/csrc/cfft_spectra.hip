@@ -290,12 +290,14 @@ hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const Geom
 // directly, F_j(k_c) = SX(kcx) SY(kcy) exp(-i k_c . c_j) with
 // exp(-i k_c . c) = exp(g k.c) (cos k.c - i sin k.c) and, for the reflected
 // spectrum, exp(+i k_c . c) = exp(-g k.c) (cos k.c + i sin k.c) (the shape
-// factors are even).  One thread per sample; the coefficients of a basis are
-// the same for every thread (wave-uniform loads); MBFs in chunks of kMChunk.
+// factors are even).  Groups whose centres are equally spaced in x and y use
+// per-axis recurrences instead (one complex product per centre step).  One
+// thread per sample; the coefficients of a basis are the same for every
+// thread (wave-uniform loads); MBFs in chunks of kMChunk.
 constexpr int kDirectThreads = 256;
 __global__ void __launch_bounds__(kDirectThreads)
-spectra_direct_kernel(Axis x, Axis y, Contour cont, GeomDevice geo, const double2* __restrict__ q, int nmbf,
-                      double2* __restrict__ spec) {
+spectra_direct_kernel(Axis x, Axis y, Contour cont, GeomDevice geo, const double2* __restrict__ q,
+                      const double2* __restrict__ qd, int nmbf, double2* __restrict__ spec) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= x.n * y.n) return;
   const int n1 = idx % x.n, n2 = idx / x.n;
@@ -318,6 +320,53 @@ spectra_direct_kernel(Axis x, Axis y, Contour cont, GeomDevice geo, const double
         const double2 sx = is_ydir(gr.kind) ? across_factor(gr.b, kcx) : along_factor(gr.kind, gr.a, kcx);
         const double2 sy = is_ydir(gr.kind) ? along_factor(gr.kind, gr.a, kcy) : across_factor(gr.b, kcy);
         const double2 shape = cmul(sx, sy);
+        if (gr.uniform) {
+          // equally spaced centres: the x and y phase factors follow by
+          // recurrence, U_{p+1} = U_p Rx, V_{r+1} = V_r Ry, and the sum over r
+          // is formed once per x-centre: M += shape U_p sum_r conj(q) V_r
+          double2 u, uh, rx, rxh, v0, v0h, ry, ryh;
+          phase_pair(kx, g, geo.xs[gr.xoff], u, uh);
+          phase_pair(kx, g, gr.dxc, rx, rxh);
+          phase_pair(ky, g, geo.ys[gr.yoff], v0, v0h);
+          phase_pair(ky, g, gr.dyc, ry, ryh);
+          double2 ga[kMChunk], gah[kMChunk];
+#pragma unroll
+          for (int i = 0; i < kMChunk; ++i) ga[i] = gah[i] = make_double2(0.0, 0.0);
+          for (int p = 0; p < gr.np; ++p) {
+            double2 w[kMChunk], wh[kMChunk];
+#pragma unroll
+            for (int i = 0; i < kMChunk; ++i) w[i] = wh[i] = make_double2(0.0, 0.0);
+            double2 v = v0, vh = v0h;
+            // coefficients in slot order (zero for empty slots): no index lookups
+            const double2* qrow = qd + gr.ioff + (size_t)p * gr.nr;
+#pragma unroll 4
+            for (int r = 0; r < gr.nr; ++r) {
+#pragma unroll
+              for (int i = 0; i < kMChunk; ++i) {
+                if (m0 + i < nmbf) {
+                  const double2 qv = qrow[(size_t)(m0 + i) * geo.total_idx + r];
+                  w[i] = cfma(w[i], v, make_double2(qv.x, -qv.y));   // conj(q) V
+                  wh[i] = cfma(wh[i], vh, qv);                       // q V#
+                }
+              }
+              v = cmul(v, ry);
+              vh = cmul(vh, ryh);
+            }
+#pragma unroll
+            for (int i = 0; i < kMChunk; ++i) {
+              ga[i] = cfma(ga[i], u, w[i]);
+              gah[i] = cfma(gah[i], uh, wh[i]);
+            }
+            u = cmul(u, rx);
+            uh = cmul(uh, rxh);
+          }
+#pragma unroll
+          for (int i = 0; i < kMChunk; ++i) {
+            acc[i] = cfma(acc[i], shape, ga[i]);
+            acch[i] = cfma(acch[i], shape, gah[i]);
+          }
+          continue;
+        }
         for (int p = 0; p < gr.np; ++p) {
           const double xc = geo.xs[gr.xoff + p];
           for (int r = 0; r < gr.nr; ++r) {
@@ -353,11 +402,27 @@ spectra_direct_kernel(Axis x, Axis y, Contour cont, GeomDevice geo, const double
   }
 }
 
+// qd[m][slot] = q[m][index[slot]] (0 for empty slots), slot order of the groups.
+__global__ void gather_slots_kernel(GeomDevice geo, const double2* __restrict__ q, int nmbf,
+                                    double2* __restrict__ qd) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nmbf * geo.total_idx) return;
+  const int m = e / geo.total_idx, li = e % geo.total_idx;
+  const int j = geo.index[li];
+  qd[e] = j < 0 ? make_double2(0.0, 0.0) : q[(size_t)m * geo.nbasis + j];
+}
+
+size_t spectra_direct_scratch_len(const GeomDevice& geo, int nmbf) { return (size_t)nmbf * geo.total_idx; }
+
 hipError_t launch_spectra_direct(const Axis& x, const Axis& y, const Contour& c, const GeomDevice& geo,
-                                 const double2* q, int nmbf, double2* spec, hipStream_t s) {
+                                 const double2* q, int nmbf, double2* scratch, double2* spec, hipStream_t s) {
+  const int ng = nmbf * geo.total_idx;
+  hipLaunchKernelGGL(gather_slots_kernel, dim3((ng + 255) / 256), dim3(256), 0, s, geo, q, nmbf, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int n = x.n * y.n;
   hipLaunchKernelGGL(spectra_direct_kernel, dim3((n + kDirectThreads - 1) / kDirectThreads), dim3(kDirectThreads), 0,
-                     s, x, y, c, geo, q, nmbf, spec);
+                     s, x, y, c, geo, q, scratch, nmbf, spec);
   return hipGetLastError();
 }
 
