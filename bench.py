@@ -143,6 +143,29 @@ def _copy_rate(torch, mib=1024, reps=20):
     return 2 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
+def _cpu_cfft(wl, z_gpu, workers):
+    """The CPU C-FFT baseline (eq. fftarry taken literally with scipy FFT2) on
+    the whole workload, with the GPU table's deviation from it."""
+    import numpy as np
+
+    from oracle import cfft_cpu
+    from oracle import cfft_oracle as co
+    grid, sub = wl.grids[0], wl.substrates[0]
+    t0 = time.perf_counter()
+    fac = co.sampled_factors(grid, sub, wl.basis, wl.q)
+    t1 = time.perf_counter()
+    z = cfft_cpu.tabulate_cfft(grid, sub, wl.basis, wl.q, wl.pairs, workers=workers, factors=fac)
+    t2 = time.perf_counter()
+    entries = z.size
+    dev = float((np.abs(z_gpu.reshape(z.shape) - z).reshape(len(wl.pairs), -1).max(axis=1)
+                 / np.abs(z).reshape(len(wl.pairs), -1).max(axis=1)).max())
+    return {"value": entries / (t2 - t0), "unit": "entries/s", "cores": workers, "kind": "cpu-cfft",
+            "seconds": t2 - t0, "seconds_factors": t1 - t0, "seconds_fft": t2 - t1,
+            "sample": f"whole table ({len(wl.pairs)} pairs x {grid.nx}x{grid.ny}), "
+                      f"{len(cfft_cpu.terms(grid.order))} FFT2 per pair, scipy.fft",
+            "rel_dev_gpu": dev}
+
+
 def _green_flops():
     """FP64 flops of one Green's-function launch (512^2 grid) from the committed rocprofv3 counters, if current."""
     path = os.path.join(ROOT, "profiles", "traffic_c2_fp64.json")
@@ -300,6 +323,28 @@ def _parabolic_leg(torch, steps, warmup, n_out):
             "dtype": "f64", "kernels_ms": km}
 
 
+def _large_leg(torch, steps, warmup):
+    """The large configuration: 4096^2, 36 pairs (M = 6, B = 1024), mixed
+    precision, followed by the bilinear lookup of 10^5 displacements."""
+    from workloads import c4_large
+    wl = c4_large()
+    st = Step(wl, torch)
+    pts = torch.tensor(wl.queries, device="cuda")
+    vals = torch.empty((len(wl.pairs), pts.shape[0]), dtype=torch.complex128, device="cuda")
+
+    def step():
+        st.run()
+        st.tab.lookup(st.z, pts, out=vals)
+
+    sec = _time_steps(torch, step, steps, warmup)
+    sec_lookup = _time_steps(torch, lambda: st.tab.lookup(st.z, pts, out=vals), steps, 1)
+    km = _kernel_times(st, steps)
+    st.tab.close()
+    return {"workload": wl.name, "entries": st.entries(), "value": st.entries() / sec, "ms_per_step": sec * 1e3,
+            "lookup_ms": sec_lookup * 1e3, "lookups": int(pts.shape[0]) * len(wl.pairs),
+            "dtype": "fp32 FFT / fp64 rest", "kernels_ms": km}
+
+
 def _sweep(torch, steps, warmup):
     """Frequency sweep, 8 uneven grids x 16 pairs (mixed), eager and as one replayed HIP graph."""
     from paper_1404_7357_amd import Tabulator
@@ -405,11 +450,13 @@ def main():
     dom = max(("row_pass", "col_pass"), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
     avg_s = kernels[dom]["avg_ms"] * 1e-3
     achieved = launch_bytes[dom] / avg_s / 1e9
-    copy_gbs = _copy_rate(torch)
+    # the device copy rate (skipped in the short profiling runs, whose copy
+    # calibration must be the only large copy)
+    copy_gbs = None if args.no_extras else _copy_rate(torch)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(dom, launch_bytes[dom]),
                 "algorithmic_bytes_per_launch": launch_bytes[dom],
-                "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
+                "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None}
     for k in ("row_pass", "col_pass"):
         kernels[k]["pairs_per_launch"] = per_launch[k]
         kernels[k]["algorithmic_bytes_per_launch"] = launch_bytes[k]
@@ -433,6 +480,8 @@ def main():
         base, err, sample = _cpu_baseline(wl, z_fp64, args.cpu_outputs, workers)
         out["cpu_baseline"] = base
         out["rel_err_vs_oracle"] = err
+        _log("cpu C-FFT baseline (eq. fftarry with scipy FFT2, whole table)")
+        out["cpu_cfft"] = _cpu_cfft(wl, z_fp64, workers)
     else:
         sample = None
 
@@ -458,6 +507,8 @@ def main():
                          "mixed": _tensor_leg(torch, args.steps, args.warmup, MIXED, max(n_out, 4))}
         _log("parabolic-contour leg (FP64)")
         out["parabolic"] = _parabolic_leg(torch, max(3, args.steps // 5), 2, max(n_out, 4))
+        _log("large leg (4096^2, 36 pairs, 10^5 lookups)")
+        out["large"] = _large_leg(torch, 3, 1)
         _log("sweep leg (8 grids, one graph)")
         out["sweep"] = _sweep(torch, max(3, args.steps // 5), 2)
         _log("adjoint leg (1024^2, 16 pairs, 4096 lookups)")

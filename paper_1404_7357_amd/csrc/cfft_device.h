@@ -124,12 +124,15 @@ __device__ __forceinline__ void contour_ratio(double beta, double gamma, int par
   else slope = beta < beta_end ? gamma * (1.0 - 2.0 * beta / beta_end) : 0.0;
 }
 
-// Non-temporal (streaming) accesses for data touched once.
+// Non-temporal (streaming) accesses for data touched once; the store moves
+// the whole complex value in one instruction.
 template <typename V> __device__ __forceinline__ void store_nt(V* p, V v) {
   using Rl = typename real_of<V>::type;
-  Rl* q = reinterpret_cast<Rl*>(p);
-  __builtin_nontemporal_store(v.x, q);
-  __builtin_nontemporal_store(v.y, q + 1);
+  typedef Rl pair_t __attribute__((ext_vector_type(2)));
+  pair_t w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<pair_t*>(p));
 }
 template <typename V> __device__ __forceinline__ V load_nt(const V* p) {
   using Rl = typename real_of<V>::type;
