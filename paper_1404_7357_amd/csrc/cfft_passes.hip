@@ -55,6 +55,9 @@
 #ifndef CFFT_COL_LDP_EXTRA
 #define CFFT_COL_LDP_EXTRA 4
 #endif
+#ifndef CFFT_COL_WIDE_FP32
+#define CFFT_COL_WIDE_FP32 1
+#endif
 #ifndef CFFT_COL_MIN_WAVES
 #define CFFT_COL_MIN_WAVES 0
 #endif
@@ -469,13 +472,16 @@ __global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
 // Points per thread of the column pass.
 __host__ __device__ constexpr int col_r(int) { return 8; }
 
-// Column tile width: as close to 128 B of contiguous row data as an 80 KiB
-// LDS tile and 512 threads allow (1024-thread blocks would cap the kernel at
-// 128 VGPRs and spill).
+// Column tile width: as close to CFFT_COL_ROW_BYTES of contiguous row data as
+// an 80 KiB LDS tile and 512 threads allow (1024-thread blocks cap a kernel at
+// 128 VGPRs: the FP64 kernels would spill; the FP32 kernels of columns of
+// 2048 and 4096, whose tiles are otherwise one or two columns wide, take
+// 1024 threads when CFFT_COL_WIDE_FP32 is set).
 __host__ __device__ constexpr int col_tile_c(int ny, int bytes) {
   int c = CFFT_COL_ROW_BYTES / bytes;
   const int r = col_r(bytes);
-  while (c > 1 && (c * (lds_len(ny) + CFFT_COL_LDP_EXTRA) * bytes > 81920 || c * (ny / r) > 512)) c /= 2;
+  const int max_threads = (CFFT_COL_WIDE_FP32 && bytes == 8 && ny >= 2048) ? 1024 : 512;
+  while (c > 1 && (c * (lds_len(ny) + CFFT_COL_LDP_EXTRA) * bytes > 81920 || c * (ny / r) > max_threads)) c /= 2;
   return c;
 }
 
