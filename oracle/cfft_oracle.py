@@ -457,6 +457,45 @@ def bilinear_lookup(grid, table, pts):
             + (1 - tx) * ty * t[:, j2 + 1, j1] + tx * ty * t[:, j2 + 1, j1 + 1])
 
 
+def quadratic_nodes(grid, pts):
+    """Stencil centre and offsets of second-order (3 x 3 Lagrange) interpolation.
+
+    Sec. III-B.3, last paragraph: the refined table is searched with a
+    second-order interpolation.  Reading: per axis the three nodes around the
+    nearest one, c - 1, c, c + 1, with c = round(u) kept in [1, n-2] (u the
+    fractional table index), and the quadratic Lagrange weights in
+    t = u - c: t (t - 1)/2, 1 - t^2, t (t + 1)/2.  Points must satisfy
+    0 <= u <= n - 1 on both axes.  Returns (c1, c2, tx, ty).
+    """
+    pts = np.asarray(pts, dtype=np.float64)
+    x_max = grid.nx * math.pi / (2.0 * grid.kx_max)
+    y_max = grid.ny * math.pi / (2.0 * grid.ky_max)
+    ux = (pts[:, 0] + x_max) / (math.pi / grid.kx_max)
+    uy = (pts[:, 1] + y_max) / (math.pi / grid.ky_max)
+    if np.any(ux < 0) or np.any(ux > grid.nx - 1) or np.any(uy < 0) or np.any(uy > grid.ny - 1):
+        raise ValueError("query outside the table")
+    c1 = np.clip(np.floor(ux + 0.5).astype(np.int64), 1, grid.nx - 2)
+    c2 = np.clip(np.floor(uy + 0.5).astype(np.int64), 1, grid.ny - 2)
+    return c1, c2, ux - c1, uy - c2
+
+
+def lagrange3(t):
+    """Quadratic Lagrange weights of the nodes -1, 0, +1 at offset t."""
+    return np.stack([0.5 * t * (t - 1.0), (1.0 - t) * (1.0 + t), 0.5 * t * (t + 1.0)])
+
+
+def quadratic_lookup(grid, table, pts):
+    """Second-order interpolation of table [npairs][ny][nx] at pts [Q][2] -> [npairs][Q]."""
+    c1, c2, tx, ty = quadratic_nodes(grid, pts)
+    wx, wy = lagrange3(tx), lagrange3(ty)
+    t = np.asarray(table)
+    out = np.zeros((t.shape[0], len(c1)), dtype=np.complex128)
+    for b in range(3):
+        for a in range(3):
+            out += wy[b] * wx[a] * t[:, c2 + b - 1, c1 + a - 1]
+    return out
+
+
 def lookup_direct(grid, substrate, basis, q, pairs, pts, workers=1):
     """Bilinear lookup with the four corners evaluated by direct sum only."""
     j1, j2, tx, ty = bilinear_corners(grid, pts)

@@ -256,3 +256,27 @@ def test_bilinear_lookup_reproduces_nodes_and_planes():
     assert np.abs(got - table[0].ravel()[:30][inner]).max() < 1e-12
     with pytest.raises(ValueError):
         co.bilinear_lookup(grid, table, np.array([[dxa[-1] + 0.01, 0.0]]))
+
+
+def test_quadratic_lookup_is_exact_for_quadratics_and_at_nodes():
+    """Second-order interpolation (Sec. III-B.3): exact on any table that is
+    a product of quadratics in the two indices, equal to the node value at a
+    node, and never reading outside the table at the edges."""
+    grid = Grid(16, 8, 5 * K0, 3 * K0, K0)
+    j1 = np.arange(16)
+    j2 = np.arange(8)
+    px = lambda u: 0.3 - 1.1j * u + (0.25 + 0.1j) * u * u
+    py = lambda u: 1.0 + 0.4 * u - 0.05j * u * u
+    table = (py(j2)[:, None] * px(j1)[None, :])[None]
+    dxa = co.displacement_axis(16, grid.kx_max)
+    dya = co.displacement_axis(8, grid.ky_max)
+    rng = np.random.default_rng(8)
+    ux = np.concatenate([rng.uniform(0, 15, 40), [0.0, 15.0, 0.2, 14.9]])
+    uy = np.concatenate([rng.uniform(0, 7, 40), [0.0, 7.0, 6.95, 0.01]])
+    pts = np.stack([dxa[0] + ux * (dxa[1] - dxa[0]), dya[0] + uy * (dya[1] - dya[0])], axis=1)
+    got = co.quadratic_lookup(grid, table, pts)[0]
+    assert np.abs(got - py(uy) * px(ux)).max() < 1e-12 * np.abs(got).max()
+    node = np.array([[dxa[5], dya[3]]])
+    assert abs(co.quadratic_lookup(grid, table, node)[0, 0] - table[0, 3, 5]) < 1e-14 * abs(table[0, 3, 5])
+    with pytest.raises(ValueError):
+        co.quadratic_lookup(grid, table, np.array([[dxa[-1] + 1e-9, 0.0]]))
