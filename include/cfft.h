@@ -176,6 +176,15 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
 cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t npairs,
                           const double* pts, int32_t npts, void* out, void* stream);
 
+/* Second-order interpolation in the table (Sec. III-B.3, last paragraph:
+ * the refined tables are searched with a second-order method).  Per axis the
+ * three nodes c-1, c, c+1 around the nearest node c (kept inside the
+ * table), with quadratic Lagrange weights.  Same arguments and output as
+ * cfft_lookup; a point outside [Dx(0), Dx(nx-1)] x [Dy(0), Dy(ny-1)] yields
+ * NaN. */
+cfft_status_t cfft_lookup_quadratic(cfft_plan_t plan, int32_t grid, const void* z, int32_t npairs,
+                                    const double* pts, int32_t npts, void* out, void* stream);
+
 /* Adjoint of cfft_lookup: dz[p][j2][j1] += sum over points of the bilinear
  * weight times dout[p][q] (complex128, FP64 grids only).  dz must be zeroed
  * by the caller before the first accumulation. */

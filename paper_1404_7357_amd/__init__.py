@@ -20,12 +20,14 @@ import torch
 from . import _lib
 from ._lib import (CONTOUR_RAY, FLAG_AUTOTUNE, FLAG_CHECK_FINITE, FP64, MIXED, TRUNC_TENSOR, TRUNC_TOTAL,  # noqa: F401
                    CfftError, Plan, cfft_backward,
-                   cfft_lookup, cfft_lookup_backward, cfft_tabulate, mbf_spectra, slab_green_eval)
+                   cfft_lookup, cfft_lookup_backward, cfft_lookup_quadratic, cfft_tabulate, mbf_spectra,
+                   slab_green_eval)
 
 _lib.load()
 
 __all__ = ["Tabulator", "Plan", "CfftError", "TableFunction", "LookupFunction", "FP64", "MIXED",
-           "slab_green_eval", "mbf_spectra", "cfft_tabulate", "cfft_lookup", "cfft_lookup_backward",
+           "slab_green_eval", "mbf_spectra", "cfft_tabulate", "cfft_lookup", "cfft_lookup_quadratic",
+           "cfft_lookup_backward",
            "cfft_backward", "displacement_axis"]
 
 
@@ -71,10 +73,17 @@ class Tabulator:
         cfft_tabulate(self.plan, grid, spec, spec.shape[0], g, pairs, z, stream)
         return z
 
-    def lookup(self, z, pts, grid: int = 0, out=None, stream=None):
+    def lookup(self, z, pts, grid: int = 0, out=None, stream=None, order: int = 1):
+        """Table values at displacements pts [Q][2]: bilinear (order 1) or
+        second-order Lagrange (order 2) interpolation."""
         out = out if out is not None else torch.empty((z.shape[0], pts.shape[0]), dtype=torch.complex128,
                                                       device=self.device)
-        cfft_lookup(self.plan, grid, z, z.shape[0], pts.contiguous(), out, stream)
+        if order == 2:
+            cfft_lookup_quadratic(self.plan, grid, z, z.shape[0], pts.contiguous(), out, stream)
+        elif order == 1:
+            cfft_lookup(self.plan, grid, z, z.shape[0], pts.contiguous(), out, stream)
+        else:
+            raise ValueError("order must be 1 or 2")
         return out
 
     def close(self):

@@ -26,7 +26,8 @@ FLAG_CHECK_FINITE = 1
 FLAG_AUTOTUNE = 2
 
 ENTRY_POINTS = ("c_fft_plan", "c_fft_plan_destroy", "slab_green_eval", "mbf_spectra", "cfft_tabulate",
-                "cfft_lookup", "cfft_lookup_backward", "cfft_backward", "cfft_profile", "cfft_profile_read",
+                "cfft_lookup", "cfft_lookup_quadratic", "cfft_lookup_backward", "cfft_backward", "cfft_profile",
+                "cfft_profile_read",
                 "cfft_last_error", "cfft_version")
 
 PROFILE_CLASSES = {"green": 0, "spectra": 1, "row_pass": 2, "col_pass": 3, "lookup": 4, "adj_col_pass": 5,
@@ -72,6 +73,7 @@ def load(path: str = LIB_PATH):
     lib.mbf_spectra.argtypes = [vp, i32, ctypes.POINTER(Basis), i32, vp, i32, vp, vp]
     lib.cfft_tabulate.argtypes = [vp, i32, vp, i32, vp, ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
     lib.cfft_lookup.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
+    lib.cfft_lookup_quadratic.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_lookup_backward.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_backward.argtypes = [vp, i32, vp, dbl, dbl, dbl, ctypes.POINTER(Basis), i32, vp, i32,
                                   ctypes.POINTER(ctypes.c_int32), i32, vp, vp, vp, vp, vp]
@@ -169,6 +171,11 @@ def cfft_tabulate(plan: Plan, grid: int, spec, nmbf: int, g, pairs, z, stream=No
 def cfft_lookup(plan: Plan, grid: int, z, npairs: int, pts, out, stream=None):
     check(load().cfft_lookup(plan.handle, grid, _ptr(z), int(npairs), _ptr(pts), int(pts.shape[0]), _ptr(out),
                              _stream(stream)))
+
+
+def cfft_lookup_quadratic(plan: Plan, grid: int, z, npairs: int, pts, out, stream=None):
+    check(load().cfft_lookup_quadratic(plan.handle, grid, _ptr(z), int(npairs), _ptr(pts), int(pts.shape[0]),
+                                       _ptr(out), _stream(stream)))
 
 
 def cfft_lookup_backward(plan: Plan, grid: int, dout, npairs: int, pts, dz, stream=None):

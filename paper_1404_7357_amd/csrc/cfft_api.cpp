@@ -812,8 +812,8 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   return check_finite(plan, z, 2 * n * (size_t)npairs, pp.precision != CFFT_FP64, s);
 }
 
-cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t npairs, const double* pts,
-                          int32_t npts, void* out, void* stream) {
+static cfft_status_t lookup_common(cfft_plan_t plan, int32_t grid, const void* z, int32_t npairs, const double* pts,
+                                   int32_t npts, void* out, void* stream, bool quadratic) {
   g_last_error.clear();
   cfft_status_t st = check_plan(plan, grid);
   if (st != CFFT_OK) return st;
@@ -825,10 +825,21 @@ cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t
   hipError_t e;
   {
     ProfScope ps(plan, 4, (hipStream_t)stream);
-    e = launch_lookup(pass_params(gs), z, npairs, pts, npts, (double2*)out, (hipStream_t)stream);
+    e = quadratic ? launch_lookup_quadratic(pass_params(gs), z, npairs, pts, npts, (double2*)out, (hipStream_t)stream)
+                  : launch_lookup(pass_params(gs), z, npairs, pts, npts, (double2*)out, (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(e, "lookup launch");
   return CFFT_OK;
+}
+
+cfft_status_t cfft_lookup_quadratic(cfft_plan_t plan, int32_t grid, const void* z, int32_t npairs, const double* pts,
+                                    int32_t npts, void* out, void* stream) {
+  return lookup_common(plan, grid, z, npairs, pts, npts, out, stream, true);
+}
+
+cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t npairs, const double* pts,
+                          int32_t npts, void* out, void* stream) {
+  return lookup_common(plan, grid, z, npairs, pts, npts, out, stream, false);
 }
 
 cfft_status_t cfft_lookup_backward(cfft_plan_t plan, int32_t grid, const void* dout, int32_t npairs,

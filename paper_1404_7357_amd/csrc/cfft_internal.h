@@ -106,6 +106,8 @@ hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, v
 
 hipError_t launch_lookup(const PassParams& p, const void* z, int npairs, const double* pts,
                          int npts, double2* out, hipStream_t s);
+hipError_t launch_lookup_quadratic(const PassParams& p, const void* z, int npairs, const double* pts,
+                                  int npts, double2* out, hipStream_t s);
 hipError_t launch_lookup_backward(const PassParams& p, const double2* dout, int npairs,
                                   const double* pts, int npts, double2* dz, hipStream_t s);
 

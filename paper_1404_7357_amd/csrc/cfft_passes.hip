@@ -1012,6 +1012,56 @@ __global__ void lookup_kernel(LookupArgs a) {
                           w00 * z00.y + w01 * z01.y + w10 * z10.y + w11 * z11.y);
 }
 
+// Second-order interpolation (Sec. III-B.3, last paragraph): per axis the
+// nodes c - 1, c, c + 1 around the nearest node c = round(u), kept in
+// [1, n-2], with the quadratic Lagrange weights in t = u - c.  Points need
+// 0 <= u <= n - 1 on both axes; others (and NaN) yield NaN.
+__device__ __forceinline__ bool stencil_of(const LookupArgs& a, int q, int& c1, int& c2, double& tx, double& ty) {
+  const double ux = (a.pts[2 * q] - a.x0) / a.ddx;
+  const double uy = (a.pts[2 * q + 1] - a.y0) / a.ddy;
+  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux <= (double)(a.nx - 1)) || !(uy <= (double)(a.ny - 1))) return false;
+  c1 = min(max((int)floor(ux + 0.5), 1), a.nx - 2);
+  c2 = min(max((int)floor(uy + 0.5), 1), a.ny - 2);
+  tx = ux - c1;
+  ty = uy - c2;
+  return true;
+}
+
+__device__ __forceinline__ void lagrange3(double t, double (&w)[3]) {
+  w[0] = 0.5 * t * (t - 1.0);
+  w[1] = (1.0 - t) * (1.0 + t);
+  w[2] = 0.5 * t * (t + 1.0);
+}
+
+__global__ void lookup_quadratic_kernel(LookupArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.npairs * a.npts) return;
+  const int p = e / a.npts, q = e % a.npts;
+  int c1, c2;
+  double tx, ty;
+  if (!stencil_of(a, q, c1, c2, tx, ty)) {
+    a.out[e] = make_double2(__builtin_nan(""), __builtin_nan(""));
+    return;
+  }
+  double wx[3], wy[3];
+  lagrange3(tx, wx);
+  lagrange3(ty, wy);
+  const size_t base = (size_t)p * a.nx * a.ny;
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const size_t row = base + (size_t)(c2 + b - 1) * a.nx + (c1 - 1);
+    double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double2 z = a.precision == 0 ? ((const double2*)a.z)[row + i] : to_d(((const float2*)a.z)[row + i]);
+      s = make_double2(s.x + wx[i] * z.x, s.y + wx[i] * z.y);
+    }
+    acc = make_double2(acc.x + wy[b] * s.x, acc.y + wy[b] * s.y);
+  }
+  a.out[e] = acc;
+}
+
 __global__ void lookup_backward_kernel(LookupArgs a, const double2* __restrict__ dout, double2* dz) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.npairs * a.npts) return;
@@ -1054,6 +1104,14 @@ hipError_t launch_lookup(const PassParams& p, const void* z, int npairs, const d
   const LookupArgs a = lookup_args(p, z, npairs, pts, npts, out);
   const long long n = (long long)npairs * npts;
   hipLaunchKernelGGL(lookup_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lookup_quadratic(const PassParams& p, const void* z, int npairs, const double* pts, int npts,
+                                  double2* out, hipStream_t s) {
+  const LookupArgs a = lookup_args(p, z, npairs, pts, npts, out);
+  const long long n = (long long)npairs * npts;
+  hipLaunchKernelGGL(lookup_quadratic_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -324,6 +324,30 @@ def test_lookup_matches_oracle_bilinear():
         assert np.isnan(out[:, -2:]).all()
 
 
+def test_lookup_quadratic_matches_oracle():
+    """Second-order lookup (3 x 3 Lagrange stencil) vs the oracle's, FP64 and
+    complex64 tables, with points on the table edges and outside (NaN)."""
+    _say("lookup quadratic")
+    from paper_1404_7357_amd import Tabulator
+    rng = np.random.default_rng(13)
+    for prec in (FP64, MIXED):
+        grid = Grid(64, 32, 8 * K0, 6 * K0, K0, precision=prec)
+        tab = Tabulator(grid, rooftop_lattice(1, 1), 1)
+        dt = torch.complex128 if prec == FP64 else torch.complex64
+        table = (rng.standard_normal((3, 32, 64)) + 1j * rng.standard_normal((3, 32, 64)))
+        zt = torch.tensor(table, dtype=dt, device="cuda")
+        dxa = co.displacement_axis(64, grid.kx_max)
+        dya = co.displacement_axis(32, grid.ky_max)
+        pts = np.stack([rng.uniform(dxa[0], dxa[-1], 500), rng.uniform(dya[0], dya[-1], 500)], 1)
+        pts = np.concatenate([pts, [[dxa[0], dya[0]], [dxa[-1], dya[-1]], [dxa[3], dya[7]]],
+                              [[dxa[-1] + 1e-6, 0.0], [0.0, dya[0] - 0.5], [float("nan"), 0.0]]])
+        out = tab.lookup(zt, torch.tensor(pts, device="cuda"), order=2).cpu().numpy()
+        tab.close()
+        ref = co.quadratic_lookup(grid, zt.cpu().numpy().astype(np.complex128), pts[:-3])
+        assert np.abs(out[:, :-3] - ref).max() < 1e-13
+        assert np.isnan(out[:, -3:]).all()
+
+
 def test_nonfinite_flag_reports_nan_input():
     _say("non-finite flag")
     from paper_1404_7357_amd import FLAG_CHECK_FINITE, CfftError
