@@ -50,6 +50,9 @@ def tabulate_cfft(grid, substrate, basis, q, pairs, workers=1, factors=None):
     kscale = (2.0 * grid.kx_max / nx) * (2.0 * grid.ky_max / ny) / (4.0 * math.pi ** 2) * sigma
     keep = terms(grid.order, getattr(grid, "truncation", 0))
     integ = co.pair_integrands(pairs, w, g, mt, mh)
+    mask = co.band_mask(grid)
+    if mask is not None:
+        integ = integ * mask
     out = np.empty((len(pairs), ny, nx), dtype=np.complex128)
     for p in range(len(pairs)):
         i_f = integ[p].reshape(ny, nx) * alt

@@ -376,6 +376,26 @@ def pair_integrands(pairs, w, g, mt, mh):
     return np.stack([integrand(mt[m], mh[n], gxx, gxy, gyy, w) for m, n in pairs])
 
 
+def band_mask(grid):
+    """Samples that carry the integrand on a x2 zero-padded grid.
+
+    Sec. III-B.3, last paragraph: the tables are refined by Whittaker-Shannon
+    interpolation with zero padding to twice the FFT size.  Reading: a grid
+    with zero_pad set is the padded grid itself (2N samples over twice the
+    spectral span, same spacing); the original samples are its central half
+    on each axis, n in [N'/4, 3N'/4), and every other sample is zero.  The
+    table then has half the displacement step over the same span.  Returns a
+    flat boolean array (x fastest) or None when the grid is not padded.
+    """
+    if not getattr(grid, "zero_pad", 0):
+        return None
+    n1 = np.arange(grid.nx)
+    n2 = np.arange(grid.ny)
+    in1 = (n1 >= grid.nx // 4) & (n1 < 3 * grid.nx // 4)
+    in2 = (n2 >= grid.ny // 4) & (n2 < 3 * grid.ny // 4)
+    return (in2[:, None] & in1[None, :]).ravel()
+
+
 def tabulate(grid, substrate, basis, q, pairs, out_idx=None, order=None, workers=1):
     """Table Z'_mn on the displacement grid (or on a subset of it).
 
@@ -385,6 +405,9 @@ def tabulate(grid, substrate, basis, q, pairs, out_idx=None, order=None, workers
     order = grid.order if order is None else order
     kx, ky, w, g, mt, mh = sampled_factors(grid, substrate, basis, q)
     integ = pair_integrands(pairs, w, g, mt, mh)
+    mask = band_mask(grid)
+    if mask is not None:
+        integ = integ * mask
     dxa = displacement_axis(grid.nx, grid.kx_max)
     dya = displacement_axis(grid.ny, grid.ky_max)
     DX, DY = np.meshgrid(dxa, dya)
@@ -411,6 +434,9 @@ def tabulate_from_factors(grid, pairs, g, mt, mh, out_idx=None, order=None, work
     kx, ky = grid_samples(grid.nx, grid.ny, grid.kx_max, grid.ky_max)
     _, _, w, gam = grid_contour(kx, ky, grid)
     integ = pair_integrands(pairs, w, g, mt, mh)
+    mask = band_mask(grid)
+    if mask is not None:
+        integ = integ * mask
     dxa = displacement_axis(grid.nx, grid.kx_max)
     dya = displacement_axis(grid.ny, grid.ky_max)
     DX, DY = np.meshgrid(dxa, dya)

@@ -103,6 +103,7 @@ class Grid:
     beta_end: float = 0.0
     precision: int = FP64
     truncation: int = TRUNC_TOTAL
+    zero_pad: int = 0                  # 1: x2 zero-padded grid (integrand on the central half only)
 
 
 @dataclasses.dataclass
