@@ -88,8 +88,15 @@ enum { CFFT_ROOFTOP_X = 0, CFFT_ROOFTOP_Y = 1, CFFT_COSINE_X = 2, CFFT_COSINE_Y 
 /* CHECK_FINITE: scan every output for NaN/Inf and report CFFT_ERR_NONFINITE
  *   (makes the call synchronous).
  * AUTOTUNE: the first cfft_tabulate per (grid, npairs) times the candidate
- *   pair-chunk schedules (synchronously) and the plan keeps the fastest. */
-enum { CFFT_FLAG_CHECK_FINITE = 1, CFFT_FLAG_AUTOTUNE = 2 };
+ *   pair-chunk schedules (synchronously) and the plan keeps the fastest.
+ * ZERO_PAD2: every grid of the plan is the x2 zero-padded extension of the
+ *   grid the caller samples (Sec. III-B.3, last paragraph: Whittaker-Shannon
+ *   refinement with zero padding to twice the FFT size).  Only the central
+ *   half of the samples on each axis, n in [N/4, 3N/4), carries the
+ *   integrand; the table then has half the displacement step over the same
+ *   span, and its even nodes are the unrefined table.  The adjoint refuses
+ *   such a plan. */
+enum { CFFT_FLAG_CHECK_FINITE = 1, CFFT_FLAG_AUTOTUNE = 2, CFFT_FLAG_ZERO_PAD2 = 4 };
 
 /* One spectral grid.  64 bytes, natural alignment. */
 typedef struct {

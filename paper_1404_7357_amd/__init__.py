@@ -18,10 +18,9 @@ import math
 import torch
 
 from . import _lib
-from ._lib import (CONTOUR_RAY, FLAG_AUTOTUNE, FLAG_CHECK_FINITE, FP64, MIXED, TRUNC_TENSOR, TRUNC_TOTAL,  # noqa: F401
-                   CfftError, Plan, cfft_backward,
-                   cfft_lookup, cfft_lookup_backward, cfft_lookup_quadratic, cfft_tabulate, mbf_spectra,
-                   slab_green_eval)
+from ._lib import (CONTOUR_RAY, FLAG_AUTOTUNE, FLAG_CHECK_FINITE, FLAG_ZERO_PAD2, FP64, MIXED,  # noqa: F401
+                   TRUNC_TENSOR, TRUNC_TOTAL, CfftError, Plan, cfft_backward, cfft_lookup, cfft_lookup_backward,
+                   cfft_lookup_quadratic, cfft_tabulate, mbf_spectra, slab_green_eval)
 
 _lib.load()
 

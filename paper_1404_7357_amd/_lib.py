@@ -24,6 +24,7 @@ FP64, MIXED = 0, 1
 TRUNC_TOTAL, TRUNC_TENSOR = 0, 1
 FLAG_CHECK_FINITE = 1
 FLAG_AUTOTUNE = 2
+FLAG_ZERO_PAD2 = 4
 
 ENTRY_POINTS = ("c_fft_plan", "c_fft_plan_destroy", "slab_green_eval", "mbf_spectra", "cfft_tabulate",
                 "cfft_lookup", "cfft_lookup_quadratic", "cfft_lookup_backward", "cfft_backward", "cfft_profile",

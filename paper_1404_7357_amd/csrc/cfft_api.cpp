@@ -175,6 +175,7 @@ struct GridState {
   double2* utab = nullptr;       // spectra tables for the current geometry
   uint64_t utab_geo = 0;
   size_t utab_bytes = 0;
+  int band = 0;                  // x2 zero-padded grid (CFFT_FLAG_ZERO_PAD2)
 };
 
 struct cfft_plan_s {
@@ -260,6 +261,7 @@ PassParams pass_params(const GridState& gs) {
   p.tensor = gs.d.truncation == CFFT_TRUNC_TENSOR ? 1 : 0;
   p.parabolic = gs.d.contour == CFFT_CONTOUR_PARABOLIC ? 1 : 0;
   p.beta_end = gs.d.beta_end;
+  p.band = gs.band;
   p.precision = gs.d.precision;
   return p;
 }
@@ -525,7 +527,7 @@ cfft_status_t c_fft_plan(const cfft_grid_desc_t* grids, int32_t ngrids, int32_t 
   if (!grids) return fail(CFFT_ERR_INVALID_ARG, "grids is NULL");
   if (ngrids < 1 || ngrids > 64) return fail(CFFT_ERR_INVALID_ARG, "ngrids %d outside [1, 64]", ngrids);
   if (max_mbf < 1 || max_mbf > 16) return fail(CFFT_ERR_INVALID_ARG, "max_mbf %d outside [1, 16]", max_mbf);
-  if (flags & ~(CFFT_FLAG_CHECK_FINITE | CFFT_FLAG_AUTOTUNE))
+  if (flags & ~(CFFT_FLAG_CHECK_FINITE | CFFT_FLAG_AUTOTUNE | CFFT_FLAG_ZERO_PAD2))
     return fail(CFFT_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
   for (int i = 0; i < ngrids; ++i) {
     const cfft_grid_desc_t& g = grids[i];
@@ -569,6 +571,7 @@ cfft_status_t c_fft_plan(const cfft_grid_desc_t* grids, int32_t ngrids, int32_t 
   for (int i = 0; i < ngrids; ++i) {
     GridState& gs = p->grids[i];
     gs.d = grids[i];
+    gs.band = (flags & CFFT_FLAG_ZERO_PAD2) ? 1 : 0;
     const double xm = gs.d.nx * M_PI / (2.0 * gs.d.kx_max);
     const double ym = gs.d.ny * M_PI / (2.0 * gs.d.ky_max);
     gs.x = Axis{gs.d.nx, -gs.d.kx_max, 2.0 * gs.d.kx_max / gs.d.nx, -xm, M_PI / gs.d.kx_max};
@@ -881,6 +884,7 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   GridState& gs = plan->grids[grid];
   if (gs.d.precision != CFFT_FP64) return fail(CFFT_ERR_UNSUPPORTED, "the adjoint needs an FP64 grid");
   if (gs.d.contour != CFFT_CONTOUR_RAY) return fail(CFFT_ERR_UNSUPPORTED, "the adjoint needs the ray contour");
+  if (gs.band) return fail(CFFT_ERR_UNSUPPORTED, "the adjoint does not handle zero-padded grids");
   hipStream_t s = (hipStream_t)stream;
   st = ensure_geometry(plan, gs, basis, nbasis, s);
   if (st != CFFT_OK) return st;

@@ -75,6 +75,7 @@ struct PassParams {
   int tensor;         // 1: tensor-product truncation (one intermediate per pair)
   int parabolic;      // 1: parabolic contour (per-sample ratio; N_t row transforms)
   double beta_end;
+  int band;           // 1: x2 zero-padded grid, integrand only on n in [N/4, 3N/4) per axis
 };
 
 // Intermediate arrays per pair between the row and column passes.

@@ -82,6 +82,7 @@ template <int N> struct RowCfg {
 
 struct RowArgs {
   int tensor;   // tensor-product truncation: only S_P is stored, in slot 0
+  int band;     // x2 zero-padded grid: integrand only on n in [N/4, 3N/4) per axis
   int parabolic;                // per-sample contour ratio (see row_terms_general)
   double ky0, dky, beta_end;
   const double2* g;
@@ -94,6 +95,9 @@ struct RowArgs {
   int pm[kMaxPairsPerLaunch];
   int pn[kMaxPairsPerLaunch];
 };
+
+// Sample n of an axis of n_len samples lies in the band of a x2 zero-padded grid.
+__device__ __forceinline__ bool in_band(int n, int n_len) { return n >= n_len / 4 && n < 3 * (n_len / 4); }
 
 // Contour weight W = (1 + i g)(1 + i beta_I') at the sample (kx, ky).
 template <typename Args>
@@ -192,6 +196,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
       h = cadd(cmul(mx, cadd(cmul(gxx, mxh), cmul(gxy, myh))), cmul(my, cadd(cmul(gxy, mxh), cmul(gyy, myh))));
       if (n1 & 1) h = make_double2(-h.x, -h.y);
       if (a.parabolic) h = cmul(h, contour_weight(a, a.kx0 + n1 * a.dkx, a.ky0 + n2 * a.dky));
+      if (a.band && !(in_band(n1, N) && in_band(n2, a.ny))) h = make_double2(0.0, 0.0);
     }
     f[r] = from_d<V>(h);
   }
@@ -244,6 +249,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a)
 // input arrays per pair instead of 7.
 struct RowGArgs {
   int tensor;
+  int band;
   int parabolic;
   double ky0, dky, beta_end;
   const double2* g;
@@ -302,6 +308,7 @@ __global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArg
       vx = cmul(vx, wc);
       vy = cmul(vy, wc);
     }
+    if (a.band && !(in_band(i, N) && in_band(n2, a.ny))) vx = vy = make_double2(0.0, 0.0);
     ax[i] = vx;
     ay[i] = vy;
   }
@@ -539,6 +546,7 @@ static hipError_t rowg_launch(const RowArgs& ra, hipStream_t s) {
   a.ny = ra.ny;
   a.order = ra.order;
   a.tensor = ra.tensor;
+  a.band = ra.band;
   a.parabolic = ra.parabolic;
   a.ky0 = ra.ky0;
   a.dky = ra.dky;
@@ -606,6 +614,7 @@ hipError_t launch_row_pass(const PassParams& p, const double2* g, const double2*
   a.ny = p.y.n;
   a.order = p.order;
   a.tensor = p.tensor;
+  a.band = p.band;
   a.parabolic = p.parabolic;
   a.ky0 = p.y.k_first;
   a.dky = p.y.dk;

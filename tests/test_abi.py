@@ -88,7 +88,7 @@ def test_plan_argument_checks():
     assert lib.c_fft_plan(desc, 1, 0, 0, ctypes.byref(h)) == 1
     assert lib.c_fft_plan(desc, 1, 17, 0, ctypes.byref(h)) == 1
     assert lib.c_fft_plan(desc, 1, 4, 0x100, ctypes.byref(h)) == 1
-    assert lib.c_fft_plan(desc, 1, 4, 4, ctypes.byref(h)) == 1
+    assert lib.c_fft_plan(desc, 1, 4, 8, ctypes.byref(h)) == 1
     assert lib.c_fft_plan(desc, 1, 4, 0, None) == 1
 
 

@@ -348,6 +348,43 @@ def test_lookup_quadratic_matches_oracle():
         assert np.isnan(out[:, -3:]).all()
 
 
+def test_zero_padded_refinement_and_quadratic_lookup():
+    """x2 zero-padded grid (Whittaker-Shannon refinement): the refined table
+    vs the oracle's, its even nodes vs the unrefined GPU table, and the
+    paper's table use (refined table + second-order lookup) vs the oracle.
+    The adjoint refuses such a plan."""
+    from paper_1404_7357_amd import FLAG_ZERO_PAD2, CfftError, Tabulator, cfft_backward
+    rng = np.random.default_rng(61)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 1), (1, 1)]
+    sub = Substrate(4.4, 0.002, 0.06)
+    for prec, tol in [(FP64, 1e-10), (MIXED, 1e-5)]:
+        base = Grid(64, 32, 8 * K0, 6 * K0, K0, precision=prec)
+        pad = dataclasses.replace(base, nx=128, ny=64, kx_max=16 * K0, ky_max=12 * K0, zero_pad=1)
+        _say(f"zero-padded 128x64 prec={prec}")
+        _, _, zb = _run(base, sub, basis, q, pairs)
+        tab = Tabulator(pad, basis, max_mbf=2, flags=FLAG_ZERO_PAD2)
+        qd = torch.tensor(q, device="cuda")
+        g = tab.green(sub.eps_r, sub.tan_delta, sub.h)
+        spec = tab.spectra(qd)
+        z = tab.tabulate(spec, g, pairs)
+        dxa = co.displacement_axis(pad.nx, pad.kx_max)
+        dya = co.displacement_axis(pad.ny, pad.ky_max)
+        pts = np.stack([rng.uniform(dxa[0], dxa[-1], 200), rng.uniform(dya[0], dya[-1], 200)], 1)
+        vals = tab.lookup(z, torch.tensor(pts, device="cuda"), order=2).cpu().numpy()
+        zz = z.cpu().numpy()
+        if prec == FP64:
+            with pytest.raises(CfftError):
+                cfft_backward(tab.plan, 0, torch.zeros_like(z), sub.eps_r, sub.tan_delta, sub.h, tab.basis, qd, pairs,
+                              g, spec, torch.empty(2, dtype=torch.float64, device="cuda"), torch.empty_like(qd))
+        tab.close()
+        ref = co.tabulate(pad, sub, basis, q, np.array(pairs))
+        assert _err(zz, ref) < tol
+        assert _err(zz[:, ::2, ::2], zb) < tol
+        assert _err(vals, co.quadratic_lookup(pad, ref, pts)) < tol
+
+
 def test_nonfinite_flag_reports_nan_input():
     _say("non-finite flag")
     from paper_1404_7357_amd import FLAG_CHECK_FINITE, CfftError
