@@ -522,6 +522,38 @@ def quadratic_lookup(grid, table, pts):
     return out
 
 
+def fill_reduced(grid, table, pairs, nmbf, positions, order=2):
+    """Substrate part of the reduced MoM matrix of an array of identical elements.
+
+    The reduced matrix is MA x MA (Sec. II, eq. MBF): block (i, j) holds the
+    interactions of the MBFs of testing element i with those of basis
+    element j.  Sec. III-B.1 and Sec. III-B.3 (last paragraph) fill it from
+    the table: entry (m, n) of block (i, j) is Z'_mn read at the relative
+    displacement r_i - r_j by low-order interpolation (order 2:
+    quadratic_lookup, order 1: bilinear_lookup).  Row i*M + m, column
+    j*M + n.  Self blocks (i = j; the paper computes them by the traditional
+    MBF method, Sec. IV-F), (m, n) not listed in pairs and displacements
+    outside the table stay NaN.
+    """
+    pos = np.asarray(positions, dtype=np.float64)
+    a_count = pos.shape[0]
+    out = np.full((a_count * nmbf, a_count * nmbf), complex(np.nan, np.nan))
+    ii, jj = np.nonzero(~np.eye(a_count, dtype=bool))
+    delta = pos[ii] - pos[jj]
+    x_max = grid.nx * math.pi / (2.0 * grid.kx_max)
+    y_max = grid.ny * math.pi / (2.0 * grid.ky_max)
+    ux = (delta[:, 0] + x_max) / (math.pi / grid.kx_max)
+    uy = (delta[:, 1] + y_max) / (math.pi / grid.ky_max)
+    inside = (ux >= 0) & (ux <= grid.nx - 1) & (uy >= 0) & (uy <= grid.ny - 1)
+    if order == 1:
+        inside &= (ux < grid.nx - 1) & (uy < grid.ny - 1)
+    ii, jj, delta = ii[inside], jj[inside], delta[inside]
+    vals = (quadratic_lookup if order == 2 else bilinear_lookup)(grid, table, delta)
+    for p, (m, n) in enumerate(pairs):
+        out[ii * nmbf + m, jj * nmbf + n] = vals[p]
+    return out
+
+
 def lookup_direct(grid, substrate, basis, q, pairs, pts, workers=1):
     """Bilinear lookup with the four corners evaluated by direct sum only."""
     j1, j2, tx, ty = bilinear_corners(grid, pts)
