@@ -192,6 +192,26 @@ cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t
 cfft_status_t cfft_lookup_quadratic(cfft_plan_t plan, int32_t grid, const void* z, int32_t npairs,
                                     const double* pts, int32_t npts, void* out, void* stream);
 
+/* Reduced-matrix fill for an array of identical elements (Sec. II eq. MBF:
+ * the reduced matrix is MA x MA; Sec. III-B.1 and the last paragraph of
+ * Sec. III-B.3: its blocks are read from the table by low-order
+ * interpolation).  For every ordered pair of distinct elements (i, j) and
+ * every listed MBF pair k = (m, n):
+ *   out[(i*nmbf + m) * (nelem*nmbf) + j*nmbf + n] = Z'_mn(r_i - r_j)
+ * interpolated in table k of z (order 1: as cfft_lookup, 2: as
+ * cfft_lookup_quadratic; NaN outside the table).
+ *   z     : device table as written by cfft_tabulate for these pairs
+ *   pairs : host int32 [npairs][2], 0 <= m, n < nmbf, each (m, n) at most once
+ *   pos   : device float64 [nelem][2], element reference points (x, y) [lambda0]
+ *   out   : device complex128 [nelem*nmbf][nelem*nmbf], row-major, caller-owned
+ * Self blocks (i == j) and entries of unlisted (m, n) are not written: the
+ * caller fills them (the paper computes self terms by the traditional MBF
+ * method).  Limits: 1 <= nmbf <= 16, nelem*nmbf <= 65535, order 1 or 2;
+ * violations return CFFT_ERR_INVALID_ARG before any launch. */
+cfft_status_t cfft_fill(cfft_plan_t plan, int32_t grid, const void* z, const int32_t* pairs,
+                        int32_t npairs, int32_t nmbf, const double* pos, int32_t nelem,
+                        int32_t order, void* out, void* stream);
+
 /* Adjoint of cfft_lookup: dz[p][j2][j1] += sum over points of the bilinear
  * weight times dout[p][q] (complex128, FP64 grids only).  dz must be zeroed
  * by the caller before the first accumulation. */

@@ -19,15 +19,14 @@ import torch
 
 from . import _lib
 from ._lib import (CONTOUR_RAY, FLAG_AUTOTUNE, FLAG_CHECK_FINITE, FLAG_ZERO_PAD2, FP64, MIXED,  # noqa: F401
-                   TRUNC_TENSOR, TRUNC_TOTAL, CfftError, Plan, cfft_backward, cfft_lookup, cfft_lookup_backward,
-                   cfft_lookup_quadratic, cfft_tabulate, mbf_spectra, slab_green_eval)
+                   TRUNC_TENSOR, TRUNC_TOTAL, CfftError, Plan, cfft_backward, cfft_fill, cfft_lookup,
+                   cfft_lookup_backward, cfft_lookup_quadratic, cfft_tabulate, mbf_spectra, slab_green_eval)
 
 _lib.load()
 
 __all__ = ["Tabulator", "Plan", "CfftError", "TableFunction", "LookupFunction", "FP64", "MIXED",
            "slab_green_eval", "mbf_spectra", "cfft_tabulate", "cfft_lookup", "cfft_lookup_quadratic",
-           "cfft_lookup_backward",
-           "cfft_backward", "displacement_axis"]
+           "cfft_fill", "cfft_lookup_backward", "cfft_backward", "displacement_axis"]
 
 
 def displacement_axis(n: int, k_max: float):
@@ -83,6 +82,17 @@ class Tabulator:
             cfft_lookup(self.plan, grid, z, z.shape[0], pts.contiguous(), out, stream)
         else:
             raise ValueError("order must be 1 or 2")
+        return out
+
+    def fill(self, z, pairs, nmbf: int, pos, order: int = 2, grid: int = 0, out=None, stream=None):
+        """Reduced matrix [A*M][A*M] of the element layout pos [A][2] read from
+        the table z of the listed pairs; self blocks and unlisted (m, n) keep
+        the contents of out (NaN when out is allocated here)."""
+        am = pos.shape[0] * nmbf
+        if out is None:
+            out = torch.full((am, am), complex(float("nan"), float("nan")), dtype=torch.complex128,
+                             device=self.device)
+        cfft_fill(self.plan, grid, z, pairs, nmbf, pos.contiguous(), order, out, stream)
         return out
 
     def close(self):

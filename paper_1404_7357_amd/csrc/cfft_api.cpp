@@ -845,6 +845,36 @@ cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t
   return lookup_common(plan, grid, z, npairs, pts, npts, out, stream, false);
 }
 
+cfft_status_t cfft_fill(cfft_plan_t plan, int32_t grid, const void* z, const int32_t* pairs, int32_t npairs,
+                        int32_t nmbf, const double* pos, int32_t nelem, int32_t order, void* out, void* stream) {
+  g_last_error.clear();
+  cfft_status_t st = check_plan(plan, grid);
+  if (st != CFFT_OK) return st;
+  if (!z || !pos || !out) return fail(CFFT_ERR_INVALID_ARG, "z, pos or out is NULL");
+  if (nmbf < 1 || nmbf > kFillMaxMbf) return fail(CFFT_ERR_INVALID_ARG, "nmbf %d outside [1, %d]", nmbf, kFillMaxMbf);
+  if (order != 1 && order != 2) return fail(CFFT_ERR_INVALID_ARG, "order %d is not 1 or 2", order);
+  if (nelem < 1 || (long long)nelem * nmbf > 65535)
+    return fail(CFFT_ERR_INVALID_ARG, "nelem %d invalid (nelem * nmbf must be <= 65535)", nelem);
+  st = validate_pairs(pairs, npairs, nmbf);
+  if (st != CFFT_OK) return st;
+  short slot[kFillMaxMbf * kFillMaxMbf];
+  for (short& v : slot) v = -1;
+  for (int k = 0; k < npairs; ++k) {
+    short& v = slot[pairs[2 * k] * kFillMaxMbf + pairs[2 * k + 1]];
+    if (v >= 0) return fail(CFFT_ERR_INVALID_ARG, "pair (%d, %d) listed twice", pairs[2 * k], pairs[2 * k + 1]);
+    v = (short)k;
+  }
+  if (nelem == 1) return CFFT_OK;   // only the self block, which is not written
+  GridState& gs = plan->grids[grid];
+  hipError_t e;
+  {
+    ProfScope ps(plan, 4, (hipStream_t)stream);
+    e = launch_fill(pass_params(gs), z, slot, nmbf, pos, nelem, order, (double2*)out, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "fill launch");
+  return CFFT_OK;
+}
+
 cfft_status_t cfft_lookup_backward(cfft_plan_t plan, int32_t grid, const void* dout, int32_t npairs,
                                    const double* pts, int32_t npts, void* dz, void* stream) {
   g_last_error.clear();

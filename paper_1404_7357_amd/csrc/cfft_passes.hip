@@ -977,17 +977,36 @@ struct LookupArgs {
   double x0, ddx, y0, ddy;
 };
 
-__device__ __forceinline__ bool cell_of(const LookupArgs& a, int q, int& j1, int& j2, double& tx, double& ty) {
-  const double ux = (a.pts[2 * q] - a.x0) / a.ddx;
-  const double uy = (a.pts[2 * q + 1] - a.y0) / a.ddy;
-  // rejects NaN, negative and beyond-the-last-cell points before any cast
-  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux < (double)(a.nx - 1)) || !(uy < (double)(a.ny - 1))) return false;
+// Bilinear cell of the fractional table index (ux, uy): rejects NaN,
+// negative and beyond-the-last-cell points before any cast.
+__device__ __forceinline__ bool cell_at(double ux, double uy, int nx, int ny, int& j1, int& j2, double& tx,
+                                        double& ty) {
+  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux < (double)(nx - 1)) || !(uy < (double)(ny - 1))) return false;
   j1 = (int)floor(ux);
   j2 = (int)floor(uy);
-  if (j1 > a.nx - 2 || j2 > a.ny - 2) return false;
+  if (j1 > nx - 2 || j2 > ny - 2) return false;
   tx = ux - j1;
   ty = uy - j2;
   return true;
+}
+
+__device__ __forceinline__ bool cell_of(const LookupArgs& a, int q, int& j1, int& j2, double& tx, double& ty) {
+  return cell_at((a.pts[2 * q] - a.x0) / a.ddx, (a.pts[2 * q + 1] - a.y0) / a.ddy, a.nx, a.ny, j1, j2, tx, ty);
+}
+
+__device__ __forceinline__ double2 table_at(const void* z, int precision, size_t i) {
+  return precision == 0 ? ((const double2*)z)[i] : to_d(((const float2*)z)[i]);
+}
+
+// Bilinear value of one table plane (base = first entry of the plane).
+__device__ __forceinline__ double2 bilinear_at(const void* z, int precision, size_t base, int nx, int j1, int j2,
+                                               double tx, double ty) {
+  const size_t i00 = base + (size_t)j2 * nx + j1;
+  const double2 z00 = table_at(z, precision, i00), z01 = table_at(z, precision, i00 + 1);
+  const double2 z10 = table_at(z, precision, i00 + nx), z11 = table_at(z, precision, i00 + nx + 1);
+  const double w00 = (1 - tx) * (1 - ty), w01 = tx * (1 - ty), w10 = (1 - tx) * ty, w11 = tx * ty;
+  return make_double2(w00 * z00.x + w01 * z01.x + w10 * z10.x + w11 * z11.x,
+                      w00 * z00.y + w01 * z01.y + w10 * z10.y + w11 * z11.y);
 }
 
 __global__ void lookup_kernel(LookupArgs a) {
@@ -1000,37 +1019,18 @@ __global__ void lookup_kernel(LookupArgs a) {
     a.out[e] = make_double2(__builtin_nan(""), __builtin_nan(""));
     return;
   }
-  const size_t base = (size_t)p * a.nx * a.ny;
-  const size_t i00 = base + (size_t)j2 * a.nx + j1;
-  double2 z00, z01, z10, z11;
-  if (a.precision == 0) {
-    const double2* z = (const double2*)a.z;
-    z00 = z[i00];
-    z01 = z[i00 + 1];
-    z10 = z[i00 + a.nx];
-    z11 = z[i00 + a.nx + 1];
-  } else {
-    const float2* z = (const float2*)a.z;
-    z00 = to_d(z[i00]);
-    z01 = to_d(z[i00 + 1]);
-    z10 = to_d(z[i00 + a.nx]);
-    z11 = to_d(z[i00 + a.nx + 1]);
-  }
-  const double w00 = (1 - tx) * (1 - ty), w01 = tx * (1 - ty), w10 = (1 - tx) * ty, w11 = tx * ty;
-  a.out[e] = make_double2(w00 * z00.x + w01 * z01.x + w10 * z10.x + w11 * z11.x,
-                          w00 * z00.y + w01 * z01.y + w10 * z10.y + w11 * z11.y);
+  a.out[e] = bilinear_at(a.z, a.precision, (size_t)p * a.nx * a.ny, a.nx, j1, j2, tx, ty);
 }
 
 // Second-order interpolation (Sec. III-B.3, last paragraph): per axis the
 // nodes c - 1, c, c + 1 around the nearest node c = round(u), kept in
 // [1, n-2], with the quadratic Lagrange weights in t = u - c.  Points need
 // 0 <= u <= n - 1 on both axes; others (and NaN) yield NaN.
-__device__ __forceinline__ bool stencil_of(const LookupArgs& a, int q, int& c1, int& c2, double& tx, double& ty) {
-  const double ux = (a.pts[2 * q] - a.x0) / a.ddx;
-  const double uy = (a.pts[2 * q + 1] - a.y0) / a.ddy;
-  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux <= (double)(a.nx - 1)) || !(uy <= (double)(a.ny - 1))) return false;
-  c1 = min(max((int)floor(ux + 0.5), 1), a.nx - 2);
-  c2 = min(max((int)floor(uy + 0.5), 1), a.ny - 2);
+__device__ __forceinline__ bool stencil_at(double ux, double uy, int nx, int ny, int& c1, int& c2, double& tx,
+                                           double& ty) {
+  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux <= (double)(nx - 1)) || !(uy <= (double)(ny - 1))) return false;
+  c1 = min(max((int)floor(ux + 0.5), 1), nx - 2);
+  c2 = min(max((int)floor(uy + 0.5), 1), ny - 2);
   tx = ux - c1;
   ty = uy - c2;
   return true;
@@ -1042,33 +1042,37 @@ __device__ __forceinline__ void lagrange3(double t, double (&w)[3]) {
   w[2] = 0.5 * t * (t + 1.0);
 }
 
+__device__ __forceinline__ double2 quadratic_at(const void* z, int precision, size_t base, int nx, int c1, int c2,
+                                                double tx, double ty) {
+  double wx[3], wy[3];
+  lagrange3(tx, wx);
+  lagrange3(ty, wy);
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const size_t row = base + (size_t)(c2 + b - 1) * nx + (c1 - 1);
+    double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double2 v = table_at(z, precision, row + i);
+      s = make_double2(s.x + wx[i] * v.x, s.y + wx[i] * v.y);
+    }
+    acc = make_double2(acc.x + wy[b] * s.x, acc.y + wy[b] * s.y);
+  }
+  return acc;
+}
+
 __global__ void lookup_quadratic_kernel(LookupArgs a) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.npairs * a.npts) return;
   const int p = e / a.npts, q = e % a.npts;
   int c1, c2;
   double tx, ty;
-  if (!stencil_of(a, q, c1, c2, tx, ty)) {
+  if (!stencil_at((a.pts[2 * q] - a.x0) / a.ddx, (a.pts[2 * q + 1] - a.y0) / a.ddy, a.nx, a.ny, c1, c2, tx, ty)) {
     a.out[e] = make_double2(__builtin_nan(""), __builtin_nan(""));
     return;
   }
-  double wx[3], wy[3];
-  lagrange3(tx, wx);
-  lagrange3(ty, wy);
-  const size_t base = (size_t)p * a.nx * a.ny;
-  double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const size_t row = base + (size_t)(c2 + b - 1) * a.nx + (c1 - 1);
-    double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double2 z = a.precision == 0 ? ((const double2*)a.z)[row + i] : to_d(((const float2*)a.z)[row + i]);
-      s = make_double2(s.x + wx[i] * z.x, s.y + wx[i] * z.y);
-    }
-    acc = make_double2(acc.x + wy[b] * s.x, acc.y + wy[b] * s.y);
-  }
-  a.out[e] = acc;
+  a.out[e] = quadratic_at(a.z, a.precision, (size_t)p * a.nx * a.ny, a.nx, c1, c2, tx, ty);
 }
 
 __global__ void lookup_backward_kernel(LookupArgs a, const double2* __restrict__ dout, double2* dz) {
@@ -1088,6 +1092,71 @@ __global__ void lookup_backward_kernel(LookupArgs a, const double2* __restrict__
     atomicAdd(d + 2 * id[k], w[k] * g.x);
     atomicAdd(d + 2 * id[k] + 1, w[k] * g.y);
   }
+}
+
+// Reduced-matrix fill (Sec. II eq. MBF; Sec. III-B.1 and III-B.3): one
+// block per matrix row r = i*M + m and 256 consecutive columns c = j*M + n,
+// so the row segment is written with coalesced stores; each thread reads
+// the table of pair (m, n) around D = r_i - r_j.  Self blocks (i == j) and
+// unlisted (m, n) are not written.
+struct FillArgs {
+  const void* z;
+  const double* pos;
+  double2* out;
+  int nx, ny, precision, nelem, nmbf, ncb;
+  double x0, ddx, y0, ddy;
+  short slot[kFillMaxMbf * kFillMaxMbf];   // pair index of (m, n), -1 when not listed
+};
+
+template <int ORDER>
+__global__ __launch_bounds__(256) void fill_kernel(FillArgs a) {
+  const int am = a.nelem * a.nmbf;
+  const int r = blockIdx.x / a.ncb;
+  const int c = (blockIdx.x - r * a.ncb) * 256 + threadIdx.x;
+  if (c >= am) return;
+  const int i = r / a.nmbf, m = r - i * a.nmbf;
+  const int j = c / a.nmbf, n = c - j * a.nmbf;
+  if (i == j) return;
+  const int p = a.slot[m * kFillMaxMbf + n];
+  if (p < 0) return;
+  const double ux = (a.pos[2 * i] - a.pos[2 * j] - a.x0) / a.ddx;
+  const double uy = (a.pos[2 * i + 1] - a.pos[2 * j + 1] - a.y0) / a.ddy;
+  const size_t base = (size_t)p * a.nx * a.ny;
+  double2 v = make_double2(__builtin_nan(""), __builtin_nan(""));
+  int c1, c2;
+  double tx, ty;
+  if (ORDER == 1) {
+    if (cell_at(ux, uy, a.nx, a.ny, c1, c2, tx, ty)) v = bilinear_at(a.z, a.precision, base, a.nx, c1, c2, tx, ty);
+  } else {
+    if (stencil_at(ux, uy, a.nx, a.ny, c1, c2, tx, ty)) v = quadratic_at(a.z, a.precision, base, a.nx, c1, c2, tx, ty);
+  }
+  a.out[(size_t)r * am + c] = v;
+}
+
+hipError_t launch_fill(const PassParams& p, const void* z, const short* slot, int nmbf, const double* pos, int nelem,
+                       int order, double2* out, hipStream_t s) {
+  FillArgs a;
+  a.z = z;
+  a.pos = pos;
+  a.out = out;
+  a.nx = p.x.n;
+  a.ny = p.y.n;
+  a.precision = p.precision;
+  a.nelem = nelem;
+  a.nmbf = nmbf;
+  const int am = nelem * nmbf;
+  a.ncb = (am + 255) / 256;
+  a.x0 = p.x.d_first;
+  a.ddx = p.x.dd;
+  a.y0 = p.y.d_first;
+  a.ddy = p.y.dd;
+  for (int k = 0; k < kFillMaxMbf * kFillMaxMbf; ++k) a.slot[k] = slot[k];
+  const dim3 grid((unsigned)((long long)am * a.ncb));
+  if (order == 1)
+    hipLaunchKernelGGL(fill_kernel<1>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(fill_kernel<2>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 static LookupArgs lookup_args(const PassParams& p, const void* z, int npairs, const double* pts, int npts,

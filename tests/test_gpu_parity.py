@@ -348,6 +348,58 @@ def test_lookup_quadratic_matches_oracle():
         assert np.isnan(out[:, -3:]).all()
 
 
+def test_fill_matches_oracle_on_given_tables():
+    """Reduced-matrix fill (cfft_fill) vs the oracle's on host-made tables:
+    FP64 and complex64 tables, orders 1 and 2, displacements outside the
+    table (NaN); self blocks and unlisted (m, n) keep the caller's values.
+    Bad arguments are rejected before any launch."""
+    _say("fill")
+    from paper_1404_7357_amd import CfftError, Tabulator, _lib as L
+    rng = np.random.default_rng(71)
+    pairs = [(0, 0), (0, 2), (1, 1), (2, 0), (2, 1)]
+    nmbf, nel = 3, 37
+    self_blk = np.kron(np.eye(nel, dtype=bool), np.ones((nmbf, nmbf), dtype=bool))
+    listed = np.zeros((nmbf, nmbf), dtype=bool)
+    for m, n in pairs:
+        listed[m, n] = True
+    written = ~self_blk & np.tile(listed, (nel, nel))
+    sentinel = complex(3.0, 4.0)
+    for prec in (FP64, MIXED):
+        grid = Grid(64, 32, 8 * K0, 6 * K0, K0, precision=prec)
+        tab = Tabulator(grid, rooftop_lattice(1, 1), nmbf)
+        dt = torch.complex128 if prec == FP64 else torch.complex64
+        table = rng.standard_normal((len(pairs), 32, 64)) + 1j * rng.standard_normal((len(pairs), 32, 64))
+        zt = torch.tensor(table, dtype=dt, device="cuda")
+        zh = zt.cpu().numpy().astype(np.complex128)
+        pos = rng.uniform([-1.1, -0.75], [1.1, 0.75], (nel, 2))     # some displacements leave the table
+        pd = torch.tensor(pos, device="cuda")
+        for order in (1, 2):
+            out = torch.full((nel * nmbf, nel * nmbf), sentinel, dtype=torch.complex128, device="cuda")
+            tab.fill(zt, pairs, nmbf, pd, order=order, out=out)
+            got = out.cpu().numpy()
+            ref = co.fill_reduced(grid, zh, pairs, nmbf, pos, order=order)
+            assert np.all(got[~written] == sentinel)
+            outside = np.isnan(ref) & written
+            assert 0 < outside.sum() < written.sum() // 2
+            assert np.all(np.isnan(got[outside]))
+            inside = written & ~outside
+            assert np.abs(got[inside] - ref[inside]).max() < 1e-13
+        out = torch.empty((nel * nmbf, nel * nmbf), dtype=torch.complex128, device="cuda")
+        for kw in (dict(order=3), dict(nmbf=17), dict(pairs=[(0, 0), (0, 0)]), dict(pairs=[(0, 3)])):
+            args = dict(pairs=pairs, nmbf=nmbf, order=2)
+            args.update(kw)
+            with pytest.raises(CfftError):
+                L.cfft_fill(tab.plan, 0, zt, args["pairs"], args["nmbf"], pd, args["order"], out)
+        big = torch.zeros((22000, 2), dtype=torch.float64, device="cuda")
+        with pytest.raises(CfftError):
+            L.cfft_fill(tab.plan, 0, zt, pairs, nmbf, big, 2, out)
+        with pytest.raises(CfftError):
+            L.cfft_fill(tab.plan, 0, zt, pairs, nmbf, pd, 2, 0)
+        one = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        tab.fill(zt, pairs, nmbf, one, out=out[:nmbf, :nmbf].contiguous())     # only a self block: no-op
+        tab.close()
+
+
 def test_zero_padded_refinement_and_quadratic_lookup():
     """x2 zero-padded grid (Whittaker-Shannon refinement): the refined table
     vs the oracle's, its even nodes vs the unrefined GPU table, and the
@@ -373,6 +425,9 @@ def test_zero_padded_refinement_and_quadratic_lookup():
         dya = co.displacement_axis(pad.ny, pad.ky_max)
         pts = np.stack([rng.uniform(dxa[0], dxa[-1], 200), rng.uniform(dya[0], dya[-1], 200)], 1)
         vals = tab.lookup(z, torch.tensor(pts, device="cuda"), order=2).cpu().numpy()
+        lay = np.stack(np.meshgrid(np.arange(5), np.arange(4)), -1).reshape(-1, 2) * 0.37
+        lay = lay - lay.mean(0) + rng.uniform(-0.05, 0.05, lay.shape)              # jittered 5 x 4 array
+        fz = tab.fill(z, pairs, 2, torch.tensor(lay, device="cuda")).cpu().numpy()
         zz = z.cpu().numpy()
         if prec == FP64:
             with pytest.raises(CfftError):
@@ -383,6 +438,10 @@ def test_zero_padded_refinement_and_quadratic_lookup():
         assert _err(zz, ref) < tol
         assert _err(zz[:, ::2, ::2], zb) < tol
         assert _err(vals, co.quadratic_lookup(pad, ref, pts)) < tol
+        fref = co.fill_reduced(pad, ref, pairs, 2, lay)
+        assert np.array_equal(np.isnan(fz), np.isnan(fref)) and np.isnan(fz).sum() == 20 * 4 + 20 * 19 * 2
+        ok = ~np.isnan(fref)
+        assert np.abs(fz[ok] - fref[ok]).max() < tol * np.abs(ref).max()
 
 
 def test_nonfinite_flag_reports_nan_input():
