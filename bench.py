@@ -64,13 +64,14 @@ class Step:
     """Resident inputs and one Tabulator for a workload grid."""
 
     def __init__(self, wl, torch):
-        from paper_1404_7357_amd import FLAG_AUTOTUNE, Tabulator, _lib
+        from paper_1404_7357_amd import FLAG_AUTOTUNE, FLAG_ZERO_PAD2, Tabulator, _lib
         self.torch = torch
         self.wl = wl
         self.grid = wl.grids[0]
         self.sub = wl.substrates[0]
         # the pair-chunk schedule is autotuned on the first (warm-up) call
-        self.tab = Tabulator(self.grid, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE)
+        flags = FLAG_AUTOTUNE | (FLAG_ZERO_PAD2 if self.grid.zero_pad else 0)
+        self.tab = Tabulator(self.grid, wl.basis, max_mbf=wl.M, flags=flags)
         self.q = torch.tensor(wl.q, device="cuda")
         self.pairs = [tuple(int(v) for v in p) for p in wl.pairs]
         gd = self.grid
@@ -345,6 +346,33 @@ def _large_leg(torch, steps, warmup):
             "dtype": "fp32 FFT / fp64 rest", "kernels_ms": km}
 
 
+def _paper_leg(torch, steps, warmup):
+    """The paper's own table setup (Sec. IV-F): a 2048^2 FFT including the x2
+    zero padding, M = 9 MBFs (81 pairs), FP64; then the fill of the reduced
+    matrix of the 25 x 25 regular array at 0.58 lambda0 (Sec. IV-E) by
+    second-order interpolation in the refined table (390 000 element pairs
+    x 81 MBF pairs)."""
+    from workloads import paper_array_2048
+    wl = paper_array_2048()
+    st = Step(wl, torch)
+    pos = torch.tensor(wl.layout, device="cuda")
+    am = pos.shape[0] * wl.M
+    mat = torch.zeros((am, am), dtype=torch.complex128, device="cuda")   # self blocks stay zero here
+    sec = _time_steps(torch, st.run, steps, warmup)
+    sec_tab = _time_steps(torch, lambda: st.tab.tabulate(st.spec, st.g, st.pairs, out=st.z), steps, 1)
+    sec_fill = _time_steps(torch, lambda: st.tab.fill(st.z, st.pairs, wl.M, pos, out=mat), steps, 1)
+    km = _kernel_times(st, steps)
+    finite = bool(torch.isfinite(mat).all().item())
+    st.tab.close()
+    a_count = pos.shape[0]
+    return {"workload": wl.name, "entries": st.entries(), "value": st.entries() / sec, "ms_per_step": sec * 1e3,
+            "passes_only": {"ms": sec_tab * 1e3, "value": st.entries() / sec_tab, "unit": "entries/s"},
+            "fill_ms": sec_fill * 1e3, "fill_element_pairs": a_count * (a_count - 1),
+            "fill_interpolations": a_count * (a_count - 1) * len(wl.pairs), "fill_all_finite": finite,
+            "paper_cpu": {"fft_s_81_pairs": 126.36, "interp_s_390000": 1.62, "hardware": "one i7-3770"},
+            "dtype": "f64", "kernels_ms": km}
+
+
 def _sweep(torch, steps, warmup):
     """Frequency sweep, 8 uneven grids x 16 pairs (mixed), eager and as one replayed HIP graph."""
     from paper_1404_7357_amd import Tabulator
@@ -509,6 +537,8 @@ def main():
         out["parabolic"] = _parabolic_leg(torch, max(3, args.steps // 5), 2, max(n_out, 4))
         _log("large leg (4096^2, 36 pairs, 10^5 lookups)")
         out["large"] = _large_leg(torch, 3, 1)
+        _log("paper-setup leg (2048^2 incl. zero padding, 81 pairs, 25 x 25 array fill)")
+        out["paper_setup"] = _paper_leg(torch, 3, 1)
         _log("sweep leg (8 grids, one graph)")
         out["sweep"] = _sweep(torch, max(3, args.steps // 5), 2)
         _log("adjoint leg (1024^2, 16 pairs, 4096 lookups)")

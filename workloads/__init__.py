@@ -125,6 +125,7 @@ class Workload:
     queries: Optional[np.ndarray] = None  # float64 [Q][2]
     target_eps_r: Optional[float] = None
     target_q: Optional[np.ndarray] = None
+    layout: Optional[np.ndarray] = None   # float64 [A][2] element positions of an array
 
     @property
     def M(self) -> int:
@@ -217,6 +218,29 @@ def c5_gradient(n: int = 1024, nq: int = 4096) -> Workload:
     return Workload(f"c5_gradient_{n}", "loss over 4096 lookups, gradient wrt eps_r, h, q",
                     [g], [Substrate(2.2, 0.0, 0.05)], basis, q, all_pairs(4), queries,
                     target_eps_r=2.3, target_q=target_q)
+
+
+def regular_layout(nx: int, ny: int, spacing: float) -> np.ndarray:
+    """Element positions of an nx x ny regular array centred on the origin."""
+    ix, iy = np.meshgrid(np.arange(nx) - 0.5 * (nx - 1), np.arange(ny) - 0.5 * (ny - 1))
+    return (spacing * np.stack([ix.ravel(), iy.ravel()], 1)).astype(np.float64)
+
+
+def paper_array_2048(n: int = 2048, elements: int = 25) -> Workload:
+    """The paper's table setup with synthetic MBFs: a 2048^2 FFT including the
+    x2 zero padding (1024^2 samples over +-5 k_d, eps_r 2.2, h 0.381 mm at
+    24.125 GHz = 0.0307 lambda0), M = 9 MBFs (81 pairs) of B = 256 rooftops,
+    FP64; the layout is the 25 x 25 regular array at 0.58 lambda0."""
+    rng = np.random.default_rng(BASE_SEED + 5)
+    k0 = k0_of(1.0)
+    eps = 2.2
+    km = 5.0 * math.sqrt(eps) * k0                # spectral half-span of the original samples
+    basis = rooftop_lattice(8, 16)
+    q = gaussian_coefficients(rng, 9, basis.shape[0])
+    g = Grid(n, n, 2.0 * km, 2.0 * km, k0, precision=FP64, zero_pad=1)
+    return Workload(f"paper_array_m9_{n}_zero_padded", "81 pairs on a x2 zero-padded grid, 25 x 25 array fill",
+                    [g], [Substrate(eps, 0.0, 0.381 / (299.792458 / 24.125))], basis, q, all_pairs(9),
+                    layout=regular_layout(elements, elements, 0.58))
 
 
 def random_smooth_field(rng: np.random.Generator, shape, scale: float = 1.0) -> np.ndarray:
