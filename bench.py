@@ -421,6 +421,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and adjoint legs")
     ap.add_argument("--copy-calibration", action="store_true", help="run one 256 MiB device copy (counter scale)")
+    ap.add_argument("--only", choices=("large", "paper_setup"),
+                    help="run one extra leg alone and print its JSON (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -440,6 +442,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    if args.only:
+        leg = {"large": _large_leg, "paper_setup": _paper_leg}[args.only]
+        print(json.dumps({"leg": args.only, **leg(torch, args.steps, args.warmup)}), flush=True)
+        return
 
     wl = c2_rooftop_512()
     _log(f"workload {wl.name}: warmup {args.warmup}, steps {args.steps}")
