@@ -400,6 +400,37 @@ def test_fill_matches_oracle_on_given_tables():
         tab.close()
 
 
+@pytest.mark.parametrize("nx,ny,variant", [(64, 32, "ray"), (32, 128, "parabolic"), (256, 64, "tensor"),
+                                            (2048, 16, "ray"), (16, 2048, "ray")])
+def test_zero_padded_kernels_and_variants(nx, ny, variant):
+    """Zero-padded grids through both row kernels (one row per block of
+    several, short and long rows), the column pass skipping the zero rows,
+    on the ray and parabolic contours and with the tensor truncation, FP64
+    and mixed; the long-axis cases at sampled outputs."""
+    from paper_1404_7357_amd import FLAG_ZERO_PAD2
+    rng = np.random.default_rng(83 + nx + ny)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 1), (1, 1), (1, 0)]
+    sub = Substrate(3.0, 0.001, 0.07)
+    idx = _sample_idx(nx, ny, 60, nx * 7 + ny) if max(nx, ny) >= 2048 else None
+    for prec, tol in [(FP64, 1e-10), (MIXED, 1e-5)]:
+        grid = Grid(nx, ny, 16 * K0, 12 * K0, K0, precision=prec, zero_pad=1)
+        if variant == "parabolic":
+            grid = _para(dataclasses.replace(grid, gamma=1 / 50), 4.5 * K0)
+        elif variant == "tensor":
+            grid = dataclasses.replace(grid, truncation=TRUNC_TENSOR)
+        _say(f"zero-padded {variant} {nx}x{ny} prec={prec}")
+        tab = _tab(grid, basis, 2, FLAG_ZERO_PAD2)
+        qd = torch.tensor(q, device="cuda")
+        z = tab.tabulate(tab.spectra(qd), tab.green(sub.eps_r, sub.tan_delta, sub.h), pairs).cpu().numpy()
+        tab.close()
+        ref = co.tabulate(grid, sub, basis, q, np.asarray(pairs), out_idx=idx, workers=8)
+        got = z.reshape(len(pairs), -1) if idx is None else z.reshape(len(pairs), -1)[:, idx]
+        err = (np.abs(got - ref.reshape(len(pairs), -1)).max(axis=1) / np.abs(ref).reshape(len(pairs), -1).max(axis=1)).max()
+        assert err < tol, (variant, nx, ny, prec, err)
+
+
 def test_zero_padded_refinement_and_quadratic_lookup():
     """x2 zero-padded grid (Whittaker-Shannon refinement): the refined table
     vs the oracle's, its even nodes vs the unrefined GPU table, and the
