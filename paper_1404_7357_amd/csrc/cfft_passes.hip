@@ -29,7 +29,9 @@
 #include "cfft_internal.h"
 
 // Scheduling knobs (compile-time): minimum waves per SIMD requested from the
-// register allocator for the two passes (0 = compiler's choice), whether the
+// register allocator for the two passes (0 = compiler's choice; the FP32
+// column pass asks for 4, i.e. two 512-thread blocks per CU instead of one,
+// at the price of a small spill: -17% at 512^2), whether the
 // column pass fetches the next term's column while transforming the current
 // one (costs one register array), whether it writes the table with
 // non-temporal stores (the table is not read again by this path, and keeping
@@ -40,7 +42,7 @@
 // 4096^2 FP32), whether
 // it reads the intermediates with non-temporal loads (they then bypass the
 // memory-side cache that still holds them from the row pass: slower), and
-// the widest column tile in bytes per row.
+// the widest column tile in bytes per row (FP64 and FP32 tiles).
 #ifndef CFFT_ROW_MIN_WAVES
 #define CFFT_ROW_MIN_WAVES 0
 #endif
@@ -64,6 +66,12 @@
 #endif
 #ifndef CFFT_COL_MIN_WAVES
 #define CFFT_COL_MIN_WAVES 0
+#endif
+#ifndef CFFT_COL_MIN_WAVES_F32
+#define CFFT_COL_MIN_WAVES_F32 4
+#endif
+#ifndef CFFT_COL_ROW_BYTES_F32
+#define CFFT_COL_ROW_BYTES_F32 64
 #endif
 #ifndef CFFT_COL_ROW_BYTES
 #define CFFT_COL_ROW_BYTES 64
@@ -391,6 +399,12 @@ struct ColArgs {
   double rinv[kMaxOrder + 1];
 };
 
+// Minimum waves per SIMD requested for the column pass (1: no constraint).
+template <typename V> constexpr int col_min_waves() {
+  return sizeof(V) == 8 ? (CFFT_COL_MIN_WAVES_F32 > 0 ? CFFT_COL_MIN_WAVES_F32 : 1)
+                        : (CFFT_COL_MIN_WAVES > 0 ? CFFT_COL_MIN_WAVES : 1);
+}
+
 // Column-pass block shape.  Thread tid works on column c = tid % C of the
 // tile at transform position t = tid / C, holding R points at stride
 // T = N/R.  A wave therefore covers 64/C consecutive rows of all C columns, so
@@ -404,11 +418,7 @@ template <int N, int C, int R> struct ColCfg {
 };
 
 template <typename V, int N, int C, int R>
-#if CFFT_COL_MIN_WAVES > 0
-__global__ void __launch_bounds__(C * (N / R), CFFT_COL_MIN_WAVES) col_pass_kernel(ColArgs a) {
-#else
-__global__ void __launch_bounds__(C * (N / R)) col_pass_kernel(ColArgs a) {
-#endif
+__global__ void __launch_bounds__(C * (N / R), col_min_waves<V>()) col_pass_kernel(ColArgs a) {
   using Cfg = ColCfg<N, C, R>;
   constexpr int T = Cfg::T, LDP = Cfg::LDP;
   using Rl = typename real_of<V>::type;
@@ -503,7 +513,7 @@ __host__ __device__ constexpr int col_r(int) { return 8; }
 // 2048 and 4096, whose tiles are otherwise one or two columns wide, take
 // 1024 threads when CFFT_COL_WIDE_FP32 is set).
 __host__ __device__ constexpr int col_tile_c(int ny, int bytes) {
-  int c = CFFT_COL_ROW_BYTES / bytes;
+  int c = (bytes == 8 ? CFFT_COL_ROW_BYTES_F32 : CFFT_COL_ROW_BYTES) / bytes;
   const int r = col_r(bytes);
   const int max_threads = (CFFT_COL_WIDE_FP32 && bytes == 8 && ny >= 2048) ? 1024 : 512;
   while (c > 1 && (c * (lds_len(ny) + CFFT_COL_LDP_EXTRA) * bytes > 81920 || c * (ny / r) > max_threads)) c /= 2;

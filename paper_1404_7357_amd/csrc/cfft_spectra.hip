@@ -130,59 +130,55 @@ constexpr int kSpecRows = CFFT_SPEC_ROWS;         // rows per spectra block
 constexpr int kMaxGroups = 32;  // host refuses basis sets needing more
 constexpr int kMChunk = 4;
 
-// Per-row contraction over y-centres.  One block per row n2; the row's V, V#
-// and SY values are staged in LDS, then each thread owns entries (v, m, pp)
-// of the row's table
+// Per-row contraction over y-centres, one thread per table entry
 //   v = 0:  w [n2][m][pp] = SY_g(n2) sum_r conj(q_m,j(g,p,r)) V_gr(n2)
 //   v = 1:  w#[n2][m][pp] = SY_g(n2) sum_r      q_m,j(g,p,r)  V#_gr(n2)
 // stored as wtab[n2][v][mpad][ppad] with pp = poff_g + p.  Slots past a
 // group's centre count and MBFs past nmbf hold zero, so the per-sample
-// kernel runs whole chunks without bounds tests.  Coefficients are fetched
-// through the slot index, eight independent loads at a time.
+// kernel runs whole chunks without bounds tests.  The row index n2 runs
+// fastest over the threads: the V tables (rows of length ny) are read with
+// coalesced loads, while the basis index and the coefficient of an entry are
+// the same for a whole wave (when 64 divides ny) and come through scalar
+// loads.
 constexpr int kRowsThreads = 256;
 __global__ void __launch_bounds__(kRowsThreads)
 spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
                     const double2* __restrict__ q, int nmbf, int mpad, double2* __restrict__ wtab) {
-  extern __shared__ double2 vs[];   // [2 total_r] V, V# interleaved by row, then [ngroups] SY
-  const int n2 = blockIdx.x;
-  const double2* vtab = utab + vtab_offset(x.n, geo);
-  const int nv = 2 * geo.total_r + geo.ngroups;
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) vs[i] = vtab[(size_t)i * y.n + n2];
-  __syncthreads();
   const int ppad = geo.ppad;
   const int per_v = mpad * ppad;
-  double2* dst = wtab + (size_t)n2 * 2 * per_v;
-  for (int e = threadIdx.x; e < 2 * per_v; e += blockDim.x) {
-    const int v = e / per_v;
-    const int m = (e % per_v) / ppad;
-    const int pp = e % ppad;
-    int g = 0;
-    while (g + 1 < geo.ngroups && geo.groups[g + 1].poff <= pp) ++g;
-    const GeomGroup gr = geo.groups[g];
-    const int p = pp - gr.poff;
-    double2 acc = make_double2(0.0, 0.0);
-    if (m < nmbf && p < gr.np) {
-      const int* irow = geo.index + gr.ioff + (size_t)p * gr.nr;
-      const double2* qm = q + (size_t)m * geo.nbasis;
-      for (int r0 = 0; r0 < gr.nr; r0 += 8) {
-        int jj[8];
+  const long long e = (long long)blockIdx.x * kRowsThreads + threadIdx.x;
+  if (e >= (long long)2 * per_v * y.n) return;
+  const int n2 = (int)(e % y.n);
+  const int ent = (int)(e / y.n);
+  const int v = ent / per_v;
+  const int m = (ent % per_v) / ppad;
+  const int pp = ent % ppad;
+  int g = 0;
+  while (g + 1 < geo.ngroups && geo.groups[g + 1].poff <= pp) ++g;
+  const GeomGroup gr = geo.groups[g];
+  const int p = pp - gr.poff;
+  double2 acc = make_double2(0.0, 0.0);
+  if (m < nmbf && p < gr.np) {
+    const double2* vtab = utab + vtab_offset(x.n, geo);
+    const int* irow = geo.index + gr.ioff + (size_t)p * gr.nr;
+    const double2* qm = q + (size_t)m * geo.nbasis;
+    // eight independent index, coefficient and V loads in flight at a time
+    for (int r0 = 0; r0 < gr.nr; r0 += 8) {
+      int jj[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) jj[k] = r0 + k < gr.nr ? irow[r0 + k] : -1;
-        double2 qq[8];
+      for (int k = 0; k < 8; ++k) jj[k] = r0 + k < gr.nr ? irow[r0 + k] : -1;
+      double2 qq[8], vv[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) qq[k] = jj[k] >= 0 ? qm[jj[k]] : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          if (r0 + k < gr.nr) {
-            const double2 vv = vs[2 * (gr.yoff + r0 + k) + v];
-            acc = cadd(acc, v == 0 ? cmulc(vv, qq[k]) : cmul(qq[k], vv));   // conj(q) V  or  q V#
-          }
-        }
+      for (int k = 0; k < 8; ++k) {
+        qq[k] = jj[k] >= 0 ? qm[jj[k]] : make_double2(0.0, 0.0);
+        vv[k] = jj[k] >= 0 ? vtab[(size_t)(2 * (gr.yoff + r0 + k) + v) * y.n + n2] : make_double2(0.0, 0.0);
       }
-      acc = cmul(acc, vs[2 * geo.total_r + g]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc = cadd(acc, v == 0 ? cmulc(vv[k], qq[k]) : cmul(qq[k], vv[k]));   // conj(q) V or q V#
     }
-    dst[e] = acc;
+    acc = cmul(acc, vtab[(size_t)(2 * geo.total_r + g) * y.n + n2]);
   }
+  wtab[((size_t)n2 * 2 + v) * per_v + (size_t)m * ppad + pp] = acc;
 }
 
 // Per-sample sums of one block: thread = sample n1 (byte offset boff in a
@@ -276,8 +272,9 @@ hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const Geom
   (void)gamma;
   const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
   dim3 grid((x.n + kSpecThreads - 1) / kSpecThreads, (y.n + kSpecRows - 1) / kSpecRows, 2);
-  hipLaunchKernelGGL(spectra_rows_kernel, dim3(y.n), dim3(kRowsThreads), spectra_lds_bytes(geo, nmbf), s, x, y, geo,
-                     utab, q, nmbf, mpad, scratch);
+  const long long rows_entries = (long long)2 * mpad * geo.ppad * y.n;
+  hipLaunchKernelGGL(spectra_rows_kernel, dim3((unsigned)((rows_entries + kRowsThreads - 1) / kRowsThreads)),
+                     dim3(kRowsThreads), 0, s, x, y, geo, utab, q, nmbf, mpad, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(spectra_kernel, grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf, mpad, spec);
