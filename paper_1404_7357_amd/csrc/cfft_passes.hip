@@ -31,7 +31,9 @@
 // Scheduling knobs (compile-time): minimum waves per SIMD requested from the
 // register allocator for the two passes (0 = compiler's choice; the FP32
 // column pass asks for 4, i.e. two 512-thread blocks per CU instead of one,
-// at the price of a small spill: -17% at 512^2), whether the
+// at the price of a small spill: -17% at 512^2; so do the FP32 rows of 1024
+// points and more: -9% on the frequency sweep, -12% at 4096^2, while shorter
+// rows lose from the spill), whether the
 // column pass fetches the next term's column while transforming the current
 // one (costs one register array), whether it writes the table with
 // non-temporal stores (the table is not read again by this path, and keeping
@@ -45,6 +47,9 @@
 // the widest column tile in bytes per row (FP64 and FP32 tiles).
 #ifndef CFFT_ROW_MIN_WAVES
 #define CFFT_ROW_MIN_WAVES 0
+#endif
+#ifndef CFFT_ROW_MIN_WAVES_F32
+#define CFFT_ROW_MIN_WAVES_F32 4
 #endif
 #ifndef CFFT_COL_PREFETCH
 #define CFFT_COL_PREFETCH 0
@@ -83,6 +88,13 @@ namespace cfft {
 // (16-byte elements: every 16; 8-byte elements: every 8).
 template <typename V> __host__ __device__ constexpr int row_pad() {
   return CFFT_ROW_PAD_SHIFT > 0 ? CFFT_ROW_PAD_SHIFT : (sizeof(V) == 16 ? 4 : 3);
+}
+
+// Minimum waves per SIMD requested for the row pass (1: no constraint); the
+// FP32 rows of 1024 points and more take CFFT_ROW_MIN_WAVES_F32.
+template <typename V, int N> constexpr int row_min_waves() {
+  return (sizeof(V) == 8 && N >= 1024) ? (CFFT_ROW_MIN_WAVES_F32 > 0 ? CFFT_ROW_MIN_WAVES_F32 : 1)
+                                       : (CFFT_ROW_MIN_WAVES > 0 ? CFFT_ROW_MIN_WAVES : 1);
 }
 
 template <int N> struct RowCfg {
@@ -171,11 +183,7 @@ __device__ __forceinline__ void row_terms_general(const Args& a, const V (&f)[R]
 }
 
 template <typename V, int N>
-#if CFFT_ROW_MIN_WAVES > 0
-__global__ void __launch_bounds__(RowCfg<N>::THREADS, CFFT_ROW_MIN_WAVES) row_pass_kernel(RowArgs a) {
-#else
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) row_pass_kernel(RowArgs a) {
-#endif
+__global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) row_pass_kernel(RowArgs a) {
   using Cfg = RowCfg<N>;
   constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
   using Rl = typename real_of<V>::type;
@@ -287,11 +295,7 @@ template <int N, int NPW> struct RowGCfg {
 };
 
 template <typename V, int N, int NPW>
-#if CFFT_ROW_MIN_WAVES > 0
-__global__ void __launch_bounds__(NPW * (N / 8), CFFT_ROW_MIN_WAVES) row_pass_grouped_kernel(RowGArgs a) {
-#else
-__global__ void __launch_bounds__(NPW * (N / 8)) row_pass_grouped_kernel(RowGArgs a) {
-#endif
+__global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pass_grouped_kernel(RowGArgs a) {
   using Cfg = RowGCfg<N, NPW>;
   constexpr int T = Cfg::T, R = Cfg::R;
   using Rl = typename real_of<V>::type;
