@@ -94,8 +94,11 @@ enum { CFFT_ROOFTOP_X = 0, CFFT_ROOFTOP_Y = 1, CFFT_COSINE_X = 2, CFFT_COSINE_Y 
  *   refinement with zero padding to twice the FFT size).  Only the central
  *   half of the samples on each axis, n in [N/4, 3N/4), carries the
  *   integrand; the table then has half the displacement step over the same
- *   span, and its even nodes are the unrefined table.  The adjoint refuses
- *   such a plan. */
+ *   span, and its even nodes are the unrefined table.  The grid descriptor
+ *   describes the padded grid (2N samples over twice the spectral span).
+ *   slab_green_eval and mbf_spectra still write every sample; the passes
+ *   read only the band and skip the rows that are zero.  The adjoint
+ *   refuses such a plan. */
 enum { CFFT_FLAG_CHECK_FINITE = 1, CFFT_FLAG_AUTOTUNE = 2, CFFT_FLAG_ZERO_PAD2 = 4 };
 
 /* One spectral grid.  64 bytes, natural alignment. */
