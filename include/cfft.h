@@ -88,7 +88,10 @@ enum { CFFT_ROOFTOP_X = 0, CFFT_ROOFTOP_Y = 1, CFFT_COSINE_X = 2, CFFT_COSINE_Y 
 /* CHECK_FINITE: scan every output for NaN/Inf and report CFFT_ERR_NONFINITE
  *   (makes the call synchronous).
  * AUTOTUNE: the first cfft_tabulate per (grid, npairs) times the candidate
- *   pair-chunk schedules (synchronously) and the plan keeps the fastest.
+ *   schedules (synchronously): pairs per launch, one or two plan-owned lanes
+ *   taking alternate chunks, default or half-width column tiles; the plan
+ *   keeps the fastest.  That first call runs the passes several times on the
+ *   caller's buffers (z ends with the same table).
  * ZERO_PAD2: every grid of the plan is the x2 zero-padded extension of the
  *   grid the caller samples (Sec. III-B.3, last paragraph: Whittaker-Shannon
  *   refinement with zero padding to twice the FFT size).  Only the central

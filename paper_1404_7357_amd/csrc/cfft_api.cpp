@@ -199,7 +199,12 @@ struct cfft_plan_s {
   int* flag_host = nullptr;
   // instrumentation: recorded (start, stop) event pairs per kernel class
   bool profiling = false;
-  std::map<long long, std::pair<long long, int>> tuned;   // (grid, npairs) -> (pair chunk, lanes)
+  struct Schedule {
+    long long chunk;   // pairs per row/column launch
+    int lanes;         // 1, or 2 plan-owned streams taking alternate chunks
+    int narrow;        // column tiles of half the default width
+  };
+  std::map<long long, Schedule> tuned;   // (grid, npairs) -> the autotuner's choice
   hipStream_t lane[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_row0 = nullptr, ev_join[2] = {nullptr, nullptr};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[kProfClasses];
@@ -263,6 +268,7 @@ PassParams pass_params(const GridState& gs) {
   p.beta_end = gs.d.beta_end;
   p.band = gs.band;
   p.precision = gs.d.precision;
+  p.col_narrow = 0;
   return p;
 }
 
@@ -681,7 +687,7 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   st = validate_pairs(pairs, npairs, nmbf);
   if (st != CFFT_OK) return st;
   GridState& gs = plan->grids[grid];
-  const PassParams pp = pass_params(gs);
+  PassParams pp = pass_params(gs);
   const size_t n = (size_t)gs.x.n * gs.y.n;
   const size_t cbytes = pp.precision == CFFT_FP64 ? 16 : 8;
   const size_t per_pair = (size_t)inter_slots(pp) * n * cbytes;
@@ -706,7 +712,8 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   // row pass (the second lane starts once the first row pass is done).  The
   // lanes fork from and join back into the caller's stream through events,
   // which keeps the call capturable in a HIP graph.
-  auto run_passes = [&](long long ck, int lanes) -> hipError_t {
+  auto run_passes = [&](long long ck, int lanes, int narrow) -> hipError_t {
+    pp.col_narrow = narrow;
     hipStream_t ls[2] = {s, s};
     if (lanes == 2) {
       hipError_t e = ensure_lanes(plan);
@@ -753,16 +760,18 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   int lanes = 1;
   const long long forced_lanes = env_ll("CFFT_LANES", 0);
   if (forced_lanes == 1 || forced_lanes == 2) lanes = (int)forced_lanes;
+  int narrow = env_ll("CFFT_COL_NARROW", 0) == 1 ? 1 : 0;
   auto lanes_ok = [&](long long ck) { return (npairs + ck - 1) / ck >= 2; };
   // With CFFT_FLAG_AUTOTUNE the first call per (grid, npairs) times every
-  // (pair chunk, lanes) candidate (synchronously) and the plan keeps the
-  // fastest.  Smaller chunks keep a chunk's intermediates resident in the
-  // memory-side cache between the two passes.
+  // (pair chunk, lanes, column tile width) candidate (synchronously) and the
+  // plan keeps the fastest.  Smaller chunks keep a chunk's intermediates
+  // resident in the memory-side cache between the two passes; narrower
+  // column tiles trade row-piece length for more, smaller blocks.
   if ((plan->flags & CFFT_FLAG_AUTOTUNE) && forced <= 0 && forced_lanes <= 0) {
     const long long key = (long long)grid * 1000003LL + npairs;
     auto it = plan->tuned.find(key);
     if (it == plan->tuned.end()) {
-      std::vector<std::pair<long long, int>> cands;
+      std::vector<cfft_plan_s::Schedule> cands;
       for (long long c : {chunk, 32LL, 16LL, 8LL, 4LL, 2LL}) {
         if (c > chunk) continue;
         for (int l : {1, 2}) {
@@ -771,21 +780,25 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
             st = ensure_ws(&plan->ws, &plan->ws_bytes, per_pair * (size_t)c * 2, "pass workspace");
             if (st != CFFT_OK) return st;
           }
-          if (std::find(cands.begin(), cands.end(), std::make_pair(c, l)) == cands.end()) cands.emplace_back(c, l);
+          for (int w : {0, 1}) {
+            bool dup = false;
+            for (const auto& x : cands) dup = dup || (x.chunk == c && x.lanes == l && x.narrow == w);
+            if (!dup) cands.push_back({c, l, w});
+          }
         }
       }
       hipEvent_t ea, eb;
       hipError_t e = hipEventCreate(&ea);
       if (e == hipSuccess) e = hipEventCreate(&eb);
       if (e != hipSuccess) return hip_fail(e, "autotune events");
-      std::pair<long long, int> best(chunk, 1);
+      cfft_plan_s::Schedule best{chunk, 1, 0};
       float best_ms = 3.4e38f;
-      for (auto c : cands) {
-        e = run_passes(c.first, c.second);  // warm-up
+      for (const auto& c : cands) {
+        e = run_passes(c.chunk, c.lanes, c.narrow);  // warm-up
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventRecord(ea, s);
-        if (e == hipSuccess) e = run_passes(c.first, c.second);
-        if (e == hipSuccess) e = run_passes(c.first, c.second);
+        if (e == hipSuccess) e = run_passes(c.chunk, c.lanes, c.narrow);
+        if (e == hipSuccess) e = run_passes(c.chunk, c.lanes, c.narrow);
         if (e == hipSuccess) e = hipEventRecord(eb, s);
         if (e == hipSuccess) e = hipEventSynchronize(eb);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
@@ -800,8 +813,9 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
       if (e != hipSuccess) return hip_fail(e, "autotune");
       it = plan->tuned.emplace(key, best).first;
     }
-    chunk = it->second.first;
-    lanes = it->second.second;
+    chunk = it->second.chunk;
+    lanes = it->second.lanes;
+    narrow = it->second.narrow;
   }
   if (lanes == 2 && !lanes_ok(chunk)) lanes = 1;
   if (lanes == 2) {
@@ -809,7 +823,7 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
     if (st != CFFT_OK) return st;
   }
   {
-    hipError_t e = run_passes(chunk, lanes);
+    hipError_t e = run_passes(chunk, lanes, narrow);
     if (e != hipSuccess) return hip_fail(e, "pass launch");
   }
   return check_finite(plan, z, 2 * n * (size_t)npairs, pp.precision != CFFT_FP64, s);

@@ -76,6 +76,7 @@ struct PassParams {
   int parabolic;      // 1: parabolic contour (per-sample ratio; N_t row transforms)
   double beta_end;
   int band;           // 1: x2 zero-padded grid, integrand only on n in [N/4, 3N/4) per axis
+  int col_narrow;     // 1: column tiles of half the default width
 };
 
 // Intermediate arrays per pair between the row and column passes.

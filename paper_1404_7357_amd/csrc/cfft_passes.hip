@@ -394,6 +394,7 @@ struct ColArgs {
   int tensor;   // every term reads slot 0 (the full row sum S_P)
   int parabolic;   // term b reads slot b and carries no (gamma ky)^b factor
   int band;     // x2 zero-padded grid: rows outside [N/4, 3N/4) are zero and not read
+  int narrow;   // tiles of half the default width (an autotuner candidate)
   const void* inter;
   void* z;
   const void* tw;
@@ -543,12 +544,22 @@ static hipError_t row_launch(const RowArgs& args, hipStream_t s) {
 
 template <typename V, int N>
 static hipError_t col_launch(const ColArgs& args, hipStream_t s) {
-  constexpr int C = col_tile_c(N, sizeof(V));
+  constexpr int C0 = col_tile_c(N, sizeof(V));
   constexpr int R = col_r(sizeof(V));
-  using Cfg = ColCfg<N, C, R>;
-  if (args.nx % C != 0) return hipErrorInvalidValue;
-  const int nblk = (args.nx / C) * args.npairs;
-  hipLaunchKernelGGL((col_pass_kernel<V, N, C, R>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
+  // the autotuner's alternative: tiles of half the width (more, smaller
+  // blocks; shorter row pieces)
+  if constexpr (C0 > 1) {
+    if (args.narrow) {
+      constexpr int C = C0 / 2;
+      if (args.nx % C != 0) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((col_pass_kernel<V, N, C, R>), dim3((args.nx / C) * args.npairs),
+                         dim3(ColCfg<N, C, R>::THREADS), 0, s, args);
+      return hipGetLastError();
+    }
+  }
+  if (args.nx % C0 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((col_pass_kernel<V, N, C0, R>), dim3((args.nx / C0) * args.npairs),
+                     dim3(ColCfg<N, C0, R>::THREADS), 0, s, args);
   return hipGetLastError();
 }
 
@@ -692,6 +703,7 @@ hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, v
   a.tensor = p.tensor;
   a.parabolic = p.parabolic;
   a.band = p.band;
+  a.narrow = p.col_narrow;
   a.npairs = npairs;
   a.ky0 = p.y.k_first;
   a.dky = p.y.dk;
