@@ -374,11 +374,12 @@ def _paper_leg(torch, steps, warmup):
 
 
 def _sweep(torch, steps, warmup):
-    """Frequency sweep, 8 uneven grids x 16 pairs (mixed), eager and as one replayed HIP graph."""
-    from paper_1404_7357_amd import Tabulator
+    """Frequency sweep, 8 uneven grids x 16 pairs (mixed), eager and as one replayed HIP graph; the
+    schedules are autotuned per grid by the first (warm-up) calls, before the capture."""
+    from paper_1404_7357_amd import FLAG_AUTOTUNE, Tabulator
     from workloads import c3_frequency_sweep
     wl = c3_frequency_sweep()
-    tab = Tabulator(wl.grids, wl.basis, max_mbf=wl.M)
+    tab = Tabulator(wl.grids, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE)
     q = torch.tensor(wl.q, device="cuda")
     pairs = [tuple(int(v) for v in p) for p in wl.pairs]
     bufs = []

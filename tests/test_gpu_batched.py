@@ -42,10 +42,13 @@ def _sweep_buffers(wl):
 
 
 def test_sweep_graph_replays_match_eager_and_oracle():
-    from paper_1404_7357_amd import Tabulator
+    """The frequency sweep with autotuned schedules (tuned by the first eager
+    calls, then captured, lanes included) replayed as one HIP graph: every
+    replay equals the eager tables, which match the oracle."""
+    from paper_1404_7357_amd import FLAG_AUTOTUNE, Tabulator
     wl = c3_frequency_sweep()
     _say("c3 sweep eager")
-    tab = Tabulator(wl.grids, wl.basis, max_mbf=wl.M)
+    tab = Tabulator(wl.grids, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE)
     q = torch.tensor(wl.q, device="cuda")
     bufs = _sweep_buffers(wl)
     _sweep_calls(tab, wl, q, bufs)
