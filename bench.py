@@ -80,20 +80,15 @@ class Step:
         self.spec = torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=torch.complex128, device="cuda")
         self.z = torch.empty((len(self.pairs), gd.ny, gd.nx), dtype=dt, device="cuda")
         self._lib = _lib
-        # The Green's function and the spectra are independent: the Green's
-        # function (few waves, latency-bound) runs on a second stream of
-        # default priority beside the spectra.
-        self.side = torch.cuda.Stream()
 
     def run(self):
+        # One stream: running the (independent) Green's function on a second
+        # stream beside the spectra measured slower at every size, the
+        # fork/join costing more than the overlap saves (512^2: 185 vs 177 us;
+        # 64^2: 93 vs 34 us).
         s = self.sub
-        torch = self.torch
-        main = torch.cuda.current_stream()
-        self.side.wait_stream(main)          # the previous step's passes are done with g
-        with torch.cuda.stream(self.side):
-            self.tab.green(s.eps_r, s.tan_delta, s.h, out=self.g)
+        self.tab.green(s.eps_r, s.tan_delta, s.h, out=self.g)
         self.tab.spectra(self.q, out=self.spec)
-        main.wait_stream(self.side)
         self.tab.tabulate(self.spec, self.g, self.pairs, out=self.z)
 
     def entries(self):
@@ -346,6 +341,25 @@ def _large_leg(torch, steps, warmup):
             "dtype": "fp32 FFT / fp64 rest", "kernels_ms": km}
 
 
+def _c1_latency(torch, steps, warmup):
+    """The smallest configuration (64^2, one MBF, one pair, FP64): launch-bound, so its step latency is
+    the figure of merit; error against the oracle's whole table."""
+    import numpy as np
+
+    from oracle import cfft_oracle as co
+    from workloads import c1_single_cosine
+    wl = c1_single_cosine()
+    st = Step(wl, torch)
+    sec = _time_steps(torch, st.run, steps, warmup)
+    torch.cuda.synchronize()
+    z = st.z.cpu().numpy()
+    st.tab.close()
+    ref = co.tabulate(wl.grids[0], wl.substrates[0], wl.basis, wl.q, wl.pairs)
+    err = float(np.abs(z - ref).max() / np.abs(ref).max())
+    return {"workload": wl.name, "latency_us": sec * 1e6, "entries": st.entries(), "rel_err_vs_oracle": err,
+            "dtype": "f64"}
+
+
 def _paper_leg(torch, steps, warmup):
     """The paper's own table setup (Sec. IV-F): a 2048^2 FFT including the x2
     zero padding, M = 9 MBFs (81 pairs), FP64; then the fill of the reduced
@@ -545,6 +559,8 @@ def main():
         out["parabolic"] = _parabolic_leg(torch, max(3, args.steps // 5), 2, max(n_out, 4))
         _log("large leg (4096^2, 36 pairs, 10^5 lookups)")
         out["large"] = _large_leg(torch, 3, 1)
+        _log("64^2 single-pair latency leg")
+        out["c1_latency"] = _c1_latency(torch, args.steps, args.warmup)
         _log("paper-setup leg (2048^2 incl. zero padding, 81 pairs, 25 x 25 array fill)")
         out["paper_setup"] = _paper_leg(torch, 3, 1)
         _log("sweep leg (8 grids, one graph)")
