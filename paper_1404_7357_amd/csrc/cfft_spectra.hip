@@ -140,19 +140,10 @@ constexpr int kMChunk = 4;
 // coalesced loads, while the basis index and the coefficient of an entry are
 // the same for a whole wave (when 64 divides ny) and come through scalar
 // loads.
-constexpr int kRowsThreads = 256;
-__global__ void __launch_bounds__(kRowsThreads)
-spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
-                    const double2* __restrict__ q, int nmbf, int mpad, double2* __restrict__ wtab) {
-  const int ppad = geo.ppad;
-  const int per_v = mpad * ppad;
-  const long long e = (long long)blockIdx.x * kRowsThreads + threadIdx.x;
-  if (e >= (long long)2 * per_v * y.n) return;
-  const int n2 = (int)(e % y.n);
-  const int ent = (int)(e / y.n);
-  const int v = ent / per_v;
-  const int m = (ent % per_v) / ppad;
-  const int pp = ent % ppad;
+// One w entry: pair slot pp of MBF m in variant v at row n2.
+__device__ __forceinline__ double2 w_entry(const Axis& x, const Axis& y, const GeomDevice& geo,
+                                           const double2* __restrict__ utab, const double2* __restrict__ q, int nmbf,
+                                           int v, int m, int pp, int n2) {
   int g = 0;
   while (g + 1 < geo.ngroups && geo.groups[g + 1].poff <= pp) ++g;
   const GeomGroup gr = geo.groups[g];
@@ -178,7 +169,23 @@ spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ 
     }
     acc = cmul(acc, vtab[(size_t)(2 * geo.total_r + g) * y.n + n2]);
   }
-  wtab[((size_t)n2 * 2 + v) * per_v + (size_t)m * ppad + pp] = acc;
+  return acc;
+}
+
+constexpr int kRowsThreads = 256;
+__global__ void __launch_bounds__(kRowsThreads)
+spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
+                    const double2* __restrict__ q, int nmbf, int mpad, double2* __restrict__ wtab) {
+  const int ppad = geo.ppad;
+  const int per_v = mpad * ppad;
+  const long long e = (long long)blockIdx.x * kRowsThreads + threadIdx.x;
+  if (e >= (long long)2 * per_v * y.n) return;
+  const int n2 = (int)(e % y.n);
+  const int ent = (int)(e / y.n);
+  const int v = ent / per_v;
+  const int m = (ent % per_v) / ppad;
+  const int pp = ent % ppad;
+  wtab[((size_t)n2 * 2 + v) * per_v + (size_t)m * ppad + pp] = w_entry(x, y, geo, utab, q, nmbf, v, m, pp, n2);
 }
 
 // Per-sample sums of one block: thread = sample n1 (byte offset boff in a
