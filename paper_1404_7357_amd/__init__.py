@@ -35,6 +35,13 @@ def displacement_axis(n: int, k_max: float):
     return [-x_max + j * math.pi / k_max for j in range(n)]
 
 
+def _check_buffer(t, shape, dtype, name):
+    """Shape, dtype and device of a caller-provided buffer (the C ABI cannot see them)."""
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a {dtype} cuda tensor of shape {tuple(shape)}, got {t.dtype} "
+                         f"{tuple(t.shape)} on {t.device}")
+
+
 class Tabulator:
     """One plan bound to one or more grids and one basis set."""
 
@@ -76,6 +83,8 @@ class Tabulator:
         second-order Lagrange (order 2) interpolation."""
         out = out if out is not None else torch.empty((z.shape[0], pts.shape[0]), dtype=torch.complex128,
                                                       device=self.device)
+        _check_buffer(out, (z.shape[0], pts.shape[0]), torch.complex128, "out")
+        _check_buffer(pts, (pts.shape[0], 2), torch.float64, "pts")
         if order == 2:
             cfft_lookup_quadratic(self.plan, grid, z, z.shape[0], pts.contiguous(), out, stream)
         elif order == 1:
@@ -92,6 +101,10 @@ class Tabulator:
         if out is None:
             out = torch.full((am, am), complex(float("nan"), float("nan")), dtype=torch.complex128,
                              device=self.device)
+        _check_buffer(out, (am, am), torch.complex128, "out")
+        _check_buffer(pos, (pos.shape[0], 2), torch.float64, "pos")
+        if z.shape[0] != len(pairs):
+            raise ValueError(f"z holds {z.shape[0]} tables for {len(pairs)} pairs")
         cfft_fill(self.plan, grid, z, pairs, nmbf, pos.contiguous(), order, out, stream)
         return out
 
