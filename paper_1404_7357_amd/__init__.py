@@ -58,6 +58,7 @@ class Tabulator:
     def green(self, eps_r, tan_delta, h, grid: int = 0, out=None, stream=None):
         gd = self._grid(grid)
         g = out if out is not None else torch.empty((3, gd.ny, gd.nx), dtype=torch.complex128, device=self.device)
+        _check_buffer(g, (3, gd.ny, gd.nx), torch.complex128, "out")
         slab_green_eval(self.plan, grid, eps_r, tan_delta, h, g, stream)
         return g
 
@@ -68,6 +69,7 @@ class Tabulator:
             raise ValueError("q must be complex128 [M][nbasis]")
         spec = out if out is not None else torch.empty((q.shape[0], 4, gd.ny, gd.nx), dtype=torch.complex128,
                                                        device=self.device)
+        _check_buffer(spec, (q.shape[0], 4, gd.ny, gd.nx), torch.complex128, "out")
         mbf_spectra(self.plan, grid, self.basis, q, spec, stream)
         return spec
 
@@ -75,6 +77,9 @@ class Tabulator:
         gd = self._grid(grid)
         dt = torch.complex128 if gd.precision == FP64 else torch.complex64
         z = out if out is not None else torch.empty((len(pairs), gd.ny, gd.nx), dtype=dt, device=self.device)
+        _check_buffer(z, (len(pairs), gd.ny, gd.nx), dt, "out")
+        _check_buffer(g, (3, gd.ny, gd.nx), torch.complex128, "g")
+        _check_buffer(spec, (spec.shape[0], 4, gd.ny, gd.nx), torch.complex128, "spec")
         cfft_tabulate(self.plan, grid, spec, spec.shape[0], g, pairs, z, stream)
         return z
 
