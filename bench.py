@@ -440,7 +440,7 @@ def main():
                     help="run one extra leg alone and print its JSON (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     _ensure_built()
     import numpy as np

@@ -67,7 +67,7 @@ typedef struct cfft_plan_s* cfft_plan_t;
 typedef enum {
   CFFT_OK = 0,
   CFFT_ERR_INVALID_ARG = 1,   /* bad size, null pointer, out-of-range index, non-finite scalar */
-  CFFT_ERR_UNSUPPORTED = 2,   /* valid request outside what this build implements */
+  CFFT_ERR_UNSUPPORTED = 2,   /* valid request outside what the library implements */
   CFFT_ERR_ALLOC = 3,         /* device allocation failed */
   CFFT_ERR_HIP = 4,           /* HIP runtime error (no device, launch failure) */
   CFFT_ERR_NONFINITE = 5      /* a kernel produced NaN/Inf (only with CFFT_FLAG_CHECK_FINITE) */
