@@ -102,6 +102,32 @@ def test_calls_on_unknown_plan_are_rejected():
     assert lib.c_fft_plan_destroy(bogus) == 1
 
 
+def test_every_entry_point_rejects_a_null_plan():
+    """Each plan-taking entry point returns CFFT_ERR_INVALID_ARG for a NULL
+    plan before touching any pointer or device."""
+    L, lib = _lib()
+    nul = ctypes.c_void_p(0)
+    pairs = (ctypes.c_int32 * 2)(0, 0)
+    basis = (L.Basis * 1)()
+    calls = {
+        "slab_green_eval": lambda: lib.slab_green_eval(None, 0, 2.2, 0.0, 0.05, nul, None),
+        "mbf_spectra": lambda: lib.mbf_spectra(None, 0, basis, 1, nul, 1, nul, None),
+        "cfft_tabulate": lambda: lib.cfft_tabulate(None, 0, nul, 1, nul, pairs, 1, nul, None),
+        "cfft_lookup": lambda: lib.cfft_lookup(None, 0, nul, 1, nul, 1, nul, None),
+        "cfft_lookup_quadratic": lambda: lib.cfft_lookup_quadratic(None, 0, nul, 1, nul, 1, nul, None),
+        "cfft_fill": lambda: lib.cfft_fill(None, 0, nul, pairs, 1, 1, nul, 2, 2, nul, None),
+        "cfft_lookup_backward": lambda: lib.cfft_lookup_backward(None, 0, nul, 1, nul, 1, nul, None),
+        "cfft_backward": lambda: lib.cfft_backward(None, 0, nul, 2.2, 0.0, 0.05, basis, 1, nul, 1, pairs, 1, nul, nul,
+                                                   nul, nul, None),
+        "cfft_profile": lambda: lib.cfft_profile(None, 1),
+    }
+    for name, call in calls.items():
+        assert call() == 1, name
+        assert lib.cfft_last_error().decode(), name
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert lib.cfft_profile_read(None, 0, ctypes.byref(ms), ctypes.byref(n)) == 1
+
+
 def test_no_device_is_reported_not_faked():
     """Without a GPU a valid plan request fails with CFFT_ERR_HIP (no CPU fallback)."""
     import torch
