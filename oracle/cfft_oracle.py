@@ -554,11 +554,22 @@ def fill_reduced(grid, table, pairs, nmbf, positions, order=2):
     return out
 
 
-def lookup_direct(grid, substrate, basis, q, pairs, pts, workers=1):
-    """Bilinear lookup with the four corners evaluated by direct sum only."""
+def interpolation_corners(grid, pts, order=1):
+    """(j1, j2, weight) of every table node an interpolated value uses: the
+    four bilinear corners (order 1) or the 3 x 3 second-order stencil of
+    quadratic_nodes with the products of lagrange3 weights (order 2)."""
+    if order == 2:
+        c1, c2, tx, ty = quadratic_nodes(grid, pts)
+        wx, wy = lagrange3(tx), lagrange3(ty)
+        return [(c1 + a - 1, c2 + b - 1, wx[a] * wy[b]) for b in range(3) for a in range(3)]
     j1, j2, tx, ty = bilinear_corners(grid, pts)
-    corners = [(j1, j2, (1 - tx) * (1 - ty)), (j1 + 1, j2, tx * (1 - ty)),
-               (j1, j2 + 1, (1 - tx) * ty), (j1 + 1, j2 + 1, tx * ty)]
+    return [(j1, j2, (1 - tx) * (1 - ty)), (j1 + 1, j2, tx * (1 - ty)),
+            (j1, j2 + 1, (1 - tx) * ty), (j1 + 1, j2 + 1, tx * ty)]
+
+
+def lookup_direct(grid, substrate, basis, q, pairs, pts, workers=1, order=1):
+    """Lookup (bilinear or second order) with the nodes it uses evaluated by direct sum only."""
+    corners = interpolation_corners(grid, pts, order)
     idx = np.concatenate([c[1] * grid.nx + c[0] for c in corners])
     z = tabulate(grid, substrate, basis, q, pairs, out_idx=idx, workers=workers)
     nq = len(pts)
@@ -606,8 +617,12 @@ def cauchy_derivative(f, z0, radius=None, count=32):
     return acc / (count * radius)
 
 
-def loss_gradient(grid, substrate, basis, q, pairs, pts, z_target, workers=1):
+def loss_gradient(grid, substrate, basis, q, pairs, pts, z_target, workers=1, order=1):
     """(L, dL/d eps_r, dL/d h, dL/dq) of the lookup loss, in FP64.
+
+    The lookup is bilinear (order 1) or second order (order 2, the
+    interpolation of Sec. III-B.3 in the refined table); on a zero-padded
+    grid only the band samples carry the integrand (band_mask).
 
     eps_r and h enter the table holomorphically, so dZ/dtheta comes from the
     Cauchy rule applied to the oracle's own forward map with complex theta;
@@ -620,15 +635,17 @@ def loss_gradient(grid, substrate, basis, q, pairs, pts, z_target, workers=1):
     d/dRe + i d/dIm convention.
     """
     pairs = np.asarray(pairs)
-    z = lookup_direct(grid, substrate, basis, q, pairs, pts, workers=workers)
+    z = lookup_direct(grid, substrate, basis, q, pairs, pts, workers=workers, order=order)
     r = z - z_target
     loss = loss_value(z, z_target)
 
     def z_of_eps(e):
-        return lookup_direct(grid, _with_substrate(substrate, eps_r=e), basis, q, pairs, pts, workers=workers)
+        return lookup_direct(grid, _with_substrate(substrate, eps_r=e), basis, q, pairs, pts, workers=workers,
+                             order=order)
 
     def z_of_h(hh):
-        return lookup_direct(grid, _with_substrate(substrate, h=hh), basis, q, pairs, pts, workers=workers)
+        return lookup_direct(grid, _with_substrate(substrate, h=hh), basis, q, pairs, pts, workers=workers,
+                             order=order)
 
     dz_de = cauchy_derivative(z_of_eps, substrate.eps_r)
     dz_dh = cauchy_derivative(z_of_h, substrate.h)
@@ -637,9 +654,7 @@ def loss_gradient(grid, substrate, basis, q, pairs, pts, z_target, workers=1):
 
     # exact q gradient from single-basis tables
     m_count, b_count = q.shape
-    j1, j2, tx, ty = bilinear_corners(grid, pts)
-    corners = [(j1, j2, (1 - tx) * (1 - ty)), (j1 + 1, j2, tx * (1 - ty)),
-               (j1, j2 + 1, (1 - tx) * ty), (j1 + 1, j2 + 1, tx * ty)]
+    corners = interpolation_corners(grid, pts, order)
     idx = np.concatenate([c[1] * grid.nx + c[0] for c in corners])
     kx, ky, w, g, mt, mh = sampled_factors(grid, substrate, basis, q)
     eye = np.eye(b_count, dtype=np.complex128)
@@ -663,11 +678,13 @@ def loss_gradient(grid, substrate, basis, q, pairs, pts, z_target, workers=1):
             out += wgt * zz[:, i * nq:(i + 1) * nq]
         return out
 
+    mask = band_mask(grid)
+    mask = 1.0 if mask is None else mask
     # A[j, n]: testing basis j (unit), basis MBF n
-    a_int = np.stack([integrand(ut[j], mh[n], gxx, gxy, gyy, w) for j in range(b_count) for n in range(m_count)])
+    a_int = np.stack([integrand(ut[j], mh[n], gxx, gxy, gyy, w) for j in range(b_count) for n in range(m_count)]) * mask
     A = lookup_of(a_int).reshape(b_count, m_count, nq)
     # B[m, j]: testing MBF m, basis j (unit)
-    b_int = np.stack([integrand(mt[m], uh[j], gxx, gxy, gyy, w) for m in range(m_count) for j in range(b_count)])
+    b_int = np.stack([integrand(mt[m], uh[j], gxx, gxy, gyy, w) for m in range(m_count) for j in range(b_count)]) * mask
     Bm = lookup_of(b_int).reshape(m_count, b_count, nq)
     # residual per (m, n)
     R = np.zeros((m_count, m_count, nq), dtype=np.complex128)
