@@ -100,8 +100,8 @@ enum { CFFT_ROOFTOP_X = 0, CFFT_ROOFTOP_Y = 1, CFFT_COSINE_X = 2, CFFT_COSINE_Y 
  *   span, and its even nodes are the unrefined table.  The grid descriptor
  *   describes the padded grid (2N samples over twice the spectral span).
  *   slab_green_eval and mbf_spectra still write every sample; the passes
- *   read only the band and skip the rows that are zero.  The adjoint
- *   refuses such a plan. */
+ *   read only the band and skip the rows that are zero; cfft_backward
+ *   returns no gradient from the samples outside the band. */
 enum { CFFT_FLAG_CHECK_FINITE = 1, CFFT_FLAG_AUTOTUNE = 2, CFFT_FLAG_ZERO_PAD2 = 4 };
 
 /* One spectral grid.  64 bytes, natural alignment. */
@@ -225,8 +225,16 @@ cfft_status_t cfft_lookup_backward(cfft_plan_t plan, int32_t grid, const void* d
                                    int32_t npairs, const double* pts, int32_t npts, void* dz,
                                    void* stream);
 
+/* Adjoint of cfft_lookup_quadratic: dz[p][j2][j1] += sum over points of the
+ * 3 x 3 Lagrange weight of node (j1, j2) times dout[p][q]; points outside
+ * the table contribute nothing.  Same arguments, layout and conditions as
+ * cfft_lookup_backward. */
+cfft_status_t cfft_lookup_quadratic_backward(cfft_plan_t plan, int32_t grid, const void* dout,
+                                             int32_t npairs, const double* pts, int32_t npts, void* dz,
+                                             void* stream);
+
 /* Gradient of a real loss L through the whole table (FP64 grids on the ray
- * contour; other grids return CFFT_ERR_UNSUPPORTED).
+ * contour, zero-padded or not; other grids return CFFT_ERR_UNSUPPORTED).
  *   dz       : device complex128 [npairs][ny][nx], dL/dRe z + i dL/dIm z
  *   eps_r, tan_delta, h, basis, nbasis, q, nmbf, pairs, npairs : the forward inputs
  *   g, spec  : device, the forward's sampled Green's function and spectra

@@ -20,13 +20,15 @@ import torch
 from . import _lib
 from ._lib import (CONTOUR_RAY, FLAG_AUTOTUNE, FLAG_CHECK_FINITE, FLAG_ZERO_PAD2, FP64, MIXED,  # noqa: F401
                    TRUNC_TENSOR, TRUNC_TOTAL, CfftError, Plan, cfft_backward, cfft_fill, cfft_lookup,
-                   cfft_lookup_backward, cfft_lookup_quadratic, cfft_tabulate, mbf_spectra, slab_green_eval)
+                   cfft_lookup_backward, cfft_lookup_quadratic, cfft_lookup_quadratic_backward, cfft_tabulate,
+                   mbf_spectra, slab_green_eval)
 
 _lib.load()
 
 __all__ = ["Tabulator", "Plan", "CfftError", "TableFunction", "LookupFunction", "FP64", "MIXED",
            "slab_green_eval", "mbf_spectra", "cfft_tabulate", "cfft_lookup", "cfft_lookup_quadratic",
-           "cfft_fill", "cfft_lookup_backward", "cfft_backward", "displacement_axis"]
+           "cfft_fill", "cfft_lookup_backward", "cfft_lookup_quadratic_backward", "cfft_backward",
+           "displacement_axis"]
 
 
 def displacement_axis(n: int, k_max: float):
@@ -148,19 +150,21 @@ class TableFunction(torch.autograd.Function):
 
 
 class LookupFunction(torch.autograd.Function):
-    """Bilinear table lookup with its scatter-add adjoint."""
+    """Table lookup (bilinear, order 1, or second order, order 2) with its
+    scatter-add adjoint."""
 
     @staticmethod
-    def forward(ctx, z, pts, tab: Tabulator, grid: int):
-        out = tab.lookup(z, pts, grid)
+    def forward(ctx, z, pts, tab: Tabulator, grid: int, order: int = 1):
+        out = tab.lookup(z, pts, grid, order=order)
         ctx.save_for_backward(pts)
-        ctx.meta = (tab, grid, z.shape)
+        ctx.meta = (tab, grid, z.shape, order)
         return out
 
     @staticmethod
     def backward(ctx, gout):
         (pts,) = ctx.saved_tensors
-        tab, grid, shape = ctx.meta
+        tab, grid, shape, order = ctx.meta
         dz = torch.zeros(shape, dtype=torch.complex128, device=gout.device)
-        cfft_lookup_backward(tab.plan, grid, gout.contiguous().to(torch.complex128), shape[0], pts, dz)
-        return dz, None, None, None
+        back = cfft_lookup_quadratic_backward if order == 2 else cfft_lookup_backward
+        back(tab.plan, grid, gout.contiguous().to(torch.complex128), shape[0], pts, dz)
+        return dz, None, None, None, None

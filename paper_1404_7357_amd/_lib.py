@@ -27,7 +27,8 @@ FLAG_AUTOTUNE = 2
 FLAG_ZERO_PAD2 = 4
 
 ENTRY_POINTS = ("c_fft_plan", "c_fft_plan_destroy", "slab_green_eval", "mbf_spectra", "cfft_tabulate",
-                "cfft_lookup", "cfft_lookup_quadratic", "cfft_fill", "cfft_lookup_backward", "cfft_backward", "cfft_profile",
+                "cfft_lookup", "cfft_lookup_quadratic", "cfft_fill", "cfft_lookup_backward",
+                "cfft_lookup_quadratic_backward", "cfft_backward", "cfft_profile",
                 "cfft_profile_read",
                 "cfft_last_error", "cfft_version")
 
@@ -77,6 +78,7 @@ def load(path: str = LIB_PATH):
     lib.cfft_lookup_quadratic.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_fill.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int32), i32, i32, vp, i32, i32, vp, vp]
     lib.cfft_lookup_backward.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
+    lib.cfft_lookup_quadratic_backward.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_backward.argtypes = [vp, i32, vp, dbl, dbl, dbl, ctypes.POINTER(Basis), i32, vp, i32,
                                   ctypes.POINTER(ctypes.c_int32), i32, vp, vp, vp, vp, vp]
     lib.cfft_profile.argtypes = [vp, i32]
@@ -189,6 +191,11 @@ def cfft_fill(plan: Plan, grid: int, z, pairs, nmbf: int, pos, order: int, out, 
 def cfft_lookup_backward(plan: Plan, grid: int, dout, npairs: int, pts, dz, stream=None):
     check(load().cfft_lookup_backward(plan.handle, grid, _ptr(dout), int(npairs), _ptr(pts), int(pts.shape[0]),
                                       _ptr(dz), _stream(stream)))
+
+
+def cfft_lookup_quadratic_backward(plan: Plan, grid: int, dout, npairs: int, pts, dz, stream=None):
+    check(load().cfft_lookup_quadratic_backward(plan.handle, grid, _ptr(dout), int(npairs), _ptr(pts),
+                                                int(pts.shape[0]), _ptr(dz), _stream(stream)))
 
 
 def cfft_backward(plan: Plan, grid: int, dz, eps_r, tan_delta, h, basis, q, pairs, g, spec, grad_sub, grad_q,

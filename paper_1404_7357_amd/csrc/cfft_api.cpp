@@ -889,8 +889,8 @@ cfft_status_t cfft_fill(cfft_plan_t plan, int32_t grid, const void* z, const int
   return CFFT_OK;
 }
 
-cfft_status_t cfft_lookup_backward(cfft_plan_t plan, int32_t grid, const void* dout, int32_t npairs,
-                                   const double* pts, int32_t npts, void* dz, void* stream) {
+static cfft_status_t lookup_backward_common(cfft_plan_t plan, int32_t grid, const void* dout, int32_t npairs,
+                                            const double* pts, int32_t npts, void* dz, void* stream, bool quadratic) {
   g_last_error.clear();
   cfft_status_t st = check_plan(plan, grid);
   if (st != CFFT_OK) return st;
@@ -900,10 +900,20 @@ cfft_status_t cfft_lookup_backward(cfft_plan_t plan, int32_t grid, const void* d
     return fail(CFFT_ERR_INVALID_ARG, "npts %d invalid", npts);
   GridState& gs = plan->grids[grid];
   if (gs.d.precision != CFFT_FP64) return fail(CFFT_ERR_UNSUPPORTED, "lookup adjoint needs an FP64 grid");
-  hipError_t e =
-      launch_lookup_backward(pass_params(gs), (const double2*)dout, npairs, pts, npts, (double2*)dz, (hipStream_t)stream);
+  hipError_t e = launch_lookup_backward(pass_params(gs), (const double2*)dout, npairs, pts, npts, (double2*)dz,
+                                        quadratic, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "lookup adjoint launch");
   return CFFT_OK;
+}
+
+cfft_status_t cfft_lookup_backward(cfft_plan_t plan, int32_t grid, const void* dout, int32_t npairs,
+                                   const double* pts, int32_t npts, void* dz, void* stream) {
+  return lookup_backward_common(plan, grid, dout, npairs, pts, npts, dz, stream, false);
+}
+
+cfft_status_t cfft_lookup_quadratic_backward(cfft_plan_t plan, int32_t grid, const void* dout, int32_t npairs,
+                                             const double* pts, int32_t npts, void* dz, void* stream) {
+  return lookup_backward_common(plan, grid, dout, npairs, pts, npts, dz, stream, true);
 }
 
 cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, double eps_r, double tan_delta, double h,
@@ -928,7 +938,6 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   GridState& gs = plan->grids[grid];
   if (gs.d.precision != CFFT_FP64) return fail(CFFT_ERR_UNSUPPORTED, "the adjoint needs an FP64 grid");
   if (gs.d.contour != CFFT_CONTOUR_RAY) return fail(CFFT_ERR_UNSUPPORTED, "the adjoint needs the ray contour");
-  if (gs.band) return fail(CFFT_ERR_UNSUPPORTED, "the adjoint does not handle zero-padded grids");
   hipStream_t s = (hipStream_t)stream;
   st = ensure_geometry(plan, gs, basis, nbasis, s);
   if (st != CFFT_OK) return st;

@@ -115,7 +115,7 @@ constexpr int kFillMaxMbf = 16;
 hipError_t launch_fill(const PassParams& p, const void* z, const short* slot, int nmbf, const double* pos,
                        int nelem, int order, double2* out, hipStream_t s);
 hipError_t launch_lookup_backward(const PassParams& p, const double2* dout, int npairs,
-                                  const double* pts, int npts, double2* dz, hipStream_t s);
+                                  const double* pts, int npts, double2* dz, bool quadratic, hipStream_t s);
 
 // Adjoint.
 hipError_t launch_adj_col_pass(const PassParams& p, const double2* dz, int npairs, double2* inter,

@@ -925,6 +925,7 @@ struct AdjIntArgs {
   double2* gg;
   double2* gspec;
   int n, npairs, nmbf, accumulate;
+  int nx, ny, band;   // zero-padded grid: samples outside the band carry no integrand
   int pm[kMaxPairsPerLaunch];
   int pn[kMaxPairsPerLaunch];
 };
@@ -932,6 +933,9 @@ struct AdjIntArgs {
 __global__ void __launch_bounds__(256) adj_integrand_kernel(AdjIntArgs a) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= a.n) return;
+  // the forward zeroes the integrand outside the band of a zero-padded grid,
+  // so nothing flows back to the Green's function or spectra there
+  const bool silent = a.band && !(in_band(idx % a.nx, a.nx) && in_band(idx / a.nx, a.ny));
   const size_t plane = (size_t)a.n;
   const double2 gxx = a.g[idx], gxy = a.g[plane + idx], gyy = a.g[2 * plane + idx];
   double2 ggxx = make_double2(0.0, 0.0), ggxy = ggxx, ggyy = ggxx;
@@ -948,7 +952,7 @@ __global__ void __launch_bounds__(256) adj_integrand_kernel(AdjIntArgs a) {
     const double2 my = a.spec[((size_t)mm * 4 + 1) * plane + idx];
     const double2 mxh_self = a.spec[((size_t)mm * 4 + 2) * plane + idx];
     const double2 myh_self = a.spec[((size_t)mm * 4 + 3) * plane + idx];
-    for (int p = 0; p < a.npairs; ++p) {
+    for (int p = 0; p < (silent ? 0 : a.npairs); ++p) {
       const int m = a.pm[p], n = a.pn[p];
       if (m != mm && n != mm) continue;
       touched = true;
@@ -1003,6 +1007,9 @@ hipError_t launch_adj_integrand(const PassParams& p, const double2* gi, const do
   a.gg = gg;
   a.gspec = gspec;
   a.n = p.x.n * p.y.n;
+  a.nx = p.x.n;
+  a.ny = p.y.n;
+  a.band = p.band;
   a.npairs = npairs;
   a.nmbf = nmbf;
   a.accumulate = accumulate;
@@ -1205,6 +1212,32 @@ hipError_t launch_fill(const PassParams& p, const void* z, const short* slot, in
   return hipGetLastError();
 }
 
+// Adjoint of the second-order lookup: dz[p][stencil] += w dout[p][q].
+__global__ void lookup_quadratic_backward_kernel(LookupArgs a, const double2* __restrict__ dout, double2* dz) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.npairs * a.npts) return;
+  const int p = e / a.npts, q = e % a.npts;
+  int c1, c2;
+  double tx, ty;
+  if (!stencil_at((a.pts[2 * q] - a.x0) / a.ddx, (a.pts[2 * q + 1] - a.y0) / a.ddy, a.nx, a.ny, c1, c2, tx, ty)) return;
+  double wx[3], wy[3];
+  lagrange3(tx, wx);
+  lagrange3(ty, wy);
+  const double2 g = dout[e];
+  double* d = (double*)dz;
+  const size_t base = (size_t)p * a.nx * a.ny;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t id = base + (size_t)(c2 + b - 1) * a.nx + (c1 + i - 1);
+      const double w = wy[b] * wx[i];
+      atomicAdd(d + 2 * id, w * g.x);
+      atomicAdd(d + 2 * id + 1, w * g.y);
+    }
+  }
+}
+
 static LookupArgs lookup_args(const PassParams& p, const void* z, int npairs, const double* pts, int npts,
                               double2* out) {
   LookupArgs a;
@@ -1240,10 +1273,14 @@ hipError_t launch_lookup_quadratic(const PassParams& p, const void* z, int npair
 }
 
 hipError_t launch_lookup_backward(const PassParams& p, const double2* dout, int npairs, const double* pts,
-                                  int npts, double2* dz, hipStream_t s) {
+                                  int npts, double2* dz, bool quadratic, hipStream_t s) {
   const LookupArgs a = lookup_args(p, nullptr, npairs, pts, npts, nullptr);
   const long long n = (long long)npairs * npts;
-  hipLaunchKernelGGL(lookup_backward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, dout, dz);
+  if (quadratic)
+    hipLaunchKernelGGL(lookup_quadratic_backward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, dout,
+                       dz);
+  else
+    hipLaunchKernelGGL(lookup_backward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, dout, dz);
   return hipGetLastError();
 }
 

@@ -40,14 +40,14 @@ def _problem(n=64, m=2, seed=41, npts=32, truncation=0):
     return grid, sub, basis, q, pairs, pts, zt
 
 
-def _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt, eps=None, h=None, qv=None, need_grad=True):
-    from paper_1404_7357_amd import LookupFunction, TableFunction, Tabulator
-    tab = Tabulator(grid, basis, max_mbf=q.shape[0])
+def _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt, eps=None, h=None, qv=None, need_grad=True, order=1):
+    from paper_1404_7357_amd import FLAG_ZERO_PAD2, LookupFunction, TableFunction, Tabulator
+    tab = Tabulator(grid, basis, max_mbf=q.shape[0], flags=FLAG_ZERO_PAD2 if getattr(grid, "zero_pad", 0) else 0)
     e = torch.tensor(sub.eps_r if eps is None else eps, dtype=torch.float64, device="cuda", requires_grad=True)
     hh = torch.tensor(sub.h if h is None else h, dtype=torch.float64, device="cuda", requires_grad=True)
     qq = torch.tensor(q if qv is None else qv, device="cuda", requires_grad=True)
     z = TableFunction.apply(e, hh, qq, tab, sub.tan_delta, pairs, 0)
-    v = LookupFunction.apply(z, torch.tensor(pts, device="cuda"), tab, 0)
+    v = LookupFunction.apply(z, torch.tensor(pts, device="cuda"), tab, 0, order)
     loss = (v - torch.tensor(zt, device="cuda")).abs().pow(2).sum()
     out = [float(loss.item())]
     if need_grad:
@@ -168,3 +168,61 @@ def test_full_size_gradient_vs_central_differences():
         fi = (loss_of(sub.eps_r, sub.h, wl.q + 1j * d, False) - loss_of(sub.eps_r, sub.h, wl.q - 1j * d, False)) / (2 * step)
         assert abs(dq[m, j] - (fr + 1j * fi)) < 1e-6 * np.abs(dq).max(), (m, j)
     tab.close()
+
+
+def test_second_order_lookup_adjoint_is_the_transpose():
+    """<dout, L z> = <L^T dout, z> for the second-order lookup L (random
+    table and cotangent), with points on the table edges and outside."""
+    _say("second-order lookup adjoint identity")
+    from paper_1404_7357_amd import Tabulator
+    rng = np.random.default_rng(61)
+    grid = Grid(64, 32, 8 * K0, 6 * K0, K0)
+    tab = Tabulator(grid, rooftop_lattice(1, 1), 1)
+    z = torch.tensor(rng.standard_normal((3, 32, 64)) + 1j * rng.standard_normal((3, 32, 64)), device="cuda")
+    dxa = co.displacement_axis(64, grid.kx_max)
+    dya = co.displacement_axis(32, grid.ky_max)
+    pts = np.stack([rng.uniform(dxa[0], dxa[-1], 300), rng.uniform(dya[0], dya[-1], 300)], 1)
+    pts = np.concatenate([pts, [[dxa[0], dya[0]], [dxa[-1], dya[-1]], [dxa[-1] + 1.0, 0.0]]])
+    p = torch.tensor(pts, device="cuda")
+    dout = torch.tensor(rng.standard_normal((3, len(pts))) + 1j * rng.standard_normal((3, len(pts))), device="cuda")
+    dout[:, -1] = 0                                   # the outside point has no value to weigh
+    from paper_1404_7357_amd import cfft_lookup_quadratic_backward
+    v = tab.lookup(z, p, order=2)
+    dz = torch.zeros_like(z)
+    cfft_lookup_quadratic_backward(tab.plan, 0, dout, 3, p, dz)
+    torch.cuda.synchronize()
+    tab.close()
+    lhs = torch.sum(torch.conj(dout[:, :-1]) * v[:, :-1]).item()
+    rhs = torch.sum(torch.conj(dz) * z).item()
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_refined_second_order_gradient_vs_oracle_and_differences():
+    """The paper's table use made differentiable: a x2 zero-padded grid read
+    by second-order lookups; the gradient (band samples only) against the
+    oracle's and central differences of the GPU forward."""
+    import dataclasses
+    _say("adjoint refined grid + second-order lookups")
+    rng = np.random.default_rng(67)
+    base = Grid(32, 32, 6 * K0, 6 * K0, K0)
+    grid = dataclasses.replace(base, nx=64, ny=64, kx_max=12 * K0, ky_max=12 * K0, zero_pad=1)
+    sub = Substrate(2.2, 0.0, 0.05)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 0), (0, 1), (1, 0), (1, 1)]
+    dxa = co.displacement_axis(64, grid.kx_max)
+    pts = rng.uniform(dxa[1], dxa[-2], (24, 2))
+    qt = q + 0.1 * gaussian_coefficients(rng, 2, basis.shape[0])
+    zt = co.lookup_direct(grid, Substrate(2.3, 0.0, 0.05), basis, qt, np.array(pairs), pts, order=2)
+    loss, de, dh, dq = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt, order=2)
+    o_loss, o_de, o_dh, o_dq = co.loss_gradient(grid, sub, basis, q, np.array(pairs), pts, zt, order=2)
+    assert abs(loss - o_loss) < 1e-9 * abs(o_loss)
+    assert abs(de - o_de) < 1e-9 * abs(o_de), (de, o_de)
+    assert abs(dh - o_dh) < 1e-9 * abs(o_dh), (dh, o_dh)
+    assert np.abs(dq - o_dq).max() < 1e-9 * np.abs(o_dq).max()
+    step = 1e-6
+
+    def L(**kw):
+        return _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt, need_grad=False, order=2, **kw)[0]
+    fd_h = (L(h=sub.h + step) - L(h=sub.h - step)) / (2 * step)
+    assert abs(dh - fd_h) < 1e-6 * abs(fd_h), (dh, fd_h)

@@ -494,9 +494,8 @@ def test_zero_padded_kernels_and_variants(nx, ny, variant):
 def test_zero_padded_refinement_and_quadratic_lookup():
     """x2 zero-padded grid (Whittaker-Shannon refinement): the refined table
     vs the oracle's, its even nodes vs the unrefined GPU table, and the
-    paper's table use (refined table + second-order lookup) vs the oracle.
-    The adjoint refuses such a plan."""
-    from paper_1404_7357_amd import FLAG_ZERO_PAD2, CfftError, Tabulator, cfft_backward
+    paper's table use (refined table + second-order lookup) vs the oracle."""
+    from paper_1404_7357_amd import FLAG_ZERO_PAD2, Tabulator
     rng = np.random.default_rng(61)
     basis = rooftop_lattice(2, 3)
     q = gaussian_coefficients(rng, 2, basis.shape[0])
@@ -520,10 +519,6 @@ def test_zero_padded_refinement_and_quadratic_lookup():
         lay = lay - lay.mean(0) + rng.uniform(-0.05, 0.05, lay.shape)              # jittered 5 x 4 array
         fz = tab.fill(z, pairs, 2, torch.tensor(lay, device="cuda")).cpu().numpy()
         zz = z.cpu().numpy()
-        if prec == FP64:
-            with pytest.raises(CfftError):
-                cfft_backward(tab.plan, 0, torch.zeros_like(z), sub.eps_r, sub.tan_delta, sub.h, tab.basis, qd, pairs,
-                              g, spec, torch.empty(2, dtype=torch.float64, device="cuda"), torch.empty_like(qd))
         tab.close()
         ref = co.tabulate(pad, sub, basis, q, np.array(pairs))
         assert _err(zz, ref) < tol
