@@ -218,6 +218,19 @@ cfft_status_t cfft_fill(cfft_plan_t plan, int32_t grid, const void* z, const int
                         int32_t npairs, int32_t nmbf, const double* pos, int32_t nelem,
                         int32_t order, void* out, void* stream);
 
+/* Adjoint of cfft_fill: every entry the fill writes scatters its cotangent,
+ * times its interpolation weights, into the table of its pair:
+ *   dz[k][j2][j1] += sum over written entries of weight(j1, j2) dout[row][col]
+ *   dout : device complex128 [nelem*nmbf][nelem*nmbf], dL/dRe + i dL/dIm
+ *   dz   : device complex128 [npairs][ny][nx], zeroed by the caller before
+ *          the first accumulation (FP64 grids only)
+ * Other arguments and limits as cfft_fill; entries that the fill does not
+ * write (self blocks, unlisted pairs, displacements outside the table)
+ * contribute nothing. */
+cfft_status_t cfft_fill_backward(cfft_plan_t plan, int32_t grid, const void* dout, const int32_t* pairs,
+                                 int32_t npairs, int32_t nmbf, const double* pos, int32_t nelem,
+                                 int32_t order, void* dz, void* stream);
+
 /* Adjoint of cfft_lookup: dz[p][j2][j1] += sum over points of the bilinear
  * weight times dout[p][q] (complex128, FP64 grids only).  dz must be zeroed
  * by the caller before the first accumulation. */

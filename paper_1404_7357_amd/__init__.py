@@ -19,15 +19,15 @@ import torch
 
 from . import _lib
 from ._lib import (CONTOUR_RAY, FLAG_AUTOTUNE, FLAG_CHECK_FINITE, FLAG_ZERO_PAD2, FP64, MIXED,  # noqa: F401
-                   TRUNC_TENSOR, TRUNC_TOTAL, CfftError, Plan, cfft_backward, cfft_fill, cfft_lookup,
+                   TRUNC_TENSOR, TRUNC_TOTAL, CfftError, Plan, cfft_backward, cfft_fill, cfft_fill_backward, cfft_lookup,
                    cfft_lookup_backward, cfft_lookup_quadratic, cfft_lookup_quadratic_backward, cfft_tabulate,
                    mbf_spectra, slab_green_eval)
 
 _lib.load()
 
-__all__ = ["Tabulator", "Plan", "CfftError", "TableFunction", "LookupFunction", "FP64", "MIXED",
+__all__ = ["Tabulator", "Plan", "CfftError", "TableFunction", "LookupFunction", "FillFunction", "FP64", "MIXED",
            "slab_green_eval", "mbf_spectra", "cfft_tabulate", "cfft_lookup", "cfft_lookup_quadratic",
-           "cfft_fill", "cfft_lookup_backward", "cfft_lookup_quadratic_backward", "cfft_backward",
+           "cfft_fill", "cfft_fill_backward", "cfft_lookup_backward", "cfft_lookup_quadratic_backward", "cfft_backward",
            "displacement_axis"]
 
 
@@ -147,6 +147,28 @@ class TableFunction(torch.autograd.Function):
         grad_q = torch.empty_like(q)
         cfft_backward(tab.plan, grid, gz, e, tan_delta, hh, tab.basis, q, pairs, g, spec, grad_sub, grad_q)
         return grad_sub[0], grad_sub[1], grad_q, None, None, None, None
+
+
+class FillFunction(torch.autograd.Function):
+    """Reduced-matrix fill of an element layout with its scatter-add adjoint
+    (entries the fill does not write are zero here)."""
+
+    @staticmethod
+    def forward(ctx, z, pos, tab: Tabulator, pairs, nmbf: int, order: int = 2, grid: int = 0):
+        am = pos.shape[0] * nmbf
+        out = torch.zeros((am, am), dtype=torch.complex128, device=z.device)
+        tab.fill(z, pairs, nmbf, pos, order=order, grid=grid, out=out)
+        ctx.save_for_backward(pos)
+        ctx.meta = (tab, list(pairs), nmbf, order, grid, z.shape)
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        (pos,) = ctx.saved_tensors
+        tab, pairs, nmbf, order, grid, shape = ctx.meta
+        dz = torch.zeros(shape, dtype=torch.complex128, device=gout.device)
+        cfft_fill_backward(tab.plan, grid, gout.contiguous().to(torch.complex128), pairs, nmbf, pos, order, dz)
+        return dz, None, None, None, None, None, None
 
 
 class LookupFunction(torch.autograd.Function):

@@ -27,7 +27,7 @@ FLAG_AUTOTUNE = 2
 FLAG_ZERO_PAD2 = 4
 
 ENTRY_POINTS = ("c_fft_plan", "c_fft_plan_destroy", "slab_green_eval", "mbf_spectra", "cfft_tabulate",
-                "cfft_lookup", "cfft_lookup_quadratic", "cfft_fill", "cfft_lookup_backward",
+                "cfft_lookup", "cfft_lookup_quadratic", "cfft_fill", "cfft_fill_backward", "cfft_lookup_backward",
                 "cfft_lookup_quadratic_backward", "cfft_backward", "cfft_profile",
                 "cfft_profile_read",
                 "cfft_last_error", "cfft_version")
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
     lib.cfft_lookup.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_lookup_quadratic.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_fill.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int32), i32, i32, vp, i32, i32, vp, vp]
+    lib.cfft_fill_backward.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int32), i32, i32, vp, i32, i32, vp, vp]
     lib.cfft_lookup_backward.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_lookup_quadratic_backward.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_backward.argtypes = [vp, i32, vp, dbl, dbl, dbl, ctypes.POINTER(Basis), i32, vp, i32,
@@ -186,6 +187,12 @@ def cfft_fill(plan: Plan, grid: int, z, pairs, nmbf: int, pos, order: int, out, 
     pa = pairs_array(pairs)
     check(load().cfft_fill(plan.handle, grid, _ptr(z), pa, len(pa) // 2, int(nmbf), _ptr(pos), int(pos.shape[0]),
                            int(order), _ptr(out), _stream(stream)))
+
+
+def cfft_fill_backward(plan: Plan, grid: int, dout, pairs, nmbf: int, pos, order: int, dz, stream=None):
+    pa = pairs_array(pairs)
+    check(load().cfft_fill_backward(plan.handle, grid, _ptr(dout), pa, len(pa) // 2, int(nmbf), _ptr(pos),
+                                    int(pos.shape[0]), int(order), _ptr(dz), _stream(stream)))
 
 
 def cfft_lookup_backward(plan: Plan, grid: int, dout, npairs: int, pts, dz, stream=None):

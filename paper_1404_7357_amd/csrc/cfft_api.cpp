@@ -859,12 +859,13 @@ cfft_status_t cfft_lookup(cfft_plan_t plan, int32_t grid, const void* z, int32_t
   return lookup_common(plan, grid, z, npairs, pts, npts, out, stream, false);
 }
 
-cfft_status_t cfft_fill(cfft_plan_t plan, int32_t grid, const void* z, const int32_t* pairs, int32_t npairs,
-                        int32_t nmbf, const double* pos, int32_t nelem, int32_t order, void* out, void* stream) {
+static cfft_status_t fill_common(cfft_plan_t plan, int32_t grid, const void* z, const int32_t* pairs, int32_t npairs,
+                                 int32_t nmbf, const double* pos, int32_t nelem, int32_t order, void* out,
+                                 const void* dout, void* stream) {
   g_last_error.clear();
   cfft_status_t st = check_plan(plan, grid);
   if (st != CFFT_OK) return st;
-  if (!z || !pos || !out) return fail(CFFT_ERR_INVALID_ARG, "z, pos or out is NULL");
+  if (!pos || !out || (!dout && !z)) return fail(CFFT_ERR_INVALID_ARG, "a table, pos or output pointer is NULL");
   if (nmbf < 1 || nmbf > kFillMaxMbf) return fail(CFFT_ERR_INVALID_ARG, "nmbf %d outside [1, %d]", nmbf, kFillMaxMbf);
   if (order != 1 && order != 2) return fail(CFFT_ERR_INVALID_ARG, "order %d is not 1 or 2", order);
   if (nelem < 1 || (long long)nelem * nmbf > 65535)
@@ -878,15 +879,36 @@ cfft_status_t cfft_fill(cfft_plan_t plan, int32_t grid, const void* z, const int
     if (v >= 0) return fail(CFFT_ERR_INVALID_ARG, "pair (%d, %d) listed twice", pairs[2 * k], pairs[2 * k + 1]);
     v = (short)k;
   }
-  if (nelem == 1) return CFFT_OK;   // only the self block, which is not written
   GridState& gs = plan->grids[grid];
+  if (dout && gs.d.precision != CFFT_FP64) return fail(CFFT_ERR_UNSUPPORTED, "the fill adjoint needs an FP64 grid");
+  if (nelem == 1) return CFFT_OK;   // only the self block, which is not written
   hipError_t e;
   {
     ProfScope ps(plan, 4, (hipStream_t)stream);
-    e = launch_fill(pass_params(gs), z, slot, nmbf, pos, nelem, order, (double2*)out, (hipStream_t)stream);
+    e = launch_fill(pass_params(gs), z, slot, nmbf, pos, nelem, order, (double2*)out, (const double2*)dout,
+                    (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(e, "fill launch");
   return CFFT_OK;
+}
+
+cfft_status_t cfft_fill(cfft_plan_t plan, int32_t grid, const void* z, const int32_t* pairs, int32_t npairs,
+                        int32_t nmbf, const double* pos, int32_t nelem, int32_t order, void* out, void* stream) {
+  if (!z) {
+    g_last_error.clear();
+    return fail(CFFT_ERR_INVALID_ARG, "z is NULL");
+  }
+  return fill_common(plan, grid, z, pairs, npairs, nmbf, pos, nelem, order, out, nullptr, stream);
+}
+
+cfft_status_t cfft_fill_backward(cfft_plan_t plan, int32_t grid, const void* dout, const int32_t* pairs,
+                                 int32_t npairs, int32_t nmbf, const double* pos, int32_t nelem, int32_t order,
+                                 void* dz, void* stream) {
+  if (!dout) {
+    g_last_error.clear();
+    return fail(CFFT_ERR_INVALID_ARG, "dout is NULL");
+  }
+  return fill_common(plan, grid, nullptr, pairs, npairs, nmbf, pos, nelem, order, dz, dout, stream);
 }
 
 static cfft_status_t lookup_backward_common(cfft_plan_t plan, int32_t grid, const void* dout, int32_t npairs,

@@ -112,8 +112,9 @@ hipError_t launch_lookup_quadratic(const PassParams& p, const void* z, int npair
                                   int npts, double2* out, hipStream_t s);
 // Reduced-matrix fill; slot[m * kFillMaxMbf + n] = pair index of (m, n) or -1.
 constexpr int kFillMaxMbf = 16;
+// dout != nullptr: the adjoint, accumulating into the FP64 table gradient `out`.
 hipError_t launch_fill(const PassParams& p, const void* z, const short* slot, int nmbf, const double* pos,
-                       int nelem, int order, double2* out, hipStream_t s);
+                       int nelem, int order, double2* out, const double2* dout, hipStream_t s);
 hipError_t launch_lookup_backward(const PassParams& p, const double2* dout, int npairs,
                                   const double* pts, int npts, double2* dz, bool quadratic, hipStream_t s);
 

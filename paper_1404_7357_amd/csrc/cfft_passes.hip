@@ -1186,8 +1186,54 @@ __global__ __launch_bounds__(256) void fill_kernel(FillArgs a) {
   a.out[(size_t)r * am + c] = v;
 }
 
+// Adjoint of the fill: every written entry scatters dout[r][c] with its
+// interpolation weights into the table of its pair (FP64 tables).
+template <int ORDER>
+__global__ __launch_bounds__(256) void fill_backward_kernel(FillArgs a, const double2* __restrict__ dout, double2* dz) {
+  const int am = a.nelem * a.nmbf;
+  const int r = blockIdx.x / a.ncb;
+  const int c = (blockIdx.x - r * a.ncb) * 256 + threadIdx.x;
+  if (c >= am) return;
+  const int i = r / a.nmbf, m = r - i * a.nmbf;
+  const int j = c / a.nmbf, n = c - j * a.nmbf;
+  if (i == j) return;
+  const int p = a.slot[m * kFillMaxMbf + n];
+  if (p < 0) return;
+  const double ux = (a.pos[2 * i] - a.pos[2 * j] - a.x0) / a.ddx;
+  const double uy = (a.pos[2 * i + 1] - a.pos[2 * j + 1] - a.y0) / a.ddy;
+  const double2 g = dout[(size_t)r * am + c];
+  double* d = (double*)dz + 2 * (size_t)p * a.nx * a.ny;
+  int c1, c2;
+  double tx, ty;
+  if (ORDER == 1) {
+    if (!cell_at(ux, uy, a.nx, a.ny, c1, c2, tx, ty)) return;
+    const double w[4] = {(1 - tx) * (1 - ty), tx * (1 - ty), (1 - tx) * ty, tx * ty};
+    const size_t id[4] = {(size_t)c2 * a.nx + c1, (size_t)c2 * a.nx + c1 + 1, (size_t)(c2 + 1) * a.nx + c1,
+                          (size_t)(c2 + 1) * a.nx + c1 + 1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      atomicAdd(d + 2 * id[k], w[k] * g.x);
+      atomicAdd(d + 2 * id[k] + 1, w[k] * g.y);
+    }
+  } else {
+    if (!stencil_at(ux, uy, a.nx, a.ny, c1, c2, tx, ty)) return;
+    double wx[3], wy[3];
+    lagrange3(tx, wx);
+    lagrange3(ty, wy);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const size_t id = (size_t)(c2 + b - 1) * a.nx + (c1 + k - 1);
+        atomicAdd(d + 2 * id, wy[b] * wx[k] * g.x);
+        atomicAdd(d + 2 * id + 1, wy[b] * wx[k] * g.y);
+      }
+    }
+  }
+}
+
 hipError_t launch_fill(const PassParams& p, const void* z, const short* slot, int nmbf, const double* pos, int nelem,
-                       int order, double2* out, hipStream_t s) {
+                       int order, double2* out, const double2* dout, hipStream_t s) {
   FillArgs a;
   a.z = z;
   a.pos = pos;
@@ -1205,6 +1251,13 @@ hipError_t launch_fill(const PassParams& p, const void* z, const short* slot, in
   a.ddy = p.y.dd;
   for (int k = 0; k < kFillMaxMbf * kFillMaxMbf; ++k) a.slot[k] = slot[k];
   const dim3 grid((unsigned)((long long)am * a.ncb));
+  if (dout != nullptr) {   // adjoint: out is the table gradient dz
+    if (order == 1)
+      hipLaunchKernelGGL(fill_backward_kernel<1>, grid, dim3(256), 0, s, a, dout, out);
+    else
+      hipLaunchKernelGGL(fill_backward_kernel<2>, grid, dim3(256), 0, s, a, dout, out);
+    return hipGetLastError();
+  }
   if (order == 1)
     hipLaunchKernelGGL(fill_kernel<1>, grid, dim3(256), 0, s, a);
   else

@@ -116,6 +116,7 @@ def test_every_entry_point_rejects_a_null_plan():
         "cfft_lookup": lambda: lib.cfft_lookup(None, 0, nul, 1, nul, 1, nul, None),
         "cfft_lookup_quadratic": lambda: lib.cfft_lookup_quadratic(None, 0, nul, 1, nul, 1, nul, None),
         "cfft_fill": lambda: lib.cfft_fill(None, 0, nul, pairs, 1, 1, nul, 2, 2, nul, None),
+        "cfft_fill_backward": lambda: lib.cfft_fill_backward(None, 0, nul, pairs, 1, 1, nul, 2, 2, nul, None),
         "cfft_lookup_backward": lambda: lib.cfft_lookup_backward(None, 0, nul, 1, nul, 1, nul, None),
         "cfft_backward": lambda: lib.cfft_backward(None, 0, nul, 2.2, 0.0, 0.05, basis, 1, nul, 1, pairs, 1, nul, nul,
                                                    nul, nul, None),

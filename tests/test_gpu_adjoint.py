@@ -226,3 +226,73 @@ def test_refined_second_order_gradient_vs_oracle_and_differences():
         return _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt, need_grad=False, order=2, **kw)[0]
     fd_h = (L(h=sub.h + step) - L(h=sub.h - step)) / (2 * step)
     assert abs(dh - fd_h) < 1e-6 * abs(fd_h), (dh, fd_h)
+
+
+def test_fill_adjoint_is_the_transpose():
+    """<dout, F z> = <F^T dout, z> for the reduced-matrix fill F, orders 1 and
+    2, with self blocks, unlisted pairs and displacements outside the table."""
+    _say("fill adjoint identity")
+    from paper_1404_7357_amd import Tabulator, cfft_fill_backward
+    rng = np.random.default_rng(71)
+    grid = Grid(64, 32, 8 * K0, 6 * K0, K0)
+    tab = Tabulator(grid, rooftop_lattice(1, 1), 3)
+    pairs = [(0, 0), (0, 2), (1, 1), (2, 1)]
+    z = torch.tensor(rng.standard_normal((4, 32, 64)) + 1j * rng.standard_normal((4, 32, 64)), device="cuda")
+    pos = torch.tensor(rng.uniform([-1.1, -0.75], [1.1, 0.75], (23, 2)), device="cuda")
+    am = 23 * 3
+    for order in (1, 2):
+        fz = torch.zeros((am, am), dtype=torch.complex128, device="cuda")
+        tab.fill(z, pairs, 3, pos, order=order, out=fz)
+        dout = torch.tensor(rng.standard_normal((am, am)) + 1j * rng.standard_normal((am, am)), device="cuda")
+        outside = torch.isnan(fz)
+        assert 0 < int(outside.sum().item()) < am * am // 4
+        fz[outside] = 0
+        dz = torch.zeros_like(z)
+        cfft_fill_backward(tab.plan, 0, dout, pairs, 3, pos, order, dz)
+        torch.cuda.synchronize()
+        lhs = torch.sum(torch.conj(dout) * fz).item()
+        rhs = torch.sum(torch.conj(dz) * z).item()
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs), (order, lhs, rhs)
+    tab.close()
+
+
+def test_fill_loss_gradient_vs_oracle():
+    """A loss over the reduced matrix of a layout filled from a refined table
+    (second-order interpolation): its gradient equals the oracle's gradient
+    of the same loss written as lookups at the layout's displacements."""
+    import dataclasses
+    _say("fill loss gradient vs oracle")
+    from paper_1404_7357_amd import FLAG_ZERO_PAD2, FillFunction, TableFunction, Tabulator
+    rng = np.random.default_rng(73)
+    base = Grid(32, 32, 6 * K0, 6 * K0, K0)
+    grid = dataclasses.replace(base, nx=64, ny=64, kx_max=12 * K0, ky_max=12 * K0, zero_pad=1)
+    sub = Substrate(2.2, 0.0, 0.05)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 0), (0, 1), (1, 1)]
+    nel, nmbf = 5, 2
+    lay = rng.uniform(-0.35, 0.35, (nel, 2))
+    ii, jj = np.nonzero(~np.eye(nel, dtype=bool))
+    target = rng.standard_normal((len(pairs), len(ii))) + 1j * rng.standard_normal((len(pairs), len(ii)))
+    tmat = np.zeros((nel * nmbf, nel * nmbf), dtype=np.complex128)
+    for p, (m, n) in enumerate(pairs):
+        tmat[ii * nmbf + m, jj * nmbf + n] = target[p] * 1e-9
+    tab = Tabulator(grid, basis, max_mbf=2, flags=FLAG_ZERO_PAD2)
+    e = torch.tensor(sub.eps_r, dtype=torch.float64, device="cuda", requires_grad=True)
+    hh = torch.tensor(sub.h, dtype=torch.float64, device="cuda", requires_grad=True)
+    qq = torch.tensor(q, device="cuda", requires_grad=True)
+    z = TableFunction.apply(e, hh, qq, tab, sub.tan_delta, pairs, 0)
+    mat = FillFunction.apply(z, torch.tensor(lay, device="cuda"), tab, pairs, nmbf, 2, 0)
+    written = torch.zeros_like(mat, dtype=torch.bool)
+    for m, n in pairs:
+        written[torch.tensor(ii * nmbf + m), torch.tensor(jj * nmbf + n)] = True
+    loss = ((mat - torch.tensor(tmat, device="cuda")).abs().pow(2) * written).sum()
+    loss.backward()
+    de, dh, dq = float(e.grad.item()), float(hh.grad.item()), qq.grad.cpu().numpy()
+    tab.close()
+    pts = lay[ii] - lay[jj]
+    o_loss, o_de, o_dh, o_dq = co.loss_gradient(grid, sub, basis, q, np.array(pairs), pts, target * 1e-9, order=2)
+    assert abs(float(loss.item()) - o_loss) < 1e-9 * abs(o_loss)
+    assert abs(de - o_de) < 1e-9 * abs(o_de), (de, o_de)
+    assert abs(dh - o_dh) < 1e-9 * abs(o_dh), (dh, o_dh)
+    assert np.abs(dq - o_dq).max() < 1e-9 * np.abs(o_dq).max()
