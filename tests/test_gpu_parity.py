@@ -491,6 +491,65 @@ def test_zero_padded_kernels_and_variants(nx, ny, variant):
         assert err < tol, (variant, nx, ny, prec, err)
 
 
+def test_paper_pair_count_on_a_zero_padded_grid():
+    """The paper's pair count (M = 9, 81 pairs: two launches of at most 64
+    pairs, nine pairs per testing MBF, so groups of two in the row pass) on a
+    zero-padded grid, FP64 and mixed, at sampled outputs."""
+    from paper_1404_7357_amd import FLAG_ZERO_PAD2
+    rng = np.random.default_rng(89)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 9, basis.shape[0])
+    pairs = [(m, n) for m in range(9) for n in range(9)]
+    sub = Substrate(2.2, 0.0, 0.031)
+    idx = _sample_idx(128, 128, 40, 89)
+    for prec, tol in [(FP64, 1e-10), (MIXED, 1e-5)]:
+        grid = Grid(128, 128, 14 * K0, 14 * K0, K0, precision=prec, zero_pad=1)
+        _say(f"81 pairs zero-padded 128x128 prec={prec}")
+        tab = _tab(grid, basis, 9, FLAG_ZERO_PAD2)
+        qd = torch.tensor(q, device="cuda")
+        z = tab.tabulate(tab.spectra(qd), tab.green(sub.eps_r, sub.tan_delta, sub.h), pairs).cpu().numpy()
+        tab.close()
+        ref = co.tabulate(grid, sub, basis, q, np.asarray(pairs), out_idx=idx, workers=8)
+        got = z.reshape(len(pairs), -1)[:, idx]
+        err = (np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
+        assert err < tol, (prec, err)
+
+
+def test_fill_at_the_paper_layout_size():
+    """The 25 x 25 array at 0.58 lambda0 filled from a 2048^2 table (the
+    paper's FFT size) of given values, 9 pairs: sampled matrix entries
+    against the oracle's second-order lookup at their displacements; the
+    self blocks stay untouched."""
+    from paper_1404_7357_amd import Tabulator
+    from workloads import paper_array_2048
+    rng = np.random.default_rng(91)
+    wl = paper_array_2048()
+    grid = wl.grids[0]
+    nmbf, pairs = 3, [(m, n) for m in range(3) for n in range(3)]
+    _say("fill 25 x 25 layout from a 2048^2 table")
+    tab = Tabulator(grid, rooftop_lattice(1, 1), nmbf)
+    zh = (rng.standard_normal((9, grid.ny, grid.nx)) + 1j * rng.standard_normal((9, grid.ny, grid.nx)))
+    z = torch.tensor(zh, device="cuda")
+    pos = wl.layout
+    am = pos.shape[0] * nmbf
+    out = torch.full((am, am), complex(7.0, -7.0), dtype=torch.complex128, device="cuda")
+    tab.fill(z, pairs, nmbf, torch.tensor(pos, device="cuda"), order=2, out=out)
+    torch.cuda.synchronize()
+    tab.close()
+    rows = rng.integers(0, am, 400)
+    cols = rng.integers(0, am, 400)
+    got = out[torch.tensor(rows, device="cuda"), torch.tensor(cols, device="cuda")].cpu().numpy()
+    i, m = rows // nmbf, rows % nmbf
+    j, n = cols // nmbf, cols % nmbf
+    self_blk = i == j
+    assert np.all(got[self_blk] == complex(7.0, -7.0))
+    keep = ~self_blk
+    d = pos[i[keep]] - pos[j[keep]]
+    ref_all = co.quadratic_lookup(grid, zh, d)                   # [9 pairs][points]
+    ref = ref_all[(m[keep] * nmbf + n[keep]), np.arange(int(keep.sum()))]
+    assert np.abs(got[keep] - ref).max() < 1e-13 * np.abs(ref).max()
+
+
 def test_zero_padded_refinement_and_quadratic_lookup():
     """x2 zero-padded grid (Whittaker-Shannon refinement): the refined table
     vs the oracle's, its even nodes vs the unrefined GPU table, and the
