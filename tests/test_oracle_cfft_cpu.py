@@ -19,7 +19,7 @@ def test_term_sets():
     assert set(cfft_cpu.terms(2)) <= set(cfft_cpu.terms(2, TRUNC_TENSOR))
 
 
-@pytest.mark.parametrize("variant", ["ray", "parabolic", "tensor"])
+@pytest.mark.parametrize("variant", ["ray", "parabolic", "tensor", "zero_padded"])
 @pytest.mark.parametrize("order", [0, 2, 3])
 def test_matches_direct_sum(variant, order):
     rng = np.random.default_rng(10 + order)
@@ -28,6 +28,8 @@ def test_matches_direct_sum(variant, order):
         grid = dataclasses.replace(grid, contour=CONTOUR_PARABOLIC, beta_end=3.5 * K0)
     elif variant == "tensor":
         grid = dataclasses.replace(grid, truncation=TRUNC_TENSOR)
+    elif variant == "zero_padded":
+        grid = dataclasses.replace(grid, nx=64, ny=32, kx_max=14 * K0, ky_max=10 * K0, zero_pad=1)
     sub = Substrate(4.4, 0.002, 0.06)
     basis = rooftop_lattice(2, 2)
     q = gaussian_coefficients(rng, 2, basis.shape[0])
