@@ -77,7 +77,7 @@ class Step:
         gd = self.grid
         dt = torch.complex128 if gd.precision == 0 else torch.complex64
         self.g = torch.empty((3, gd.ny, gd.nx), dtype=torch.complex128, device="cuda")
-        self.spec = torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=torch.complex128, device="cuda")
+        self.spec = torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=dt, device="cuda")
         self.z = torch.empty((len(self.pairs), gd.ny, gd.nx), dtype=dt, device="cuda")
         self._lib = _lib
 
@@ -427,7 +427,7 @@ def _sweep(torch, steps, warmup):
     bufs = []
     for gd in wl.grids:
         bufs.append((torch.empty((3, gd.ny, gd.nx), dtype=torch.complex128, device="cuda"),
-                     torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=torch.complex128, device="cuda"),
+                     torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=torch.complex64, device="cuda"),
                      torch.empty((len(pairs), gd.ny, gd.nx), dtype=torch.complex64, device="cuda")))
 
     def calls():

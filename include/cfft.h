@@ -151,11 +151,13 @@ cfft_status_t c_fft_plan_destroy(cfft_plan_t plan);
 cfft_status_t slab_green_eval(cfft_plan_t plan, int32_t grid, double eps_r, double tan_delta,
                               double h, void* g, void* stream);
 
-/* Spectra of the MBFs on the contour (eq. FTMBF), FP64.
+/* Spectra of the MBFs on the contour (eq. FTMBF), evaluated in FP64 and
+ * stored in the grid's precision: complex128 for CFFT_FP64, complex64
+ * (rounded) for CFFT_MIXED.
  *   basis : host, nbasis records (read during the call; the geometry is
  *           uploaded to plan-owned device memory, blocking, and cached)
  *   q     : device, complex128 [nmbf][nbasis], row m = coefficients of MBF m
- *   spec  : device, complex128 [nmbf][4][ny][nx]:
+ *   spec  : device, complex128 or complex64 [nmbf][4][ny][nx]:
  *           [0] Mx_m(k_c) = sum_j conj(q_mj) Fx_j(k_c)    (testing side)
  *           [1] My_m(k_c)
  *           [2] Mx#_m(k_c) = sum_j q_mj Fx_j(-k_c)        (basis side: analytic
@@ -169,7 +171,7 @@ cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* ba
  * (ray contour; (P+1)(P+2)/2 on the parabolic contour) with partial
  * recombination, P+1 column FFTs per column with the per-output
  * recombination and the Appendix scaling.
- *   spec  : device, output of mbf_spectra for nmbf MBFs
+ *   spec  : device, output of mbf_spectra for nmbf MBFs (the grid's precision)
  *   g     : device, output of slab_green_eval
  *   pairs : host, int32 [npairs][2] = (m, n), 0 <= m, n < nmbf (testing m, basis n)
  *   z     : device [npairs][ny][nx], complex128 (FP64) or complex64 (MIXED);

@@ -7,7 +7,7 @@ Importing the package fails loudly when the library is not built.
     from paper_1404_7357_amd import Tabulator
     tab = Tabulator(grid, basis, max_mbf=4)
     g = tab.green(eps_r, tan_delta, h)          # [3][ny][nx] complex128
-    spec = tab.spectra(q)                       # [M][4][ny][nx] complex128
+    spec = tab.spectra(q)                       # [M][4][ny][nx] complex128 (complex64 for mixed grids)
     z = tab.tabulate(spec, g, pairs)            # [npairs][ny][nx]
     vals = tab.lookup(z, pts)                   # [npairs][Q] complex128
 """
@@ -69,9 +69,9 @@ class Tabulator:
         q = q.contiguous()
         if q.dtype != torch.complex128 or q.shape[1] != self.nbasis:
             raise ValueError("q must be complex128 [M][nbasis]")
-        spec = out if out is not None else torch.empty((q.shape[0], 4, gd.ny, gd.nx), dtype=torch.complex128,
-                                                       device=self.device)
-        _check_buffer(spec, (q.shape[0], 4, gd.ny, gd.nx), torch.complex128, "out")
+        sdt = torch.complex128 if gd.precision == FP64 else torch.complex64
+        spec = out if out is not None else torch.empty((q.shape[0], 4, gd.ny, gd.nx), dtype=sdt, device=self.device)
+        _check_buffer(spec, (q.shape[0], 4, gd.ny, gd.nx), sdt, "out")
         mbf_spectra(self.plan, grid, self.basis, q, spec, stream)
         return spec
 
@@ -81,7 +81,7 @@ class Tabulator:
         z = out if out is not None else torch.empty((len(pairs), gd.ny, gd.nx), dtype=dt, device=self.device)
         _check_buffer(z, (len(pairs), gd.ny, gd.nx), dt, "out")
         _check_buffer(g, (3, gd.ny, gd.nx), torch.complex128, "g")
-        _check_buffer(spec, (spec.shape[0], 4, gd.ny, gd.nx), torch.complex128, "spec")
+        _check_buffer(spec, (spec.shape[0], 4, gd.ny, gd.nx), dt, "spec")
         cfft_tabulate(self.plan, grid, spec, spec.shape[0], g, pairs, z, stream)
         return z
 

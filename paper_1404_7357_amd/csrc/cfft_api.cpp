@@ -662,18 +662,18 @@ cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* ba
     if (st != CFFT_OK) return st;
     const Contour c{gs.d.gamma, 1, gs.d.beta_end};
     ProfScope ps(plan, 1, s);
-    e = launch_spectra_direct(gs.x, gs.y, c, plan->geo_dev, (const double2*)q, nmbf, (double2*)plan->ws3,
-                              (double2*)spec, s);
+    e = launch_spectra_direct(gs.x, gs.y, c, plan->geo_dev, (const double2*)q, nmbf, (double2*)plan->ws3, spec,
+                              gs.d.precision, s);
   } else {
     st = ensure_ws(&plan->ws3, &plan->ws3_bytes, sizeof(double2) * spectra_scratch_len(gs.y, plan->geo_dev, nmbf),
                    "spectra scratch");
     if (st != CFFT_OK) return st;
     ProfScope ps(plan, 1, s);
     e = launch_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, (const double2*)q, nmbf, (double2*)plan->ws3,
-                       (double2*)spec, s);
+                       spec, gs.d.precision, s);
   }
   if (e != hipSuccess) return hip_fail(e, "mbf_spectra launch");
-  return check_finite(plan, spec, (size_t)8 * nmbf * gs.x.n * gs.y.n, false, s);
+  return check_finite(plan, spec, (size_t)8 * nmbf * gs.x.n * gs.y.n, gs.d.precision != CFFT_FP64, s);
 }
 
 cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, int32_t nmbf, const void* g,
@@ -733,7 +733,7 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
       hipError_t e;
       {
         ProfScope ps(plan, 2, st2);
-        e = launch_row_pass(pp, (const double2*)g, (const double2*)spec, pm.data() + p0, pn.data() + p0, np, wsl,
+        e = launch_row_pass(pp, (const double2*)g, spec, pm.data() + p0, pn.data() + p0, np, wsl,
                             twx, st2);
       }
       if (e != hipSuccess) return e;

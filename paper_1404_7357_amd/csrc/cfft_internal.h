@@ -91,16 +91,17 @@ hipError_t launch_spectra_tables(const Axis& x, const Axis& y, double gamma, con
 size_t spectra_tables_len(const Axis& x, const Axis& y, const GeomDevice& geo);
 hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
                           const double2* utab, const double2* q, int nmbf, double2* scratch,
-                          double2* spec, hipStream_t s);
+                          void* spec, int precision, hipStream_t s);
 // Spectra on the parabolic contour (no per-axis separation): per sample.
 hipError_t launch_spectra_direct(const Axis& x, const Axis& y, const Contour& c, const GeomDevice& geo,
-                                 const double2* q, int nmbf, double2* scratch, double2* spec, hipStream_t s);
+                                 const double2* q, int nmbf, double2* scratch, void* spec, int precision,
+                                 hipStream_t s);
 size_t spectra_direct_scratch_len(const GeomDevice& geo, int nmbf);
 size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf);
 size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf);
 
 // Row + column passes for one chunk of <= kMaxPairsPerLaunch pairs.
-hipError_t launch_row_pass(const PassParams& p, const double2* g, const double2* spec,
+hipError_t launch_row_pass(const PassParams& p, const double2* g, const void* spec,
                            const int* pm, const int* pn, int npairs, void* inter,
                            const void* twx, hipStream_t s);
 hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, void* z,

@@ -110,7 +110,7 @@ struct RowArgs {
   int parabolic;                // per-sample contour ratio (see row_terms_general)
   double ky0, dky, beta_end;
   const double2* g;
-  const double2* spec;
+  const void* spec;   // V elements: complex128 (FP64 grids) or complex64 (mixed)
   void* inter;
   const void* tw;
   int nx, ny, order, npairs;
@@ -212,10 +212,11 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) r
     if (valid && (!a.band || in_band(n1, N))) {
       const size_t idx = (size_t)n2 * N + n1;
       const double2 gxx = a.g[idx], gxy = a.g[plane + idx], gyy = a.g[2 * plane + idx];
-      const double2 mx = a.spec[((size_t)m * 4 + 0) * plane + idx];
-      const double2 my = a.spec[((size_t)m * 4 + 1) * plane + idx];
-      const double2 mxh = a.spec[((size_t)n * 4 + 2) * plane + idx];
-      const double2 myh = a.spec[((size_t)n * 4 + 3) * plane + idx];
+      const V* sp = (const V*)a.spec;
+      const double2 mx = to_d(sp[((size_t)m * 4 + 0) * plane + idx]);
+      const double2 my = to_d(sp[((size_t)m * 4 + 1) * plane + idx]);
+      const double2 mxh = to_d(sp[((size_t)n * 4 + 2) * plane + idx]);
+      const double2 myh = to_d(sp[((size_t)n * 4 + 3) * plane + idx]);
       h = cadd(cmul(mx, cadd(cmul(gxx, mxh), cmul(gxy, myh))), cmul(my, cadd(cmul(gxy, mxh), cmul(gyy, myh))));
       if (n1 & 1) h = make_double2(-h.x, -h.y);
       if (a.parabolic) h = cmul(h, contour_weight(a, a.kx0 + n1 * a.dkx, a.ky0 + n2 * a.dky));
@@ -275,7 +276,7 @@ struct RowGArgs {
   int parabolic;
   double ky0, dky, beta_end;
   const double2* g;
-  const double2* spec;
+  const void* spec;   // V elements
   void* inter;
   const void* tw;
   int nx, ny, order, ngroups;
@@ -317,8 +318,8 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pa
       continue;
     }
     const double2 gxx = a.g[row + i], gxy = a.g[plane + row + i], gyy = a.g[2 * plane + row + i];
-    const double2 mx = a.spec[((size_t)m * 4 + 0) * plane + row + i];
-    const double2 my = a.spec[((size_t)m * 4 + 1) * plane + row + i];
+    const double2 mx = to_d(((const V*)a.spec)[((size_t)m * 4 + 0) * plane + row + i]);
+    const double2 my = to_d(((const V*)a.spec)[((size_t)m * 4 + 1) * plane + row + i]);
     double2 vx = cfma(cmul(mx, gxx), my, gxy);
     double2 vy = cfma(cmul(mx, gxy), my, gyy);
     if (i & 1) {
@@ -346,8 +347,8 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pa
     const int n1 = t + T * r;
     double2 h = make_double2(0.0, 0.0);
     if (active && (!a.band || in_band(n1, N))) {
-      const double2 mxh = a.spec[((size_t)n * 4 + 2) * plane + row + n1];
-      const double2 myh = a.spec[((size_t)n * 4 + 3) * plane + row + n1];
+      const double2 mxh = to_d(((const V*)a.spec)[((size_t)n * 4 + 2) * plane + row + n1]);
+      const double2 myh = to_d(((const V*)a.spec)[((size_t)n * 4 + 3) * plane + row + n1]);
       h = cfma(cmul(ax[n1], mxh), ay[n1], myh);
     }
     f[r] = from_d<V>(h);
@@ -646,7 +647,7 @@ template <int N> static hipError_t row_fp32(const RowArgs& a, hipStream_t s) {
 template <int N> static hipError_t col_fp64(const ColArgs& a, hipStream_t s) { return col_launch<double2, N>(a, s); }
 template <int N> static hipError_t col_fp32(const ColArgs& a, hipStream_t s) { return col_launch<float2, N>(a, s); }
 
-hipError_t launch_row_pass(const PassParams& p, const double2* g, const double2* spec, const int* pm,
+hipError_t launch_row_pass(const PassParams& p, const double2* g, const void* spec, const int* pm,
                            const int* pn, int npairs, void* inter, const void* twx, hipStream_t s) {
   if (npairs < 1 || npairs > kMaxPairsPerLaunch) return hipErrorInvalidValue;
   RowArgs a;

@@ -193,10 +193,10 @@ spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ 
 //   M_m^c(n1, n2) = sum_{g of component c} sum_p (SX_g U_gp)(n1) w[n2][m][p].
 // A U value is loaded once and used for every row.  Padded centres use a
 // clamped U times a zero w.
-template <int RB>
+template <int RB, typename O>
 __device__ __forceinline__ void spectra_block(const GeomDevice& geo, const double2* __restrict__ utab, size_t rs,
                                               unsigned boff, const double2* const (&wrow)[RB], int v, int nmbf,
-                                              int mpad, int n1, int n2_0, int ny, double2* __restrict__ spec) {
+                                              int mpad, int n1, int n2_0, int ny, O* __restrict__ spec) {
   const int ppad = geo.ppad;
   const size_t plane = rs * (size_t)ny;
   for (int m0 = 0; m0 < mpad; m0 += kMChunk) {
@@ -237,7 +237,7 @@ __device__ __forceinline__ void spectra_block(const GeomDevice& geo, const doubl
 #pragma unroll
         for (int i = 0; i < kMChunk; ++i) {
           if (m0 + i < nmbf)
-            spec[((size_t)(m0 + i) * 4 + 2 * v + c) * plane + (size_t)(n2_0 + r) * rs + n1] = acc[r][i];
+            spec[((size_t)(m0 + i) * 4 + 2 * v + c) * plane + (size_t)(n2_0 + r) * rs + n1] = from_d<O>(acc[r][i]);
         }
       }
     }
@@ -247,10 +247,13 @@ __device__ __forceinline__ void spectra_block(const GeomDevice& geo, const doubl
 // w tables from spectra_rows_kernel; every thread of a block reads the same
 // entries (wave-uniform addresses, served by scalar loads).  Block =
 // kSpecThreads samples of kSpecRows rows and one variant v (blockIdx.z:
-// 0 = M with U and w, 1 = M# with U# and w#).
+// 0 = M with U and w, 1 = M# with U# and w#).  O is the stored type:
+// complex128 for FP64 grids, complex64 (rounded from the FP64 sums) for
+// mixed ones.
+template <typename O>
 __global__ void __launch_bounds__(kSpecThreads)
 spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
-               const double2* __restrict__ wtab, int nmbf, int mpad, double2* __restrict__ spec) {
+               const double2* __restrict__ wtab, int nmbf, int mpad, O* __restrict__ spec) {
   constexpr int RB = kSpecRows;
   const int n2_0 = blockIdx.y * RB;
   const int v = blockIdx.z;
@@ -259,8 +262,8 @@ spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
   const double2* wrow[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) wrow[r] = wtab + ((size_t)min(n2_0 + r, y.n - 1) * 2 + v) * mpad * geo.ppad;
-  spectra_block<RB>(geo, utab, (size_t)x.n, (unsigned)n1 * (unsigned)sizeof(double2), wrow, v, nmbf, mpad, n1, n2_0,
-                    y.n, spec);
+  spectra_block<RB, O>(geo, utab, (size_t)x.n, (unsigned)n1 * (unsigned)sizeof(double2), wrow, v, nmbf, mpad, n1,
+                       n2_0, y.n, spec);
 }
 
 size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf) {
@@ -275,7 +278,7 @@ size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf) {
 }
 
 hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo, const double2* utab,
-                          const double2* q, int nmbf, double2* scratch, double2* spec, hipStream_t s) {
+                          const double2* q, int nmbf, double2* scratch, void* spec, int precision, hipStream_t s) {
   (void)gamma;
   const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
   dim3 grid((x.n + kSpecThreads - 1) / kSpecThreads, (y.n + kSpecRows - 1) / kSpecRows, 2);
@@ -284,7 +287,12 @@ hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const Geom
                      dim3(kRowsThreads), 0, s, x, y, geo, utab, q, nmbf, mpad, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(spectra_kernel, grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf, mpad, spec);
+  if (precision == 0)
+    hipLaunchKernelGGL(spectra_kernel<double2>, grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf, mpad,
+                       (double2*)spec);
+  else
+    hipLaunchKernelGGL(spectra_kernel<float2>, grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf, mpad,
+                       (float2*)spec);
   return hipGetLastError();
 }
 
@@ -299,9 +307,10 @@ hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const Geom
 // thread per sample; the coefficients of a basis are the same for every
 // thread (wave-uniform loads); MBFs in chunks of kMChunk.
 constexpr int kDirectThreads = 256;
+template <typename O>
 __global__ void __launch_bounds__(kDirectThreads)
 spectra_direct_kernel(Axis x, Axis y, Contour cont, GeomDevice geo, const double2* __restrict__ q,
-                      const double2* __restrict__ qd, int nmbf, double2* __restrict__ spec) {
+                      const double2* __restrict__ qd, int nmbf, O* __restrict__ spec) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= x.n * y.n) return;
   const int n1 = idx % x.n, n2 = idx / x.n;
@@ -398,8 +407,8 @@ spectra_direct_kernel(Axis x, Axis y, Contour cont, GeomDevice geo, const double
 #pragma unroll
       for (int i = 0; i < kMChunk; ++i) {
         if (m0 + i < nmbf) {
-          spec[((size_t)(m0 + i) * 4 + c) * plane + o] = acc[i];
-          spec[((size_t)(m0 + i) * 4 + 2 + c) * plane + o] = acch[i];
+          spec[((size_t)(m0 + i) * 4 + c) * plane + o] = from_d<O>(acc[i]);
+          spec[((size_t)(m0 + i) * 4 + 2 + c) * plane + o] = from_d<O>(acch[i]);
         }
       }
     }
@@ -419,14 +428,19 @@ __global__ void gather_slots_kernel(GeomDevice geo, const double2* __restrict__ 
 size_t spectra_direct_scratch_len(const GeomDevice& geo, int nmbf) { return (size_t)nmbf * geo.total_idx; }
 
 hipError_t launch_spectra_direct(const Axis& x, const Axis& y, const Contour& c, const GeomDevice& geo,
-                                 const double2* q, int nmbf, double2* scratch, double2* spec, hipStream_t s) {
+                                 const double2* q, int nmbf, double2* scratch, void* spec, int precision,
+                                 hipStream_t s) {
   const int ng = nmbf * geo.total_idx;
   hipLaunchKernelGGL(gather_slots_kernel, dim3((ng + 255) / 256), dim3(256), 0, s, geo, q, nmbf, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = x.n * y.n;
-  hipLaunchKernelGGL(spectra_direct_kernel, dim3((n + kDirectThreads - 1) / kDirectThreads), dim3(kDirectThreads), 0,
-                     s, x, y, c, geo, q, scratch, nmbf, spec);
+  if (precision == 0)
+    hipLaunchKernelGGL(spectra_direct_kernel<double2>, dim3((n + kDirectThreads - 1) / kDirectThreads),
+                       dim3(kDirectThreads), 0, s, x, y, c, geo, q, scratch, nmbf, (double2*)spec);
+  else
+    hipLaunchKernelGGL(spectra_direct_kernel<float2>, dim3((n + kDirectThreads - 1) / kDirectThreads),
+                       dim3(kDirectThreads), 0, s, x, y, c, geo, q, scratch, nmbf, (float2*)spec);
   return hipGetLastError();
 }
 

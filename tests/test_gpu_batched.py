@@ -36,7 +36,7 @@ def _sweep_buffers(wl):
     for gd in wl.grids:
         dt = torch.complex128 if gd.precision == FP64 else torch.complex64
         bufs.append((torch.empty((3, gd.ny, gd.nx), dtype=torch.complex128, device="cuda"),
-                     torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=torch.complex128, device="cuda"),
+                     torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=dt, device="cuda"),
                      torch.empty((len(wl.pairs), gd.ny, gd.nx), dtype=dt, device="cuda")))
     return bufs
 
@@ -138,7 +138,8 @@ def test_large_table_sampled(prec):
     tab = Tabulator(gd, rooftop_lattice(1, 1), max_mbf=m)
     pairs = [(a, b) for a in range(m) for b in range(m)]
     _say(f"c4 table prec={prec}: gpu")
-    z = tab.tabulate(torch.tensor(spec.reshape(m, 4, n, n), device="cuda"),
+    sdt = torch.complex128 if prec == FP64 else torch.complex64
+    z = tab.tabulate(torch.tensor(spec.reshape(m, 4, n, n), device="cuda").to(sdt),
                      torch.tensor(g.reshape(3, n, n), device="cuda"), pairs)
     torch.cuda.synchronize()
     check = [0, 7, 20, 35]
