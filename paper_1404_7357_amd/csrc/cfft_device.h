@@ -306,7 +306,7 @@ __device__ __forceinline__ void stockham_stage(V (&x)[R], V* lds, const V* ltw, 
 // transform must be lanes of one wave, and only they synchronise.
 template <typename V, int N, int R, bool WAVE = false, int PS = 3>
 __device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* ltw, int t) {
-  static_assert(R == 8 || R == 16, "8 or 16 points per thread");
+  static_assert(R == 8 || R == 16 || R == 32, "8, 16 or 32 points per thread");
   static_assert(!WAVE || N / R <= 64, "a wave-local transform needs at most 64 threads");
   // Keep the twiddle addressing inside the caller's term loop: without this
   // the compiler hoists every stage's twiddle loads out of the loop and keeps

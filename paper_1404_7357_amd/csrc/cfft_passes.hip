@@ -23,6 +23,7 @@
 // recombination weight and accumulator is FP64.
 #include <algorithm>
 #include <map>
+#include <type_traits>
 #include <vector>
 
 #include "cfft_device.h"
@@ -80,6 +81,18 @@
 #endif
 #ifndef CFFT_COL_ROW_BYTES
 #define CFFT_COL_ROW_BYTES 64
+#endif
+
+// Points per thread of the FP32 column pass on columns of 4096 points, and
+// of the FP64 column pass on columns of 2048 and 4096 points.
+#ifndef CFFT_COL_R_F32_4096
+#define CFFT_COL_R_F32_4096 32
+#endif
+// (16 gives the FP64 columns four-column tiles too, but such a tile takes a
+// CU's whole LDS, so the column pass of one pair chunk can no longer overlap
+// the row pass of the next: slower on the 2048^2 zero-padded tables.)
+#ifndef CFFT_COL_R_F64_2048
+#define CFFT_COL_R_F64_2048 8
 #endif
 
 namespace cfft {
@@ -236,10 +249,14 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) r
 #pragma unroll
   for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
   for (int ao = 0; ao <= a.order; ++ao) {
+    // opaque copy of t: the per-point factors and store addresses are
+    // rebuilt per term instead of being hoisted and held across the loop
+    int tb = t;
+    asm volatile("" : "+v"(tb));
     if (ao > 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int n1 = t + T * r;
+        const int n1 = tb + T * r;
         f[r] = cscale(f[r], (Rl)(a.gamma * (a.kx0 + n1 * a.dkx)));
       }
     }
@@ -253,12 +270,12 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) r
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       // Dx(j1)^a / a!, rebuilt per term (cheaper than keeping it live)
-      const double dx = a.x0 + (t + T * r) * a.ddx;
+      const double dx = a.x0 + (tb + T * r) * a.ddx;
       double cf = 1.0;
       for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
-      if (valid && keep) dst[t + T * r] = from_d<V>(S[r]);
+      if (valid && keep) dst[tb + T * r] = from_d<V>(S[r]);
     }
   }
 }
@@ -365,10 +382,14 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pa
 #pragma unroll
   for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
   for (int ao = 0; ao <= a.order; ++ao) {
+    // opaque copy of t: the per-point factors and store addresses are
+    // rebuilt per term instead of being hoisted and held across the loop
+    int tb = t;
+    asm volatile("" : "+v"(tb));
     if (ao > 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int n1 = t + T * r;
+        const int n1 = tb + T * r;
         f[r] = cscale(f[r], (Rl)(a.gamma * (a.kx0 + n1 * a.dkx)));
       }
     }
@@ -381,12 +402,12 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pa
     V* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + n2) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const double dx = a.x0 + (t + T * r) * a.ddx;
+      const double dx = a.x0 + (tb + T * r) * a.ddx;
       double cf = 1.0;
       for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
-      if (active && keep) dst[t + T * r] = from_d<V>(S[r]);
+      if (active && keep) dst[tb + T * r] = from_d<V>(S[r]);
     }
   }
 }
@@ -406,9 +427,12 @@ struct ColArgs {
 };
 
 // Minimum waves per SIMD requested for the column pass (1: no constraint).
-template <typename V> constexpr int col_min_waves() {
-  return sizeof(V) == 8 ? (CFFT_COL_MIN_WAVES_F32 > 0 ? CFFT_COL_MIN_WAVES_F32 : 1)
-                        : (CFFT_COL_MIN_WAVES > 0 ? CFFT_COL_MIN_WAVES : 1);
+// 32-point tiles run one 512-thread block per CU (their LDS tile takes the
+// CU's LDS), two waves per SIMD.
+template <typename V, int R> constexpr int col_min_waves() {
+  return R == 32 ? 2
+         : sizeof(V) == 8 ? (CFFT_COL_MIN_WAVES_F32 > 0 ? CFFT_COL_MIN_WAVES_F32 : 1)
+                          : (CFFT_COL_MIN_WAVES > 0 ? CFFT_COL_MIN_WAVES : 1);
 }
 
 // Column-pass block shape.  Thread tid works on column c = tid % C of the
@@ -424,7 +448,7 @@ template <int N, int C, int R> struct ColCfg {
 };
 
 template <typename V, int N, int C, int R>
-__global__ void __launch_bounds__(C * (N / R), col_min_waves<V>()) col_pass_kernel(ColArgs a) {
+__global__ void __launch_bounds__(C * (N / R), (col_min_waves<V, R>())) col_pass_kernel(ColArgs a) {
   using Cfg = ColCfg<N, C, R>;
   constexpr int T = Cfg::T, LDP = Cfg::LDP;
   using Rl = typename real_of<V>::type;
@@ -442,38 +466,46 @@ __global__ void __launch_bounds__(C * (N / R), col_min_waves<V>()) col_pass_kern
   const int nsl = a.tensor ? 1 : a.order + 1;
   const V* col0 = (const V*)a.inter + (size_t)pair * nsl * plane + j1;
 
-  double2 Z[R];
+  // the recombination sums in FP64, except in the 16-point FP32 tiles, where
+  // FP64 accumulators would not fit the 128 registers of a 1024-thread block
+  using Acc = typename std::conditional<(R > 8), V, double2>::type;
+  using Ra = typename real_of<Acc>::type;
+  Acc Z[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) Z[r] = make_double2(0.0, 0.0);
+  for (int r = 0; r < R; ++r) Z[r] = from_d<Acc>(make_double2(0.0, 0.0));
   // term b reads S_{P-b}; the next term's column is fetched while this one
   // is transformed.  The weights s(n2)(gamma ky)^b and Dy^b/b! are rebuilt
   // per term (a few multiplies) rather than kept live in registers.
   // n2 = t + T r lies in the band [N/4, 3N/4) of a zero-padded grid exactly
   // when 2R/8 <= r < 6R/8; outside it the intermediates are zero (never
   // written by the row pass) and are not read
-  auto load_term = [&](const V* src, int r) -> V {
+  auto load_term = [&](const V* src, int r, int tt) -> V {
     if (a.band && (8 * r < 2 * R || 8 * r >= 6 * R)) return from_d<V>(make_double2(0.0, 0.0));
-    if constexpr (CFFT_COL_NT_LOAD) return load_nt(src + (size_t)(t + T * r) * a.nx);
-    return src[(size_t)(t + T * r) * a.nx];
+    if constexpr (CFFT_COL_NT_LOAD) return load_nt(src + (size_t)(tt + T * r) * a.nx);
+    return src[(size_t)(tt + T * r) * a.nx];
   };
   V nxt[R];
   if constexpr (CFFT_COL_PREFETCH) {
     const V* src = col0 + (size_t)(a.tensor || a.parabolic ? 0 : a.order) * plane;
 #pragma unroll
-    for (int r = 0; r < R; ++r) nxt[r] = load_term(src, r);
+    for (int r = 0; r < R; ++r) nxt[r] = load_term(src, r, t);
   }
   V* my_lds = lds + c * LDP;
   __syncthreads();   // twiddle tables ready
   for (int b = 0; b <= a.order; ++b) {
     V x[R];
+    // an opaque copy of t keeps the per-point weights and addresses inside
+    // the term loop (hoisted, they would stay live in registers across it)
+    int tb = t;
+    asm volatile("" : "+v"(tb));
     if constexpr (!CFFT_COL_PREFETCH) {
       const V* src = col0 + (size_t)(a.tensor ? 0 : a.parabolic ? b : a.order - b) * plane;
 #pragma unroll
-      for (int r = 0; r < R; ++r) nxt[r] = load_term(src, r);
+      for (int r = 0; r < R; ++r) nxt[r] = load_term(src, r, tb);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int n2 = t + T * r;
+      const int n2 = tb + T * r;
       const Rl gk = (Rl)(a.gamma * (a.ky0 + n2 * a.dky));
       Rl w = (n2 & 1) ? (Rl)-1 : (Rl)1;
       if (!a.parabolic)
@@ -483,24 +515,25 @@ __global__ void __launch_bounds__(C * (N / R), col_min_waves<V>()) col_pass_kern
     if (CFFT_COL_PREFETCH && b < a.order) {
       const V* src = col0 + (size_t)(a.tensor ? 0 : a.parabolic ? b + 1 : a.order - b - 1) * plane;
 #pragma unroll
-      for (int r = 0; r < R; ++r) nxt[r] = load_term(src, r);
+      for (int r = 0; r < R; ++r) nxt[r] = load_term(src, r, tb);
     }
     fft_forward<V, N, R>(x, my_lds, ltw, t);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int j2 = t + T * r;
+      const int j2 = tb + T * r;
       const double dy = a.y0 + j2 * a.ddy;
       double cf = 1.0;
       for (int i = 1; i <= b; ++i) cf *= dy * a.rinv[i];
-      const double2 xv = to_d(x[r]);
-      Z[r] = make_double2(Z[r].x + cf * xv.x, Z[r].y + cf * xv.y);
+      const Acc xv = from_d<Acc>(to_d(x[r]));
+      Z[r].x += (Ra)cf * xv.x;
+      Z[r].y += (Ra)cf * xv.y;
     }
   }
   V* dst = (V*)a.z + (size_t)pair * plane + j1;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j2 = t + T * r;
-    double2 v = cmul(Z[r], a.scale);
+    double2 v = cmul(to_d(Z[r]), a.scale);
     if ((j1 + j2) & 1) v = make_double2(-v.x, -v.y);
     // streaming stores for whole 64-byte row pieces; narrower tiles store
     // through the cache, where the neighbouring tiles' pieces complete a line
@@ -510,21 +543,29 @@ __global__ void __launch_bounds__(C * (N / R), col_min_waves<V>()) col_pass_kern
   }
 }
 
-// Points per thread of the column pass.
-__host__ __device__ constexpr int col_r(int) { return 8; }
+// Points per thread of the column pass: 8, except on the columns whose LDS
+// tile would otherwise be one or two columns wide (FP32 columns of 4096
+// points; FP64 columns of 2048 and 4096 when CFFT_COL_R_F64_2048 asks for
+// it): there 16 or 32 points per thread keep a tile of four columns within
+// 512 threads and 152 KiB of LDS.
+__host__ __device__ constexpr int col_r(int ny, int bytes) {
+  return (bytes == 8 && ny >= 4096) ? CFFT_COL_R_F32_4096 : (bytes == 16 && ny >= 2048) ? CFFT_COL_R_F64_2048 : 8;
+}
 
-// Column tile width: as close to CFFT_COL_ROW_BYTES of contiguous row data as
-// an 80 KiB LDS tile and 512 threads allow (1024-thread blocks cap a kernel at
-// 128 VGPRs: the FP64 kernels would spill; the FP32 kernels of columns of
-// 2048 and 4096, whose tiles are otherwise one or two columns wide, take
-// 1024 threads when CFFT_COL_WIDE_FP32 is set).
-__host__ __device__ constexpr int col_tile_c(int ny, int bytes) {
+// Column tile width for r points per thread: as close to CFFT_COL_ROW_BYTES
+// of contiguous row data as an 80 KiB LDS tile (152 KiB when r > 8: one block
+// per CU) and 512 threads allow (1024-thread blocks cap a kernel at 128
+// VGPRs: the FP64 kernels would spill; the FP32 kernels of columns of 2048
+// and 4096 take 1024 threads when CFFT_COL_WIDE_FP32 is set).
+__host__ __device__ constexpr int col_tile_cr(int ny, int bytes, int r) {
   int c = (bytes == 8 ? CFFT_COL_ROW_BYTES_F32 : CFFT_COL_ROW_BYTES) / bytes;
-  const int r = col_r(bytes);
   const int max_threads = (CFFT_COL_WIDE_FP32 && bytes == 8 && ny >= 2048) ? 1024 : 512;
-  while (c > 1 && (c * (lds_len(ny) + CFFT_COL_LDP_EXTRA) * bytes > 81920 || c * (ny / r) > max_threads)) c /= 2;
+  const int lds_cap = r > 8 ? 155648 : 81920;
+  while (c > 1 && (c * (lds_len(ny) + CFFT_COL_LDP_EXTRA) * bytes > lds_cap || c * (ny / r) > max_threads)) c /= 2;
   return c;
 }
+
+__host__ __device__ constexpr int col_tile_c(int ny, int bytes) { return col_tile_cr(ny, bytes, col_r(ny, bytes)); }
 
 int col_tile(int ny, int precision) { return col_tile_c(ny, precision == 0 ? 16 : 8); }
 
@@ -546,7 +587,7 @@ static hipError_t row_launch(const RowArgs& args, hipStream_t s) {
 template <typename V, int N>
 static hipError_t col_launch(const ColArgs& args, hipStream_t s) {
   constexpr int C0 = col_tile_c(N, sizeof(V));
-  constexpr int R = col_r(sizeof(V));
+  constexpr int R = col_r(N, sizeof(V));
   // the autotuner's alternative: tiles of half the width (more, smaller
   // blocks; shorter row pieces)
   if constexpr (C0 > 1) {
@@ -855,7 +896,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
 
 template <int N>
 static hipError_t adj_col_launch(const AdjColArgs& args, hipStream_t s) {
-  constexpr int C = col_tile_c(N, 16);
+  constexpr int C = col_tile_cr(N, 16, 8);
   using Cfg = ColCfg<N, C, 8>;
   if (args.nx % C != 0) return hipErrorInvalidValue;
   const int nblk = (args.nx / C) * args.npairs;
