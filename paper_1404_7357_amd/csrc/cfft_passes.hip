@@ -83,6 +83,15 @@
 #define CFFT_COL_ROW_BYTES 64
 #endif
 
+// Row pass: rebuild the per-point factors and store addresses in every term
+// (1), let the compiler keep them live across the term loop (0), or rebuild
+// them only in the FP32 rows of 1024 points and more (2), whose kernels
+// otherwise spill at the 128 registers of their occupancy target (elsewhere
+// the rebuilt factors cost 3% of the FP64 row pass).
+#ifndef CFFT_ROW_OPAQUE_T
+#define CFFT_ROW_OPAQUE_T 2
+#endif
+
 // Points per thread of the FP32 column pass on columns of 4096 points, and
 // of the FP64 column pass on columns of 2048 and 4096 points.
 #ifndef CFFT_COL_R_F32_4096
@@ -108,6 +117,11 @@ template <typename V> __host__ __device__ constexpr int row_pad() {
 template <typename V, int N> constexpr int row_min_waves() {
   return (sizeof(V) == 8 && N >= 1024) ? (CFFT_ROW_MIN_WAVES_F32 > 0 ? CFFT_ROW_MIN_WAVES_F32 : 1)
                                        : (CFFT_ROW_MIN_WAVES > 0 ? CFFT_ROW_MIN_WAVES : 1);
+}
+
+// Whether the row pass rebuilds its per-point factors in every term.
+template <typename V, int N> constexpr bool row_opaque_t() {
+  return CFFT_ROW_OPAQUE_T == 1 || (CFFT_ROW_OPAQUE_T == 2 && sizeof(V) == 8 && N >= 1024);
 }
 
 template <int N> struct RowCfg {
@@ -252,7 +266,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) r
     // opaque copy of t: the per-point factors and store addresses are
     // rebuilt per term instead of being hoisted and held across the loop
     int tb = t;
-    asm volatile("" : "+v"(tb));
+    if constexpr (row_opaque_t<V, N>()) asm volatile("" : "+v"(tb));
     if (ao > 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -385,7 +399,7 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pa
     // opaque copy of t: the per-point factors and store addresses are
     // rebuilt per term instead of being hoisted and held across the loop
     int tb = t;
-    asm volatile("" : "+v"(tb));
+    if constexpr (row_opaque_t<V, N>()) asm volatile("" : "+v"(tb));
     if (ao > 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
