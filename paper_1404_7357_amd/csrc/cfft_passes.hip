@@ -480,8 +480,9 @@ __global__ void __launch_bounds__(C * (N / R), (col_min_waves<V, R>())) col_pass
   const int nsl = a.tensor ? 1 : a.order + 1;
   const V* col0 = (const V*)a.inter + (size_t)pair * nsl * plane + j1;
 
-  // the recombination sums in FP64, except in the 16-point FP32 tiles, where
-  // FP64 accumulators would not fit the 128 registers of a 1024-thread block
+  // the recombination sums in FP64, except in the FP32 tiles of 16 or 32
+  // points per thread, where FP64 accumulators do not fit the registers (at
+  // 32 points: 83 spilled; FP32 ones spill 7)
   using Acc = typename std::conditional<(R > 8), V, double2>::type;
   using Ra = typename real_of<Acc>::type;
   Acc Z[R];
