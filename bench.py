@@ -8,9 +8,10 @@ rooftops each), and the C-FFT table of all 16 MBF pairs on a 512 x 512 grid
 substrate) are resident before the timed region.
 
 Printed: one JSON line with the headline (table entries per second), the
-roofline of the dominant kernel (per-kernel HIP event timing), the CPU
-oracle timed on a bounded sample, and side measurements (mixed precision,
-adjoint/forward time on the 1024^2 differentiation workload).
+roofline of the dominant kernel (per-kernel HIP event timing), side
+measurements (mixed precision, the other workloads, adjoint/forward time on
+the 1024^2 differentiation workload), and, from a last host-CPU leg, the
+oracle timed on a bounded sample with each GPU result's error against it.
 """
 from __future__ import annotations
 
@@ -245,6 +246,56 @@ def _cpu_baseline(wl, z_gpu, n_out, workers):
                       f"{dt:.1f} s"}, err, (idx, ref)
 
 
+def _rel_err(got, ref):
+    """Largest error over pairs, relative to each pair's largest oracle value."""
+    import numpy as np
+    return float((np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+
+
+def _cpu_leg(out, tables, n_out, workers):
+    """The host-CPU leg, run after every GPU leg: the oracle timed on a bounded
+    sample of the benchmark workload (cpu_baseline) and the CPU C-FFT
+    baselines.  The oracle's values on that sample, and on sampled outputs of
+    the other legs' tables (collected in `tables`), state each GPU result's
+    error against the FP64 oracle.  Nothing else in this script runs the
+    oracle."""
+    import numpy as np
+
+    from oracle import cfft_oracle as co
+    wl, z_fp64 = tables["c2"]
+    npairs = len(wl.pairs)
+    _log(f"cpu oracle on {n_out} outputs x {npairs} pairs, {workers} threads")
+    base, err, (idx, ref) = _cpu_baseline(wl, z_fp64, n_out, workers)
+    out["cpu_baseline"] = base
+    out["rel_err_vs_oracle"] = err
+    _log("cpu C-FFT baseline (eq. fftarry with scipy FFT2, whole table)")
+    out["cpu_cfft"] = _cpu_cfft(wl, z_fp64, workers)
+    _log("cpu C-FFT, one pair of the paper's 2048^2 setup")
+    out["cpu_cfft_paper_pair"] = _cpu_cfft_paper_pair(workers)
+    if "mixed" in tables:
+        out["mixed"]["rel_err_vs_oracle"] = _rel_err(tables["mixed"].reshape(npairs, -1)[:, idx], ref)
+    # other legs: the oracle at 64 sampled outputs per pair plus Delta = 0
+    for key, seed, target in (("tensor_fp64", 77, ("tensor", "fp64")), ("tensor_mixed", 77, ("tensor", "mixed")),
+                              ("parabolic", 78, ("parabolic",))):
+        if key not in tables:
+            continue
+        wlx, z = tables[key]
+        grid, sub = wlx.grids[0], wlx.substrates[0]
+        rng = np.random.default_rng(seed)
+        sidx = np.unique(np.concatenate([rng.choice(grid.nx * grid.ny, 64, replace=False),
+                                         [(grid.ny // 2) * grid.nx + grid.nx // 2]]))
+        sref = co.tabulate(grid, sub, wlx.basis, wlx.q, wlx.pairs, out_idx=sidx, workers=workers)
+        leg = out
+        for k in target:
+            leg = leg[k]
+        leg["rel_err_vs_oracle"] = _rel_err(z[:, sidx], sref)
+        leg["oracle_sample"] = f"{len(sidx)} outputs x {len(wlx.pairs)} pairs"
+    if "c1" in tables:
+        wl1, z1 = tables["c1"]
+        r1 = co.tabulate(wl1.grids[0], wl1.substrates[0], wl1.basis, wl1.q, wl1.pairs)
+        out["c1_latency"]["rel_err_vs_oracle"] = float(np.abs(z1 - r1).max() / np.abs(r1).max())
+
+
 def _adjoint_ratio(torch, steps, warmup):
     """Forward (table + lookup + loss) vs backward (lookup adjoint + cfft_backward) on 1024^2."""
     from paper_1404_7357_amd import LookupFunction, TableFunction, Tabulator
@@ -282,15 +333,13 @@ def _adjoint_ratio(torch, steps, warmup):
             "queries": int(pts.shape[0])}
 
 
-def _tensor_leg(torch, steps, warmup, precision, n_out):
+def _tensor_leg(torch, steps, warmup, precision):
     """The 512^2 workload with the tensor-product truncation (one intermediate
-    per pair; not in the paper), with its error against the oracle's tensor
-    mode on n_out sampled outputs per pair."""
+    per pair; not in the paper).  Returns the leg's figures and (workload,
+    table) for the CPU leg, which states its error against the oracle's
+    tensor mode."""
     import dataclasses
 
-    import numpy as np
-
-    from oracle import cfft_oracle as co
     from workloads import TRUNC_TENSOR, c2_rooftop_512
     wl = c2_rooftop_512(precision=precision)
     wl = dataclasses.replace(wl, grids=[dataclasses.replace(wl.grids[0], truncation=TRUNC_TENSOR)])
@@ -301,28 +350,18 @@ def _tensor_leg(torch, steps, warmup, precision, n_out):
     torch.cuda.synchronize()
     z = st.z.cpu().numpy().reshape(len(wl.pairs), -1)
     st.tab.close()
-    grid, sub = wl.grids[0], wl.substrates[0]
-    rng = np.random.default_rng(77)
-    idx = np.unique(np.concatenate([rng.choice(grid.nx * grid.ny, n_out, replace=False),
-                                    [(grid.ny // 2) * grid.nx + grid.nx // 2]]))
-    ref = co.tabulate(grid, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=min(16, os.cpu_count() or 1))
-    err = float((np.abs(z[:, idx] - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
     return {"value": st.entries() / sec, "ms_per_step": sec * 1e3,
             "passes_only": {"ms": sec_tab * 1e3, "value": st.entries() / sec_tab, "unit": "entries/s"},
-            "rel_err_vs_oracle": err, "oracle_sample": f"{len(idx)} outputs x {len(wl.pairs)} pairs",
-            "dtype": "f64" if precision == 0 else "fp32 FFT / fp64 rest", "kernels_ms": km}
+            "dtype": "f64" if precision == 0 else "fp32 FFT / fp64 rest", "kernels_ms": km}, (wl, z)
 
 
-def _parabolic_leg(torch, steps, warmup, n_out):
+def _parabolic_leg(torch, steps, warmup):
     """The 512^2 workload on the parabolic contour (beta_end = 2 k0 sqrt(eps_r)):
-    per-sample spectra, (P+1)(P+2)/2 row transforms; FP64, error against the
-    oracle on n_out sampled outputs per pair."""
+    per-sample spectra, (P+1)(P+2)/2 row transforms; FP64.  Returns the
+    leg's figures and (workload, table) for the CPU leg's error statement."""
     import dataclasses
     import math as _m
 
-    import numpy as np
-
-    from oracle import cfft_oracle as co
     from workloads import CONTOUR_PARABOLIC, c2_rooftop_512
     wl = c2_rooftop_512()
     sub = wl.substrates[0]
@@ -336,15 +375,9 @@ def _parabolic_leg(torch, steps, warmup, n_out):
     torch.cuda.synchronize()
     z = st.z.cpu().numpy().reshape(len(wl.pairs), -1)
     st.tab.close()
-    rng = np.random.default_rng(78)
-    idx = np.unique(np.concatenate([rng.choice(grid.nx * grid.ny, n_out, replace=False),
-                                    [(grid.ny // 2) * grid.nx + grid.nx // 2]]))
-    ref = co.tabulate(grid, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=min(16, os.cpu_count() or 1))
-    err = float((np.abs(z[:, idx] - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
     return {"value": st.entries() / sec, "ms_per_step": sec * 1e3, "beta_end": grid.beta_end,
             "passes_only": {"ms": sec_tab * 1e3, "value": st.entries() / sec_tab, "unit": "entries/s"},
-            "rel_err_vs_oracle": err, "oracle_sample": f"{len(idx)} outputs x {len(wl.pairs)} pairs",
-            "dtype": "f64", "kernels_ms": km}
+            "dtype": "f64", "kernels_ms": km}, (wl, z)
 
 
 def _large_leg(torch, steps, warmup):
@@ -371,10 +404,8 @@ def _large_leg(torch, steps, warmup):
 
 def _c1_latency(torch, steps, warmup):
     """The smallest configuration (64^2, one MBF, one pair, FP64): launch-bound, so its step latency is
-    the figure of merit; error against the oracle's whole table."""
-    import numpy as np
-
-    from oracle import cfft_oracle as co
+    the figure of merit.  Returns (workload, table) too: the CPU leg states its error against the
+    oracle's whole table."""
     from workloads import c1_single_cosine
     wl = c1_single_cosine()
     st = Step(wl, torch)
@@ -382,10 +413,7 @@ def _c1_latency(torch, steps, warmup):
     torch.cuda.synchronize()
     z = st.z.cpu().numpy()
     st.tab.close()
-    ref = co.tabulate(wl.grids[0], wl.substrates[0], wl.basis, wl.q, wl.pairs)
-    err = float(np.abs(z - ref).max() / np.abs(ref).max())
-    return {"workload": wl.name, "latency_us": sec * 1e6, "entries": st.entries(), "rel_err_vs_oracle": err,
-            "dtype": "f64"}
+    return {"workload": wl.name, "latency_us": sec * 1e6, "entries": st.entries(), "dtype": "f64"}, (wl, z)
 
 
 def _paper_leg(torch, steps, warmup):
@@ -471,7 +499,6 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     _ensure_built()
-    import numpy as np
     import torch
 
     from workloads import MIXED, c2_rooftop_512
@@ -552,18 +579,8 @@ def main():
     st.tab.close()
     del st
 
-    if not args.no_cpu_baseline:
-        workers = min(16, os.cpu_count() or 1)
-        _log(f"cpu oracle on {args.cpu_outputs} outputs x {npairs} pairs, {workers} threads")
-        base, err, sample = _cpu_baseline(wl, z_fp64, args.cpu_outputs, workers)
-        out["cpu_baseline"] = base
-        out["rel_err_vs_oracle"] = err
-        _log("cpu C-FFT baseline (eq. fftarry with scipy FFT2, whole table)")
-        out["cpu_cfft"] = _cpu_cfft(wl, z_fp64, workers)
-        _log("cpu C-FFT, one pair of the paper's 2048^2 setup")
-        out["cpu_cfft_paper_pair"] = _cpu_cfft_paper_pair(workers)
-    else:
-        sample = None
+    # GPU tables kept for the CPU leg's error statements
+    tables = {"c2": (wl, z_fp64)}
 
     if not args.no_extras:
         wlm = c2_rooftop_512(precision=MIXED)
@@ -574,29 +591,30 @@ def main():
         mixed = {"value": stm.entries() / secm, "ms_per_step": secm * 1e3, "dtype": "fp32 FFT / fp64 rest",
                  "passes_only": {"ms": secm_tab * 1e3, "value": stm.entries() / secm_tab, "unit": "entries/s"},
                  "kernels_ms": km}
-        if sample is not None:
-            idx, ref = sample
-            zm = stm.z.cpu().numpy().reshape(npairs, -1)[:, idx]
-            mixed["rel_err_vs_oracle"] = float((np.abs(zm - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+        torch.cuda.synchronize()
+        tables["mixed"] = stm.z.cpu().numpy()
         stm.tab.close()
         del stm
         out["mixed"] = mixed
         _log("tensor-product truncation legs (FP64, mixed)")
-        n_out = 0 if args.no_cpu_baseline else 64
-        out["tensor"] = {"fp64": _tensor_leg(torch, args.steps, args.warmup, 0, max(n_out, 4)),
-                         "mixed": _tensor_leg(torch, args.steps, args.warmup, MIXED, max(n_out, 4))}
+        tf, tables["tensor_fp64"] = _tensor_leg(torch, args.steps, args.warmup, 0)
+        tm, tables["tensor_mixed"] = _tensor_leg(torch, args.steps, args.warmup, MIXED)
+        out["tensor"] = {"fp64": tf, "mixed": tm}
         _log("parabolic-contour leg (FP64)")
-        out["parabolic"] = _parabolic_leg(torch, max(3, args.steps // 5), 2, max(n_out, 4))
+        out["parabolic"], tables["parabolic"] = _parabolic_leg(torch, max(3, args.steps // 5), 2)
         _log("large leg (4096^2, 36 pairs, 10^5 lookups)")
         out["large"] = _large_leg(torch, 3, 1)
         _log("64^2 single-pair latency leg")
-        out["c1_latency"] = _c1_latency(torch, args.steps, args.warmup)
+        out["c1_latency"], tables["c1"] = _c1_latency(torch, args.steps, args.warmup)
         _log("paper-setup leg (2048^2 incl. zero padding, 81 pairs, 25 x 25 array fill)")
         out["paper_setup"] = _paper_leg(torch, 3, 1)
         _log("sweep leg (8 grids, one graph)")
         out["sweep"] = _sweep(torch, max(3, args.steps // 5), 2)
         _log("adjoint leg (1024^2, 16 pairs, 4096 lookups)")
         out["adjoint"] = _adjoint_ratio(torch, max(3, args.steps // 5), 2)
+
+    if not args.no_cpu_baseline:
+        _cpu_leg(out, tables, args.cpu_outputs, min(16, os.cpu_count() or 1))
     print(json.dumps(out), flush=True)
 
 
