@@ -441,8 +441,9 @@ struct ColArgs {
 };
 
 // Minimum waves per SIMD requested for the column pass (1: no constraint).
-// 32-point tiles run one 512-thread block per CU (their LDS tile takes the
-// CU's LDS), two waves per SIMD.
+// The 32-point tiles (512 threads, 256 when narrow) take the register
+// budget of two waves per SIMD: a four-column tile's LDS fills the CU, so
+// one block (two waves per SIMD) is all that runs there anyway.
 template <typename V, int R> constexpr int col_min_waves() {
   return R == 32 ? 2
          : sizeof(V) == 8 ? (CFFT_COL_MIN_WAVES_F32 > 0 ? CFFT_COL_MIN_WAVES_F32 : 1)
