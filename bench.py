@@ -492,7 +492,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and adjoint legs")
     ap.add_argument("--copy-calibration", action="store_true", help="run one 256 MiB device copy (counter scale)")
-    ap.add_argument("--only", choices=("large", "paper_setup"),
+    ap.add_argument("--only", choices=("large", "paper_setup", "sweep", "adjoint"),
                     help="run one extra leg alone and print its JSON (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -514,7 +514,7 @@ def main():
         del a, b
 
     if args.only:
-        leg = {"large": _large_leg, "paper_setup": _paper_leg}[args.only]
+        leg = {"large": _large_leg, "paper_setup": _paper_leg, "sweep": _sweep, "adjoint": _adjoint_ratio}[args.only]
         print(json.dumps({"leg": args.only, **leg(torch, args.steps, args.warmup)}), flush=True)
         return
 

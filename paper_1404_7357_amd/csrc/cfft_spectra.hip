@@ -448,10 +448,13 @@ hipError_t launch_spectra_direct(const Axis& x, const Axis& y, const Contour& c,
 // Gradient of L w.r.t. q from the gradient w.r.t. the spectra (gspec, same
 // layout as spec, in the d/dRe + i d/dIm convention):
 //   gq_mj = sum_n conj(gM_m(n)) F_j(k_c(n)) + gM#_m(n) conj(F_j(-k_c(n))).
-// Per row n2 the sums over n1 are reduced per (m, g, p) in the block, then
-// multiplied by the row factors and written to rowacc[n2][m][j]; a second
-// kernel sums rowacc over rows in a fixed order.
+// Per row n2 the sums over n1 are reduced per (m, g, p), one wave per
+// (m, p) item (lane-strided sums, then a butterfly over the wave's lanes),
+// then multiplied by the row factors and written to rowacc[n2][m][j]; two
+// more kernels sum rowacc over rows in a fixed order (row classes modulo
+// kAdjSplit in place, then the classes).
 constexpr int kAdjThreads = 256;
+constexpr int kAdjSplit = 64;
 
 __global__ void __launch_bounds__(kAdjThreads)
 adj_spectra_rows_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __restrict__ utab,
@@ -460,7 +463,6 @@ adj_spectra_rows_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const doub
   // a1, a2: [nmbf][total_p]
   double2* a1 = sh;
   double2* a2 = sh + nmbf * geo.total_p;
-  __shared__ double2 red[2][kAdjThreads];
   __shared__ GeomGroup grp[kMaxGroups];
   const int n2 = blockIdx.x;
   const double ky = y.k_first + n2 * y.dk;
@@ -468,39 +470,37 @@ adj_spectra_rows_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const doub
   if (threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
   __syncthreads();
   const size_t plane = (size_t)x.n * y.n;
-  for (int m = 0; m < nmbf; ++m) {
-    for (int g = 0; g < geo.ngroups; ++g) {
-      const GeomGroup gr = grp[g];
-      const int comp = is_ydir(gr.kind) ? 1 : 0;
-      for (int p = 0; p < gr.np; ++p) {
-        const int prow = gr.uoff + p;
-        double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
-        for (int n1 = threadIdx.x; n1 < x.n; n1 += blockDim.x) {
-          const double2 u = utab[(size_t)(2 * prow) * x.n + n1];        // SX U
-          const double2 uh = utab[(size_t)(2 * prow + 1) * x.n + n1];   // SX U#
-          const double2 gm = gspec[((size_t)m * 4 + comp) * plane + (size_t)n2 * x.n + n1];
-          const double2 gmh = gspec[((size_t)m * 4 + 2 + comp) * plane + (size_t)n2 * x.n + n1];
-          s1 = cadd(s1, cmulc(u, gm));      // conj(gM) SX U  (conj applied below)
-          s2 = cadd(s2, cmulc(gmh, uh));    // gM# conj(SX U#)
-        }
-        red[0][threadIdx.x] = s1;
-        red[1][threadIdx.x] = s2;
-        __syncthreads();
-        for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
-          if (threadIdx.x < w) {
-            red[0][threadIdx.x] = cadd(red[0][threadIdx.x], red[0][threadIdx.x + w]);
-            red[1][threadIdx.x] = cadd(red[1][threadIdx.x], red[1][threadIdx.x + w]);
-          }
-          __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-          a1[m * geo.total_p + prow] = red[0][0];
-          a2[m * geo.total_p + prow] = red[1][0];
-        }
-        __syncthreads();
-      }
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nitems = nmbf * geo.total_p;
+  for (int it = wave; it < nitems; it += kAdjThreads / 64) {
+    const int m = it / geo.total_p;
+    const int prow = it - m * geo.total_p;   // U row uoff_g + p of the group g holding it
+    int g = 0;
+    while (g + 1 < geo.ngroups && grp[g + 1].uoff <= prow) ++g;
+    const int comp = is_ydir(grp[g].kind) ? 1 : 0;
+    double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+    for (int n1 = lane; n1 < x.n; n1 += 64) {
+      const double2 u = utab[(size_t)(2 * prow) * x.n + n1];        // SX U
+      const double2 uh = utab[(size_t)(2 * prow + 1) * x.n + n1];   // SX U#
+      const double2 gm = gspec[((size_t)m * 4 + comp) * plane + (size_t)n2 * x.n + n1];
+      const double2 gmh = gspec[((size_t)m * 4 + 2 + comp) * plane + (size_t)n2 * x.n + n1];
+      s1 = cadd(s1, cmulc(u, gm));      // conj(gM) SX U  (conj applied below)
+      s2 = cadd(s2, cmulc(gmh, uh));    // gM# conj(SX U#)
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s1.x += __shfl_xor(s1.x, off, 64);
+      s1.y += __shfl_xor(s1.y, off, 64);
+      s2.x += __shfl_xor(s2.x, off, 64);
+      s2.y += __shfl_xor(s2.y, off, 64);
+    }
+    if (lane == 0) {
+      a1[it] = s1;
+      a2[it] = s2;
     }
   }
+  __syncthreads();
   // rowacc[n2][m][j] = SY V_r a1[p] + conj(SY V#_r) a2[p]
   const int nent = nmbf * geo.total_idx;
   for (int e = threadIdx.x; e < nent; e += blockDim.x) {
@@ -521,6 +521,18 @@ adj_spectra_rows_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const doub
     const double2 t2 = cmulc(a2[m * geo.total_p + gr.uoff + p], cmul(sy, vh));
     rowacc[((size_t)n2 * nmbf + m) * geo.nbasis + j] = cadd(t1, t2);
   }
+}
+
+// In place: rowacc[s][e] <- sum over rows r = s, s + kAdjSplit, ... of
+// rowacc[r][e], for s < min(kAdjSplit, nrows) (fixed order; thread (s, e) is
+// the only one to read or write any row of its class at column e).
+__global__ void adj_spectra_split_kernel(double2* __restrict__ rowacc, int nrows, int count) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (e >= count || s >= nrows) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int r = s; r < nrows; r += kAdjSplit) acc = cadd(acc, rowacc[(size_t)r * count + e]);
+  rowacc[(size_t)s * count + e] = acc;
 }
 
 // gq[m][j] = sum_n2 rowacc[n2][m][j]  (fixed summation order)
@@ -546,7 +558,12 @@ hipError_t launch_adj_spectra(const Axis& x, const Axis& y, double gamma, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int count = nmbf * geo.nbasis;
-  hipLaunchKernelGGL(adj_spectra_sum_kernel, dim3((count + 255) / 256), dim3(256), 0, s, rowacc, y.n, count, gq);
+  hipLaunchKernelGGL(adj_spectra_split_kernel, dim3((count + 255) / 256, kAdjSplit), dim3(256), 0, s, rowacc, y.n,
+                     count);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adj_spectra_sum_kernel, dim3((count + 255) / 256), dim3(256), 0, s, rowacc,
+                     y.n < kAdjSplit ? y.n : kAdjSplit, count, gq);
   return hipGetLastError();
 }
 
