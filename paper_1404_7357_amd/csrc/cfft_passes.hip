@@ -1054,6 +1054,97 @@ __global__ void __launch_bounds__(256) adj_integrand_kernel(AdjIntArgs a) {
   a.gg[2 * plane + idx] = ggyy;
 }
 
+// The same gradients for at most NM MBFs, with one pass over the pairs: the
+// sample's spectra of every MBF and the gradient accumulators stay in
+// registers (the MBF of a pair is wave-uniform, so selecting its registers
+// costs unrolled uniform branches), and each pair's integrand gradient is
+// read once.  The generic kernel above re-reads it and the spectra per MBF.
+template <int NM>
+__global__ void __launch_bounds__(256) adj_integrand_small_kernel(AdjIntArgs a) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.n) return;
+  const bool silent = a.band && !(in_band(idx % a.nx, a.nx) && in_band(idx / a.nx, a.ny));
+  const size_t plane = (size_t)a.n;
+  const double2 zero = make_double2(0.0, 0.0);
+  const double2 gxx = a.g[idx], gxy = a.g[plane + idx], gyy = a.g[2 * plane + idx];
+  double2 ggxx = zero, ggxy = zero, ggyy = zero;
+  if (a.accumulate) {
+    ggxx = a.gg[idx];
+    ggxy = a.gg[plane + idx];
+    ggyy = a.gg[2 * plane + idx];
+  }
+  double2 sx[NM], sy[NM], sxh[NM], syh[NM], gmx[NM], gmy[NM], gmxh[NM], gmyh[NM];
+#pragma unroll
+  for (int mm = 0; mm < NM; ++mm) {
+    gmx[mm] = gmy[mm] = gmxh[mm] = gmyh[mm] = zero;
+    sx[mm] = sy[mm] = sxh[mm] = syh[mm] = zero;
+    if (mm < a.nmbf && !silent) {
+      const double2* sp = a.spec + (size_t)mm * 4 * plane + idx;
+      sx[mm] = sp[0];
+      sy[mm] = sp[plane];
+      sxh[mm] = sp[2 * plane];
+      syh[mm] = sp[3 * plane];
+    }
+  }
+  for (int p = 0; p < (silent ? 0 : a.npairs); ++p) {
+    const int m = a.pm[p], n = a.pn[p];
+    const double2 gh = a.gi[(size_t)p * plane + idx];
+    double2 mx = zero, my = zero, nxh = zero, nyh = zero;
+#pragma unroll
+    for (int mm = 0; mm < NM; ++mm) {
+      if (mm == m) {
+        mx = sx[mm];
+        my = sy[mm];
+      }
+      if (mm == n) {
+        nxh = sxh[mm];
+        nyh = syh[mm];
+      }
+    }
+    const double2 cx = cmulc(gh, cadd(cmul(gxx, nxh), cmul(gxy, nyh)));
+    const double2 cy = cmulc(gh, cadd(cmul(gxy, nxh), cmul(gyy, nyh)));
+    const double2 chx = cmulc(gh, cadd(cmul(mx, gxx), cmul(my, gxy)));
+    const double2 chy = cmulc(gh, cadd(cmul(mx, gxy), cmul(my, gyy)));
+    ggxx = cadd(ggxx, cmulc(gh, cmul(mx, nxh)));
+    ggxy = cadd(ggxy, cmulc(gh, cadd(cmul(mx, nyh), cmul(my, nxh))));
+    ggyy = cadd(ggyy, cmulc(gh, cmul(my, nyh)));
+#pragma unroll
+    for (int mm = 0; mm < NM; ++mm) {
+      if (mm == m) {
+        gmx[mm] = cadd(gmx[mm], cx);
+        gmy[mm] = cadd(gmy[mm], cy);
+      }
+      if (mm == n) {
+        gmxh[mm] = cadd(gmxh[mm], chx);
+        gmyh[mm] = cadd(gmyh[mm], chy);
+      }
+    }
+  }
+#pragma unroll
+  for (int mm = 0; mm < NM; ++mm) {
+    if (mm >= a.nmbf) break;
+    double2* gs = a.gspec + (size_t)mm * 4 * plane + idx;
+    if (a.accumulate) {
+      bool touched = false;
+      for (int p = 0; p < a.npairs; ++p) touched = touched || a.pm[p] == mm || a.pn[p] == mm;
+      if (touched && !silent) {
+        gs[0] = cadd(gs[0], gmx[mm]);
+        gs[plane] = cadd(gs[plane], gmy[mm]);
+        gs[2 * plane] = cadd(gs[2 * plane], gmxh[mm]);
+        gs[3 * plane] = cadd(gs[3 * plane], gmyh[mm]);
+      }
+    } else {
+      gs[0] = gmx[mm];
+      gs[plane] = gmy[mm];
+      gs[2 * plane] = gmxh[mm];
+      gs[3 * plane] = gmyh[mm];
+    }
+  }
+  a.gg[idx] = ggxx;
+  a.gg[plane + idx] = ggxy;
+  a.gg[2 * plane + idx] = ggyy;
+}
+
 hipError_t launch_adj_integrand(const PassParams& p, const double2* gi, const double2* g, const double2* spec,
                                 const int* pm, const int* pn, int npairs, int nmbf, double2* gg, double2* gspec,
                                 int accumulate, hipStream_t s) {
@@ -1075,7 +1166,10 @@ hipError_t launch_adj_integrand(const PassParams& p, const double2* gi, const do
     a.pm[i] = i < npairs ? pm[i] : 0;
     a.pn[i] = i < npairs ? pn[i] : 0;
   }
-  hipLaunchKernelGGL(adj_integrand_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  if (nmbf <= 4)
+    hipLaunchKernelGGL(adj_integrand_small_kernel<4>, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(adj_integrand_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
