@@ -91,6 +91,30 @@ def test_gradient_vs_oracle():
     assert np.abs(dq - o_dq).max() < 1e-9 * np.abs(o_dq).max()
 
 
+def test_gradient_five_mbfs_vs_oracle():
+    """More than four MBFs, an uneven pair list (the integrand adjoint's
+    generic kernel, which reads each pair's gradient once per MBF), against
+    the oracle's gradient."""
+    _say("adjoint 5 MBFs vs oracle 32^2")
+    rng = np.random.default_rng(59)
+    n, m = 32, 5
+    grid = Grid(n, n, 6 * K0, 6 * K0, K0)
+    sub = Substrate(2.2, 0.0, 0.05)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, m, basis.shape[0])
+    pairs = [(0, 0), (1, 4), (4, 2), (3, 3), (2, 1), (4, 4), (0, 3)]
+    dxa = co.displacement_axis(n, grid.kx_max)
+    pts = rng.uniform(dxa[1], dxa[-3], (16, 2))
+    qt = q + 0.1 * gaussian_coefficients(rng, m, basis.shape[0])
+    zt = co.lookup_direct(grid, Substrate(2.3, 0.0, 0.05), basis, qt, np.array(pairs), pts)
+    loss, de, dh, dq = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt)
+    o_loss, o_de, o_dh, o_dq = co.loss_gradient(grid, sub, basis, q, np.array(pairs), pts, zt)
+    assert abs(loss - o_loss) < 1e-9 * abs(o_loss)
+    assert abs(de - o_de) < 1e-9 * max(abs(o_de), 1e-300), (de, o_de)
+    assert abs(dh - o_dh) < 1e-9 * max(abs(o_dh), 1e-300), (dh, o_dh)
+    assert np.abs(dq - o_dq).max() < 1e-9 * np.abs(o_dq).max()
+
+
 def test_tensor_truncation_gradient_vs_oracle_and_differences():
     """Adjoint of the tensor-product truncation (one stored intermediate per
     pair): against the oracle's gradient of the same mode and central
