@@ -82,4 +82,13 @@ def test_lattice_geometry():
     assert (b["kind"][:128] == ROOFTOP_X).all() and (b["kind"][128:] == ROOFTOP_Y).all()
     xs = b["cx"][:128]
     assert abs(xs.min() + 0.25 - 0.5 / 9) < 1e-15 and abs(xs.max() - 0.25 + 0.5 / 9) < 1e-15
-    assert (np.abs(b["cx"]) + b["a"] <= 0.25 + 1e-12).all() or True
+    # every rooftop lies inside the patch: the triangle (half-base a) along its
+    # current and the strip (width b) across it
+    xr, yr = b[:128], b[128:]
+    assert (np.abs(xr["cx"]) + xr["a"] <= 0.25 + 1e-12).all()
+    assert (np.abs(xr["cy"]) + xr["b"] / 2 <= 0.25 + 1e-12).all()
+    assert (np.abs(yr["cy"]) + yr["a"] <= 0.25 + 1e-12).all()
+    assert (np.abs(yr["cx"]) + yr["b"] / 2 <= 0.25 + 1e-12).all()
+    # and they tile it: the outermost triangles and strips touch the patch edges
+    assert abs(np.abs(xr["cx"]).max() + xr["a"][0] - 0.25) < 1e-12
+    assert abs(np.abs(yr["cx"]).max() + yr["b"][0] / 2 - 0.25) < 1e-12
