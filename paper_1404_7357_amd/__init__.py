@@ -38,10 +38,15 @@ def displacement_axis(n: int, k_max: float):
 
 
 def _check_buffer(t, shape, dtype, name):
-    """Shape, dtype and device of a caller-provided buffer (the C ABI cannot see them)."""
-    if tuple(t.shape) != tuple(shape) or t.dtype != dtype or t.device.type != "cuda":
+    """Shape, dtype, memory layout and device of a caller-provided buffer (the C
+    ABI sees only a pointer): any mismatch raises ValueError before a launch."""
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype:
         raise ValueError(f"{name} must be a {dtype} cuda tensor of shape {tuple(shape)}, got {t.dtype} "
                          f"{tuple(t.shape)} on {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (the library reads it as a dense row-major array)")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a cuda tensor, got one on {t.device}")
 
 
 class Tabulator:
@@ -64,11 +69,21 @@ class Tabulator:
         slab_green_eval(self.plan, grid, eps_r, tan_delta, h, g, stream)
         return g
 
+    def _table_dtype(self, grid):
+        return torch.complex128 if self._grid(grid).precision == FP64 else torch.complex64
+
+    def _check_table(self, z, grid):
+        """A table as cfft_tabulate writes it for this grid: [npairs][ny][nx] in the grid's precision."""
+        gd = self._grid(grid)
+        if z.dim() != 3:
+            raise ValueError(f"z must be a table [npairs][{gd.ny}][{gd.nx}], got shape {tuple(z.shape)}")
+        _check_buffer(z, (z.shape[0], gd.ny, gd.nx), self._table_dtype(grid), "z")
+
     def spectra(self, q, grid: int = 0, out=None, stream=None):
         gd = self._grid(grid)
-        q = q.contiguous()
-        if q.dtype != torch.complex128 or q.shape[1] != self.nbasis:
-            raise ValueError("q must be complex128 [M][nbasis]")
+        if q.dim() != 2:
+            raise ValueError(f"q must be complex128 [M][{self.nbasis}], got shape {tuple(q.shape)}")
+        _check_buffer(q, (q.shape[0], self.nbasis), torch.complex128, "q")
         sdt = torch.complex128 if gd.precision == FP64 else torch.complex64
         spec = out if out is not None else torch.empty((q.shape[0], 4, gd.ny, gd.nx), dtype=sdt, device=self.device)
         _check_buffer(spec, (q.shape[0], 4, gd.ny, gd.nx), sdt, "out")
@@ -88,14 +103,17 @@ class Tabulator:
     def lookup(self, z, pts, grid: int = 0, out=None, stream=None, order: int = 1):
         """Table values at displacements pts [Q][2]: bilinear (order 1) or
         second-order Lagrange (order 2) interpolation."""
+        self._check_table(z, grid)
+        if pts.dim() != 2:
+            raise ValueError(f"pts must be float64 [Q][2], got shape {tuple(pts.shape)}")
         out = out if out is not None else torch.empty((z.shape[0], pts.shape[0]), dtype=torch.complex128,
                                                       device=self.device)
         _check_buffer(out, (z.shape[0], pts.shape[0]), torch.complex128, "out")
         _check_buffer(pts, (pts.shape[0], 2), torch.float64, "pts")
         if order == 2:
-            cfft_lookup_quadratic(self.plan, grid, z, z.shape[0], pts.contiguous(), out, stream)
+            cfft_lookup_quadratic(self.plan, grid, z, z.shape[0], pts, out, stream)
         elif order == 1:
-            cfft_lookup(self.plan, grid, z, z.shape[0], pts.contiguous(), out, stream)
+            cfft_lookup(self.plan, grid, z, z.shape[0], pts, out, stream)
         else:
             raise ValueError("order must be 1 or 2")
         return out
@@ -104,6 +122,9 @@ class Tabulator:
         """Reduced matrix [A*M][A*M] of the element layout pos [A][2] read from
         the table z of the listed pairs; self blocks and unlisted (m, n) keep
         the contents of out (NaN when out is allocated here)."""
+        self._check_table(z, grid)
+        if pos.dim() != 2:
+            raise ValueError(f"pos must be float64 [A][2], got shape {tuple(pos.shape)}")
         am = pos.shape[0] * nmbf
         if out is None:
             out = torch.full((am, am), complex(float("nan"), float("nan")), dtype=torch.complex128,
@@ -112,7 +133,7 @@ class Tabulator:
         _check_buffer(pos, (pos.shape[0], 2), torch.float64, "pos")
         if z.shape[0] != len(pairs):
             raise ValueError(f"z holds {z.shape[0]} tables for {len(pairs)} pairs")
-        cfft_fill(self.plan, grid, z, pairs, nmbf, pos.contiguous(), order, out, stream)
+        cfft_fill(self.plan, grid, z, pairs, nmbf, pos, order, out, stream)
         return out
 
     def close(self):

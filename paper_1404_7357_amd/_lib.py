@@ -13,8 +13,7 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# CFFT_LIB selects another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("CFFT_LIB") or os.path.join(HERE, "libcfft.so")
+LIB_PATH = os.path.join(HERE, "libcfft.so")
 
 CFFT_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "ALLOC", 4: "HIP", 5: "NONFINITE"}

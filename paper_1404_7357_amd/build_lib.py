@@ -39,25 +39,21 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the gfx950 library cannot be built")
 
 
-def _compile(src: str, defines=(), build_dir=None) -> str:
-    obj = os.path.join(build_dir or BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *COMMON, *[f"-D{d}" for d in defines], "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str) -> str:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc(), *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{res.stderr[-6000:]}")
     return obj
 
 
-def build(verbose: bool = False, defines=(), out=None) -> str:
-    """Compile every source and link libcfft.so (or `out`); returns the library path.
-
-    `defines` are extra NAME=VALUE macros (the scheduling knobs of
-    csrc/cfft_passes.hip); the default build uses none."""
-    lib = out or LIB
-    bdir = BUILD if out is None else os.path.join(BUILD, os.path.basename(out) + ".d")
-    os.makedirs(bdir, exist_ok=True)
+def build(verbose: bool = False) -> str:
+    """Compile every source and link libcfft.so; returns the library path."""
+    lib = LIB
+    os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, defines, bdir), SOURCES))
+        objs = list(ex.map(_compile, SOURCES))
     tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)

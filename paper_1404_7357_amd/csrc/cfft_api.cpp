@@ -56,6 +56,12 @@ long long env_ll(const char* name, long long dflt) {
   return (end && *end == 0) ? r : dflt;
 }
 
+// Cap of the pass workspace (the intermediates of one pair chunk), MiB:
+// CFFT_WORKSPACE_MB, else 64 GiB, which lets every benchmark grid run all
+// its pairs in one launch on a 288 GB device (4096^2 FP64, 36 pairs:
+// 38.7 GB).  cfft_tabulate takes smaller chunks when the allocation fails.
+long long workspace_limit_mb() { return env_ll("CFFT_WORKSPACE_MB", 65536); }
+
 // Device allocation with the test hook CFFT_TEST_FAIL_ALLOC=1.
 cfft_status_t dev_alloc(void** p, size_t bytes, const char* what) {
   *p = nullptr;
@@ -257,6 +263,35 @@ cfft_status_t check_plan(cfft_plan_t plan, int grid) {
   return CFFT_OK;
 }
 
+// Largest factor by which the Taylor recombination of eq. fftarry can
+// amplify the rounding of a transform over the table.  A transform of term
+// (a, b) is weighted by (gamma kx)^a (gamma ky)^b before it and by
+// Dx^a Dy^b / (a! b!) after it; with |k| <= k_max and |D| <= n pi / (2 k_max)
+// per axis the product is at most x^a y^b / (a! b!), x = gamma nx pi / 2,
+// y = gamma ny pi / 2, whatever the spectral span.  Summed over the terms:
+// sum_{c <= P} (x + y)^c / c! for the total-degree truncation, and
+// (sum_a x^a / a!)(sum_b y^b / b!) for the tensor truncation.  The parabolic
+// contour's ratio never exceeds gamma, so the same bound holds there.
+double taylor_amplification(const cfft_grid_desc_t& d) {
+  const double x = d.gamma * d.nx * M_PI / 2.0, y = d.gamma * d.ny * M_PI / 2.0;
+  auto poly = [&](double v) {
+    double s = 0.0, t = 1.0;
+    for (int c = 0; c <= d.order; ++c) {
+      if (c > 0) t *= v / c;
+      s += t;
+    }
+    return s;
+  };
+  return d.truncation == CFFT_TRUNC_TENSOR ? poly(x) * poly(y) : poly(x + y);
+}
+
+// Mixed grids run their transforms in FP32 up to this amplification and in
+// FP64 (on the same FP32-stored data) beyond it.  Measured FP32-transform
+// errors against the FP64 oracle: <= 5.4e-7 up to an amplification of 4.4e3
+// (every mixed workload up to 2048-point axes), 1.1e-5 at 2.1e4 (a
+// 4096-point axis), above the mixed path's 1e-5 target.
+constexpr double kFp32MaxAmplification = 8000.0;
+
 PassParams pass_params(const GridState& gs) {
   PassParams p;
   p.x = gs.x;
@@ -268,6 +303,7 @@ PassParams pass_params(const GridState& gs) {
   p.beta_end = gs.d.beta_end;
   p.band = gs.band;
   p.precision = gs.d.precision;
+  p.hi_compute = gs.d.precision == CFFT_MIXED && taylor_amplification(gs.d) > kFp32MaxAmplification ? 1 : 0;
   p.col_narrow = 0;
   return p;
 }
@@ -691,16 +727,20 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   const size_t n = (size_t)gs.x.n * gs.y.n;
   const size_t cbytes = pp.precision == CFFT_FP64 ? 16 : 8;
   const size_t per_pair = (size_t)inter_slots(pp) * n * cbytes;
-  const long long limit_mb = env_ll("CFFT_WORKSPACE_MB", 16384);
-  long long chunk = std::max<long long>(1, (limit_mb << 20) / (long long)per_pair);
+  long long chunk = std::max<long long>(1, (workspace_limit_mb() << 20) / (long long)per_pair);
   chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
   const long long forced = env_ll("CFFT_PAIR_CHUNK", 0);
   if (forced > 0) chunk = std::min<long long>(chunk, forced);
   hipStream_t s = (hipStream_t)stream;
-  st = ensure_ws(&plan->ws, &plan->ws_bytes, per_pair * (size_t)chunk, "pass workspace");
+  // a workspace that does not fit the device's free memory takes fewer pairs per launch
+  while ((st = ensure_ws(&plan->ws, &plan->ws_bytes, per_pair * (size_t)chunk, "pass workspace")) == CFFT_ERR_ALLOC &&
+         chunk > 1 && !env_flag("CFFT_TEST_FAIL_ALLOC"))
+    chunk /= 2;
   if (st != CFFT_OK) return st;
-  const void* twx = pp.precision == CFFT_FP64 ? gs.tw64x : gs.tw32x;
-  const void* twy = pp.precision == CFFT_FP64 ? gs.tw64y : gs.tw32y;
+  // twiddles in the transforms' compute precision
+  const bool c64 = pp.precision == CFFT_FP64 || pp.hi_compute;
+  const void* twx = c64 ? gs.tw64x : gs.tw32x;
+  const void* twy = c64 ? gs.tw64y : gs.tw32y;
   std::vector<int> pm(npairs), pn(npairs);
   for (int i = 0; i < npairs; ++i) {
     pm[i] = pairs[2 * i];
@@ -777,7 +817,13 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
         for (int l : {1, 2}) {
           if (l == 2 && !lanes_ok(c)) continue;
           if (l == 2 && per_pair * (size_t)c * 2 > plan->ws_bytes) {
+            // a two-lane workspace that does not fit leaves the candidate out
             st = ensure_ws(&plan->ws, &plan->ws_bytes, per_pair * (size_t)c * 2, "pass workspace");
+            if (st == CFFT_ERR_ALLOC) {
+              st = ensure_ws(&plan->ws, &plan->ws_bytes, per_pair * (size_t)chunk, "pass workspace");
+              if (st != CFFT_OK) return st;
+              continue;
+            }
             if (st != CFFT_OK) return st;
           }
           for (int w : {0, 1}) {
@@ -966,8 +1012,7 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   const PassParams pp = pass_params(gs);
   const size_t n = (size_t)gs.x.n * gs.y.n;
   const size_t per_pair = (size_t)inter_slots(pp) * n * 16 + n * 16;   // intermediates + gH
-  const long long limit_mb = env_ll("CFFT_WORKSPACE_MB", 16384);
-  long long chunk = std::max<long long>(1, (limit_mb << 20) / (long long)per_pair);
+  long long chunk = std::max<long long>(1, (workspace_limit_mb() << 20) / (long long)per_pair);
   chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
   const long long forced = env_ll("CFFT_PAIR_CHUNK", 0);
   if (forced > 0) chunk = std::min<long long>(chunk, forced);

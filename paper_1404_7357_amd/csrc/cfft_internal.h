@@ -9,10 +9,7 @@ namespace cfft {
 
 constexpr int kMaxPairsPerLaunch = 64;
 constexpr int kMaxOrder = 7;
-#ifndef CFFT_SPEC_PCHUNK
-#define CFFT_SPEC_PCHUNK 4
-#endif
-constexpr int kSpecPChunk = CFFT_SPEC_PCHUNK;   // spectra kernel: centres per unrolled chunk
+constexpr int kSpecPChunk = 4;   // spectra kernel: centres per unrolled chunk
 
 // Sampling of one axis: k(n) = k0 + n dk, D(j) = d0 + j dd.
 struct Axis {
@@ -71,7 +68,8 @@ struct PassParams {
   Axis x, y;
   double gamma;
   int order;
-  int precision;      // 0 FP64, 1 MIXED
+  int precision;      // 0 FP64, 1 MIXED (storage precision)
+  int hi_compute;     // MIXED only: transforms in FP64 on the FP32-stored data
   int tensor;         // 1: tensor-product truncation (one intermediate per pair)
   int parabolic;      // 1: parabolic contour (per-sample ratio; N_t row transforms)
   double beta_end;
@@ -134,8 +132,7 @@ hipError_t launch_adj_spectra(const Axis& x, const Axis& y, double gamma, const 
                               const double2* utab, const double2* gspec, int nmbf, double2* rowacc,
                               double2* gq, hipStream_t s);
 
-// Sizes of the column tile and of the adjoint scratch (host helpers).
-int col_tile(int ny, int precision);
+// Size of the adjoint scratch (host helper).
 size_t adj_spectra_scratch(const Axis& y, const GeomDevice& geo, int nmbf);
 
 }  // namespace cfft

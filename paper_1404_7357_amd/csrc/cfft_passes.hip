@@ -19,8 +19,16 @@
 // each wave loads whole C-column row segments of S_{P-b} straight into
 // registers, FFTs every column along n2 (LDS exchanges), accumulates
 // Dy^b/b! times the result in FP64 and writes the scaled table.
-// The FFT precision is FP64 (CFFT_FP64) or FP32 (CFFT_MIXED); every
-// recombination weight and accumulator is FP64.
+//
+// Precision.  Every pass kernel has a storage type Vs (spectra,
+// intermediates and table in HBM: complex128 on FP64 grids, complex64 on
+// mixed grids) and a compute type Vc (butterflies, twiddles and LDS
+// exchanges of the transforms).  FP64 grids compute in FP64.  Mixed grids
+// compute in FP32, except where the Taylor recombination would amplify FP32
+// rounding past the mixed path's error target (long transforms): there they
+// compute in FP64 on the FP32-stored data, so the HBM traffic stays that of
+// the mixed path.  The integrand, the Taylor weights, the partial sums S_c
+// and the column accumulators are FP64 in every case.
 #include <algorithm>
 #include <map>
 #include <type_traits>
@@ -29,103 +37,29 @@
 #include "cfft_device.h"
 #include "cfft_internal.h"
 
-// Scheduling knobs (compile-time): minimum waves per SIMD requested from the
-// register allocator for the two passes (0 = compiler's choice; the FP32
-// column pass asks for 4, i.e. two 512-thread blocks per CU instead of one,
-// at the price of a small spill: -17% at 512^2; so do the FP32 rows of 1024
-// points and more: -9% on the frequency sweep, -12% at 4096^2, while shorter
-// rows lose from the spill), whether the
-// column pass fetches the next term's column while transforming the current
-// one (costs one register array), whether it writes the table with
-// non-temporal stores (the table is not read again by this path, and keeping
-// it out of the caches leaves them to the intermediates and inputs; 2: only
-// tiles that store whole 64-byte row pieces, since narrower pieces streamed
-// out one by one become partial-line writes, while through the cache the
-// neighbouring tiles complete the line first: -40% column-pass time at
-// 4096^2 FP32), whether
-// it reads the intermediates with non-temporal loads (they then bypass the
-// memory-side cache that still holds them from the row pass: slower), and
-// the widest column tile in bytes per row (FP64 and FP32 tiles).
-#ifndef CFFT_ROW_MIN_WAVES
-#define CFFT_ROW_MIN_WAVES 0
-#endif
-#ifndef CFFT_ROW_MIN_WAVES_F32
-#define CFFT_ROW_MIN_WAVES_F32 4
-#endif
-#ifndef CFFT_COL_PREFETCH
-#define CFFT_COL_PREFETCH 0
-#endif
-#ifndef CFFT_COL_NT_STORE
-#define CFFT_COL_NT_STORE 2
-#endif
-#ifndef CFFT_COL_NT_LOAD
-#define CFFT_COL_NT_LOAD 0
-#endif
-#ifndef CFFT_ROW_PAD_SHIFT
-#define CFFT_ROW_PAD_SHIFT 0
-#endif
-#ifndef CFFT_COL_LDP_EXTRA
-#define CFFT_COL_LDP_EXTRA 4
-#endif
-#ifndef CFFT_COL_WIDE_FP32
-#define CFFT_COL_WIDE_FP32 1
-#endif
-#ifndef CFFT_COL_MIN_WAVES
-#define CFFT_COL_MIN_WAVES 0
-#endif
-#ifndef CFFT_COL_MIN_WAVES_F32
-#define CFFT_COL_MIN_WAVES_F32 4
-#endif
-#ifndef CFFT_COL_ROW_BYTES_F32
-#define CFFT_COL_ROW_BYTES_F32 64
-#endif
-#ifndef CFFT_COL_ROW_BYTES
-#define CFFT_COL_ROW_BYTES 64
-#endif
-
-// Row pass: rebuild the per-point factors and store addresses in every term
-// (1), let the compiler keep them live across the term loop (0), or rebuild
-// them only in the FP32 rows of 1024 points and more (2), whose kernels
-// otherwise spill at the 128 registers of their occupancy target (elsewhere
-// the rebuilt factors cost 3% of the FP64 row pass).
-#ifndef CFFT_ROW_OPAQUE_T
-#define CFFT_ROW_OPAQUE_T 2
-#endif
-
-// Points per thread of the FP32 column pass on columns of 4096 points, and
-// of the FP64 column pass on columns of 2048 and 4096 points.
-#ifndef CFFT_COL_R_F32_4096
-#define CFFT_COL_R_F32_4096 32
-#endif
-// (16 gives the FP64 columns four-column tiles too, but such a tile takes a
-// CU's whole LDS, so the column pass of one pair chunk can no longer overlap
-// the row pass of the next: slower on the 2048^2 zero-padded tables.)
-#ifndef CFFT_COL_R_F64_2048
-#define CFFT_COL_R_F64_2048 8
-#endif
-
 namespace cfft {
 
 // LDS padding of the row transforms: one pad slot per 2^row_pad<V>() elements
 // (16-byte elements: every 16; 8-byte elements: every 8).
-template <typename V> __host__ __device__ constexpr int row_pad() {
-  return CFFT_ROW_PAD_SHIFT > 0 ? CFFT_ROW_PAD_SHIFT : (sizeof(V) == 16 ? 4 : 3);
-}
+template <typename V> __host__ __device__ constexpr int row_pad() { return sizeof(V) == 16 ? 4 : 3; }
 
-// Minimum waves per SIMD requested for the row pass (1: no constraint); the
-// FP32 rows of 1024 points and more take CFFT_ROW_MIN_WAVES_F32.
-template <typename V, int N> constexpr int row_min_waves() {
-  return (sizeof(V) == 8 && N >= 1024) ? (CFFT_ROW_MIN_WAVES_F32 > 0 ? CFFT_ROW_MIN_WAVES_F32 : 1)
-                                       : (CFFT_ROW_MIN_WAVES > 0 ? CFFT_ROW_MIN_WAVES : 1);
-}
+// Minimum waves per SIMD requested for the row pass (1: no constraint).  The
+// FP32 rows of 1024 points and more take 4 waves per SIMD at the price of a
+// small spill (-9% on the frequency sweep); shorter rows lose from it.
+template <typename Vc, int N> constexpr int row_min_waves() { return (sizeof(Vc) == 8 && N >= 1024) ? 4 : 1; }
 
-// Whether the row pass rebuilds its per-point factors in every term.
-template <typename V, int N> constexpr bool row_opaque_t() {
-  return CFFT_ROW_OPAQUE_T == 1 || (CFFT_ROW_OPAQUE_T == 2 && sizeof(V) == 8 && N >= 1024);
-}
+// Whether the row pass rebuilds its per-point factors and store addresses in
+// every term (from an opaque copy of the thread index) instead of keeping
+// them live across the term loop: only in the FP32 rows of 1024 points and
+// more, whose kernels otherwise spill at the 128 registers of their
+// occupancy target (elsewhere the rebuilt factors cost 3%).
+template <typename Vc, int N> constexpr bool row_opaque_t() { return sizeof(Vc) == 8 && N >= 1024; }
 
-template <int N> struct RowCfg {
-  static constexpr int R = 8;
+// Points per thread of the row transforms (16 points per thread in the
+// FP64 rows of 4096 points take 256 registers and one wave per SIMD).
+template <typename Vc, int N> __host__ __device__ constexpr int row_r() { return 8; }
+
+template <int N, int R> struct RowCfg {
   static constexpr int T = N / R;
   static constexpr int ROWS = T >= 64 ? 1 : 64 / T;
   static constexpr int THREADS = ROWS * T;
@@ -137,9 +71,9 @@ struct RowArgs {
   int parabolic;                // per-sample contour ratio (see row_terms_general)
   double ky0, dky, beta_end;
   const double2* g;
-  const void* spec;   // V elements: complex128 (FP64 grids) or complex64 (mixed)
-  void* inter;
-  const void* tw;
+  const void* spec;   // Vs elements
+  void* inter;        // Vs elements
+  const void* tw;     // Vc elements
   int nx, ny, order, npairs;
   double kx0, dkx, x0, ddx, gamma;
   double rinv[kMaxOrder + 1];   // 1/i (the Taylor weights need no division)
@@ -164,11 +98,11 @@ __device__ __forceinline__ double2 contour_weight(const Args& a, double kx, doub
 // stores it in slot b; the column pass then applies no ky factor.  That is
 // (P+1)(P+2)/2 row transforms, the N_t of eq. fftarry.  f already carries
 // s(n1) and the contour weight.
-template <typename V, int N, int R, bool WAVE, int PS, typename Args>
-__device__ __forceinline__ void row_terms_general(const Args& a, const V (&f)[R], V* lds, const V* ltw, int t, int n2,
-                                                  V* dst0, size_t slot_stride, bool store) {
+template <typename Vs, typename Vc, int N, int R, bool WAVE, int PS, typename Args>
+__device__ __forceinline__ void row_terms_general(const Args& a, const Vc (&f)[R], Vc* lds, const Vc* ltw, int t,
+                                                  int n2, Vs* dst0, size_t slot_stride, bool store) {
   constexpr int T = N / R;
-  using Rl = typename real_of<V>::type;
+  using Rc = typename real_of<Vc>::type;
   const double ky = a.ky0 + n2 * a.dky;
   double gkx[R], gky[R];
 #pragma unroll
@@ -184,15 +118,15 @@ __device__ __forceinline__ void row_terms_general(const Args& a, const V (&f)[R]
 #pragma unroll
     for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
     for (int ao = 0; ao + b <= a.order; ++ao) {
-      V x[R];
+      Vc x[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         double w = 1.0;
         for (int i = 0; i < ao; ++i) w *= gkx[r];
         for (int i = 0; i < b; ++i) w *= gky[r];
-        x[r] = cscale(f[r], (Rl)w);
+        x[r] = cscale(f[r], (Rc)w);
       }
-      fft_forward<V, N, R, WAVE, PS>(x, lds, ltw, t);
+      fft_forward<Vc, N, R, WAVE, PS>(x, lds, ltw, t);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const double dx = a.x0 + (t + T * r) * a.ddx;
@@ -204,19 +138,19 @@ __device__ __forceinline__ void row_terms_general(const Args& a, const V (&f)[R]
     }
     if (store) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst0[(size_t)b * slot_stride + t + T * r] = from_d<V>(S[r]);
+      for (int r = 0; r < R; ++r) dst0[(size_t)b * slot_stride + t + T * r] = from_d<Vs>(S[r]);
     }
   }
 }
 
-template <typename V, int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) row_pass_kernel(RowArgs a) {
-  using Cfg = RowCfg<N>;
-  constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
-  using Rl = typename real_of<V>::type;
-  __shared__ V lds[ROWS * lds_len<row_pad<V>()>(N)];
-  __shared__ V ltw[TwLds<N>::LEN];
-  load_twiddles<V, N>(ltw, (const V*)a.tw, threadIdx.x, Cfg::THREADS);
+template <typename Vs, typename Vc, int N, int R>
+__global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>())) row_pass_kernel(RowArgs a) {
+  using Cfg = RowCfg<N, R>;
+  constexpr int T = Cfg::T, ROWS = Cfg::ROWS;
+  using Rc = typename real_of<Vc>::type;
+  __shared__ Vc lds[ROWS * lds_len<row_pad<Vc>()>(N)];
+  __shared__ Vc ltw[TwLds<N>::LEN];
+  load_twiddles<Vc, N>(ltw, (const Vc*)a.tw, threadIdx.x, Cfg::THREADS);
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int pair = lid % a.npairs;
   const int rb = lid / a.npairs;
@@ -229,9 +163,9 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) r
   const bool valid = n2 < a.ny - row0;
   const size_t plane = (size_t)a.nx * a.ny;
   const int m = a.pm[pair], n = a.pn[pair];
-  V* inter = (V*)a.inter;
+  Vs* inter = (Vs*)a.inter;
 
-  V f[R];
+  Vc f[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int n1 = t + T * r;
@@ -239,7 +173,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) r
     if (valid && (!a.band || in_band(n1, N))) {
       const size_t idx = (size_t)n2 * N + n1;
       const double2 gxx = a.g[idx], gxy = a.g[plane + idx], gyy = a.g[2 * plane + idx];
-      const V* sp = (const V*)a.spec;
+      const Vs* sp = (const Vs*)a.spec;
       const double2 mx = to_d(sp[((size_t)m * 4 + 0) * plane + idx]);
       const double2 my = to_d(sp[((size_t)m * 4 + 1) * plane + idx]);
       const double2 mxh = to_d(sp[((size_t)n * 4 + 2) * plane + idx]);
@@ -248,15 +182,15 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) r
       if (n1 & 1) h = make_double2(-h.x, -h.y);
       if (a.parabolic) h = cmul(h, contour_weight(a, a.kx0 + n1 * a.dkx, a.ky0 + n2 * a.dky));
     }
-    f[r] = from_d<V>(h);
+    f[r] = from_d<Vc>(h);
   }
-  V* my_lds = lds + grp * lds_len<row_pad<V>()>(N);
+  Vc* my_lds = lds + grp * lds_len<row_pad<Vc>()>(N);
   __syncthreads();   // twiddle tables ready
   if (a.parabolic) {
     const size_t slot = (size_t)a.ny * N;
-    row_terms_general<V, N, R, (T <= 64), row_pad<V>()>(a, f, my_lds, ltw, t, valid ? n2 : 0,
-                                                         inter + ((size_t)pair * (a.order + 1) * a.ny + (valid ? n2 : 0)) * N,
-                                                         slot, valid);
+    row_terms_general<Vs, Vc, N, R, (T <= 64), row_pad<Vc>()>(
+        a, f, my_lds, ltw, t, valid ? n2 : 0, inter + ((size_t)pair * (a.order + 1) * a.ny + (valid ? n2 : 0)) * N,
+        slot, valid);
     return;
   }
   double2 S[R];
@@ -266,21 +200,21 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) r
     // opaque copy of t: the per-point factors and store addresses are
     // rebuilt per term instead of being hoisted and held across the loop
     int tb = t;
-    if constexpr (row_opaque_t<V, N>()) asm volatile("" : "+v"(tb));
+    if constexpr (row_opaque_t<Vc, N>()) asm volatile("" : "+v"(tb));
     if (ao > 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int n1 = tb + T * r;
-        f[r] = cscale(f[r], (Rl)(a.gamma * (a.kx0 + n1 * a.dkx)));
+        f[r] = cscale(f[r], (Rc)(a.gamma * (a.kx0 + n1 * a.dkx)));
       }
     }
-    V x[R];
+    Vc x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = f[r];
-    fft_forward<V, N, R, (T <= 64), row_pad<V>()>(x, my_lds, ltw, t);
+    fft_forward<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, my_lds, ltw, t);
     const bool keep = !a.tensor || ao == a.order;
     const int nsl = a.tensor ? 1 : a.order + 1;
-    V* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + (valid ? n2 : 0)) * N;
+    Vs* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + (valid ? n2 : 0)) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       // Dx(j1)^a / a!, rebuilt per term (cheaper than keeping it live)
@@ -289,7 +223,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<V, N>())) r
       for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
-      if (valid && keep) dst[tb + T * r] = from_d<V>(S[r]);
+      if (valid && keep) dst[tb + T * r] = from_d<Vs>(S[r]);
     }
   }
 }
@@ -307,9 +241,9 @@ struct RowGArgs {
   int parabolic;
   double ky0, dky, beta_end;
   const double2* g;
-  const void* spec;   // V elements
-  void* inter;
-  const void* tw;
+  const void* spec;   // Vs elements
+  void* inter;        // Vs elements
+  const void* tw;     // Vc elements
   int nx, ny, order, ngroups;
   double kx0, dkx, x0, ddx, gamma;
   double rinv[kMaxOrder + 1];
@@ -326,15 +260,15 @@ template <int N, int NPW> struct RowGCfg {
   static constexpr int THREADS = NPW * T;
 };
 
-template <typename V, int N, int NPW>
-__global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pass_grouped_kernel(RowGArgs a) {
+template <typename Vs, typename Vc, int N, int NPW>
+__global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<Vc, N>())) row_pass_grouped_kernel(RowGArgs a) {
   using Cfg = RowGCfg<N, NPW>;
   constexpr int T = Cfg::T, R = Cfg::R;
-  using Rl = typename real_of<V>::type;
+  using Rc = typename real_of<Vc>::type;
   __shared__ double2 ax[N], ay[N];
-  __shared__ V lds[NPW * lds_len<row_pad<V>()>(N)];
-  __shared__ V ltw[TwLds<N>::LEN];
-  load_twiddles<V, N>(ltw, (const V*)a.tw, threadIdx.x, Cfg::THREADS);
+  __shared__ Vc lds[NPW * lds_len<row_pad<Vc>()>(N)];
+  __shared__ Vc ltw[TwLds<N>::LEN];
+  load_twiddles<Vc, N>(ltw, (const Vc*)a.tw, threadIdx.x, Cfg::THREADS);
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int grp = lid % a.ngroups;
   const int n2 = lid / a.ngroups + (a.band ? a.ny / 4 : 0);   // zero-padded grid: band rows only
@@ -343,14 +277,15 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pa
   const size_t plane = (size_t)a.nx * a.ny;
   const int m = a.gm[grp];
   const size_t row = (size_t)n2 * N;
+  const Vs* sp = (const Vs*)a.spec;
   for (int i = threadIdx.x; i < N; i += Cfg::THREADS) {
     if (a.band && !in_band(i, N)) {
       ax[i] = ay[i] = make_double2(0.0, 0.0);
       continue;
     }
     const double2 gxx = a.g[row + i], gxy = a.g[plane + row + i], gyy = a.g[2 * plane + row + i];
-    const double2 mx = to_d(((const V*)a.spec)[((size_t)m * 4 + 0) * plane + row + i]);
-    const double2 my = to_d(((const V*)a.spec)[((size_t)m * 4 + 1) * plane + row + i]);
+    const double2 mx = to_d(sp[((size_t)m * 4 + 0) * plane + row + i]);
+    const double2 my = to_d(sp[((size_t)m * 4 + 1) * plane + row + i]);
     double2 vx = cfma(cmul(mx, gxx), my, gxy);
     double2 vy = cfma(cmul(mx, gxy), my, gyy);
     if (i & 1) {
@@ -372,48 +307,45 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pa
   }
   const int pair = active ? a.gpair[a.gfirst[grp] + w] : 0;
   const int n = a.pn[pair];
-  V f[R];
+  Vc f[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int n1 = t + T * r;
     double2 h = make_double2(0.0, 0.0);
     if (active && (!a.band || in_band(n1, N))) {
-      const double2 mxh = to_d(((const V*)a.spec)[((size_t)n * 4 + 2) * plane + row + n1]);
-      const double2 myh = to_d(((const V*)a.spec)[((size_t)n * 4 + 3) * plane + row + n1]);
+      const double2 mxh = to_d(sp[((size_t)n * 4 + 2) * plane + row + n1]);
+      const double2 myh = to_d(sp[((size_t)n * 4 + 3) * plane + row + n1]);
       h = cfma(cmul(ax[n1], mxh), ay[n1], myh);
     }
-    f[r] = from_d<V>(h);
+    f[r] = from_d<Vc>(h);
   }
-  V* my_lds = lds + w * lds_len<row_pad<V>()>(N);
-  V* inter = (V*)a.inter;
+  Vc* my_lds = lds + w * lds_len<row_pad<Vc>()>(N);
+  Vs* inter = (Vs*)a.inter;
   if (a.parabolic) {
-    row_terms_general<V, N, R, (T <= 64), row_pad<V>()>(a, f, my_lds, ltw, t, n2,
-                                                         inter + ((size_t)pair * (a.order + 1) * a.ny + n2) * N,
-                                                         (size_t)a.ny * N, active);
+    row_terms_general<Vs, Vc, N, R, (T <= 64), row_pad<Vc>()>(
+        a, f, my_lds, ltw, t, n2, inter + ((size_t)pair * (a.order + 1) * a.ny + n2) * N, (size_t)a.ny * N, active);
     return;
   }
   double2 S[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
   for (int ao = 0; ao <= a.order; ++ao) {
-    // opaque copy of t: the per-point factors and store addresses are
-    // rebuilt per term instead of being hoisted and held across the loop
     int tb = t;
-    if constexpr (row_opaque_t<V, N>()) asm volatile("" : "+v"(tb));
+    if constexpr (row_opaque_t<Vc, N>()) asm volatile("" : "+v"(tb));
     if (ao > 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int n1 = tb + T * r;
-        f[r] = cscale(f[r], (Rl)(a.gamma * (a.kx0 + n1 * a.dkx)));
+        f[r] = cscale(f[r], (Rc)(a.gamma * (a.kx0 + n1 * a.dkx)));
       }
     }
-    V x[R];
+    Vc x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = f[r];
-    fft_forward<V, N, R, (T <= 64), row_pad<V>()>(x, my_lds, ltw, t);
+    fft_forward<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, my_lds, ltw, t);
     const bool keep = !a.tensor || ao == a.order;
     const int nsl = a.tensor ? 1 : a.order + 1;
-    V* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + n2) * N;
+    Vs* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + n2) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double dx = a.x0 + (tb + T * r) * a.ddx;
@@ -421,7 +353,7 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<V, N>())) row_pa
       for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
-      if (active && keep) dst[tb + T * r] = from_d<V>(S[r]);
+      if (active && keep) dst[tb + T * r] = from_d<Vs>(S[r]);
     }
   }
 }
@@ -431,45 +363,68 @@ struct ColArgs {
   int parabolic;   // term b reads slot b and carries no (gamma ky)^b factor
   int band;     // x2 zero-padded grid: rows outside [N/4, 3N/4) are zero and not read
   int narrow;   // tiles of half the default width (an autotuner candidate)
-  const void* inter;
-  void* z;
-  const void* tw;
+  const void* inter;   // Vs elements
+  void* z;             // Vs elements
+  const void* tw;      // Vc elements
   int nx, ny, order, npairs;
   double ky0, dky, y0, ddy, gamma;
   double2 scale;   // K sigma W
   double rinv[kMaxOrder + 1];
 };
 
-// Minimum waves per SIMD requested for the column pass (1: no constraint).
-// The 32-point tiles (512 threads, 256 when narrow) take the register
-// budget of two waves per SIMD: a four-column tile's LDS fills the CU, so
-// one block (two waves per SIMD) is all that runs there anyway.
-template <typename V, int R> constexpr int col_min_waves() {
-  return R == 32 ? 2
-         : sizeof(V) == 8 ? (CFFT_COL_MIN_WAVES_F32 > 0 ? CFFT_COL_MIN_WAVES_F32 : 1)
-                          : (CFFT_COL_MIN_WAVES > 0 ? CFFT_COL_MIN_WAVES : 1);
-}
+// Column-pass tile: C adjacent columns per block and R points per thread of
+// each column transform.  The widest C that keeps a block within 64-byte row
+// pieces, its LDS budget (80 KiB: two blocks per CU; 152 KiB with more than
+// 8 points per thread: one block) and 512 threads (1024 for FP32 transforms
+// of 2048 points and more).
+template <typename Vs, typename Vc, int N> struct ColShape {
+  static constexpr int lds_per_col() { return (lds_len(N) + 4) * (int)sizeof(Vc); }
+  // FP64 transforms of 4096 points: two-column tiles of 8 points per thread
+  // (1024 threads, one block per CU).  Measured on the 4096^2 table against
+  // one-column tiles of 8 or 16 points per thread and two-column tiles of 16,
+  // each with and without loading the next term during the transform, it
+  // was the fastest in both storage precisions (one-column tiles move 16-byte
+  // row pieces; 16 points per thread leave one wave per SIMD).
+  static constexpr bool wide4096 = sizeof(Vc) == 16 && N >= 4096;
+  static constexpr int R = wide4096 ? 8 : (sizeof(Vc) == 8 && N >= 4096) ? 16 : 8;
+  static constexpr int pick_c() {
+    if (wide4096) return 2;
+    int c = 64 / (int)sizeof(Vs);
+    const int max_threads = (sizeof(Vc) == 8 && N >= 2048 && R == 8) ? 1024 : 512;
+    const int cap = R > 8 ? 155648 : 81920;
+    while (c > 1 && (c * lds_per_col() > cap || c * (N / R) > max_threads)) c /= 2;
+    return c;
+  }
+  static constexpr int C = pick_c();
+};
 
-// Column-pass block shape.  Thread tid works on column c = tid % C of the
-// tile at transform position t = tid / C, holding R points at stride
-// T = N/R.  A wave therefore covers 64/C consecutive rows of all C columns, so
-// every global load and store moves whole C*s-byte row segments (128 B when
-// C*s = 128) straight between HBM and registers; LDS is used only for the
-// FFT exchanges (one region of LDP entries per column).
+// Minimum waves per SIMD requested for the column pass (1: no constraint).
+// Tiles of more than 8 points per thread fill a CU's LDS with one block, so
+// they take the register budget of that block; the FP32 transforms of 8
+// points take 4 waves per SIMD (two 512-thread blocks per CU) at the price
+// of a small spill (-17% at 512^2).
+template <typename Vc, int R> constexpr int col_min_waves() { return (sizeof(Vc) == 8 && R == 8) ? 4 : 1; }
+
 template <int N, int C, int R> struct ColCfg {
   static constexpr int T = N / R;
   static constexpr int THREADS = C * T;
-  static constexpr int LDP = lds_len(N) + CFFT_COL_LDP_EXTRA;
+  static constexpr int LDP = lds_len(N) + 4;
 };
 
-template <typename V, int N, int C, int R>
-__global__ void __launch_bounds__(C * (N / R), (col_min_waves<V, R>())) col_pass_kernel(ColArgs a) {
+// Column-pass block.  Thread tid works on column c = tid % C of the tile at
+// transform position t = tid / C, holding R points at stride T = N/R.  A
+// wave therefore covers 64/C consecutive rows of all C columns, so every
+// global load and store moves whole C-column row segments straight between
+// HBM and registers; LDS is used only for the FFT exchanges (one region of
+// LDP entries per column).
+template <typename Vs, typename Vc, int N, int C, int R>
+__global__ void __launch_bounds__(C * (N / R), (col_min_waves<Vc, R>())) col_pass_kernel(ColArgs a) {
   using Cfg = ColCfg<N, C, R>;
   constexpr int T = Cfg::T, LDP = Cfg::LDP;
-  using Rl = typename real_of<V>::type;
-  __shared__ V lds[C * LDP];
-  __shared__ V ltw[TwLds<N>::LEN];
-  load_twiddles<V, N>(ltw, (const V*)a.tw, threadIdx.x, Cfg::THREADS);
+  using Rc = typename real_of<Vc>::type;
+  __shared__ Vc lds[C * LDP];
+  __shared__ Vc ltw[TwLds<N>::LEN];
+  load_twiddles<Vc, N>(ltw, (const Vc*)a.tw, threadIdx.x, Cfg::THREADS);
   const int ntile = a.nx / C;
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = lid % ntile;
@@ -479,111 +434,70 @@ __global__ void __launch_bounds__(C * (N / R), (col_min_waves<V, R>())) col_pass
   const int j1 = tile * C + c;
   const size_t plane = (size_t)N * a.nx;
   const int nsl = a.tensor ? 1 : a.order + 1;
-  const V* col0 = (const V*)a.inter + (size_t)pair * nsl * plane + j1;
+  const Vs* col0 = (const Vs*)a.inter + (size_t)pair * nsl * plane + j1;
 
-  // the recombination sums in FP64, except in the FP32 tiles of 16 or 32
-  // points per thread, where FP64 accumulators do not fit the registers (at
-  // 32 points: 83 spilled; FP32 ones spill 7)
-  using Acc = typename std::conditional<(R > 8), V, double2>::type;
-  using Ra = typename real_of<Acc>::type;
-  Acc Z[R];
+  double2 Z[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) Z[r] = from_d<Acc>(make_double2(0.0, 0.0));
-  // term b reads S_{P-b}; the next term's column is fetched while this one
-  // is transformed.  The weights s(n2)(gamma ky)^b and Dy^b/b! are rebuilt
-  // per term (a few multiplies) rather than kept live in registers.
+  for (int r = 0; r < R; ++r) Z[r] = make_double2(0.0, 0.0);
+  // Term b reads S_{P-b} (total degree), S'_b (parabolic) or S_P (tensor).
   // n2 = t + T r lies in the band [N/4, 3N/4) of a zero-padded grid exactly
   // when 2R/8 <= r < 6R/8; outside it the intermediates are zero (never
-  // written by the row pass) and are not read
-  auto load_term = [&](const V* src, int r, int tt) -> V {
-    if (a.band && (8 * r < 2 * R || 8 * r >= 6 * R)) return from_d<V>(make_double2(0.0, 0.0));
-    if constexpr (CFFT_COL_NT_LOAD) return load_nt(src + (size_t)(tt + T * r) * a.nx);
-    return src[(size_t)(tt + T * r) * a.nx];
-  };
-  V nxt[R];
-  if constexpr (CFFT_COL_PREFETCH) {
-    const V* src = col0 + (size_t)(a.tensor || a.parabolic ? 0 : a.order) * plane;
+  // written by the row pass) and are not read.
+  auto load_term = [&](Vs(&dst)[R], int b, int tt) {
+    const Vs* src = col0 + (size_t)(a.tensor ? 0 : a.parabolic ? b : a.order - b) * plane;
 #pragma unroll
-    for (int r = 0; r < R; ++r) nxt[r] = load_term(src, r, t);
-  }
-  V* my_lds = lds + c * LDP;
+    for (int r = 0; r < R; ++r) {
+      if (a.band && (8 * r < 2 * R || 8 * r >= 6 * R)) dst[r] = from_d<Vs>(make_double2(0.0, 0.0));
+      else dst[r] = src[(size_t)(tt + T * r) * a.nx];
+    }
+  };
+  Vs nxt[R];
+  Vc* my_lds = lds + c * LDP;
   __syncthreads();   // twiddle tables ready
   for (int b = 0; b <= a.order; ++b) {
-    V x[R];
     // an opaque copy of t keeps the per-point weights and addresses inside
     // the term loop (hoisted, they would stay live in registers across it)
     int tb = t;
     asm volatile("" : "+v"(tb));
-    if constexpr (!CFFT_COL_PREFETCH) {
-      const V* src = col0 + (size_t)(a.tensor ? 0 : a.parabolic ? b : a.order - b) * plane;
-#pragma unroll
-      for (int r = 0; r < R; ++r) nxt[r] = load_term(src, r, tb);
-    }
+    load_term(nxt, b, tb);
+    Vc x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+      // s(n2) (gamma ky)^b, rebuilt per term (a few multiplies)
       const int n2 = tb + T * r;
-      const Rl gk = (Rl)(a.gamma * (a.ky0 + n2 * a.dky));
-      Rl w = (n2 & 1) ? (Rl)-1 : (Rl)1;
-      if (!a.parabolic)
+      double w = (n2 & 1) ? -1.0 : 1.0;
+      if (!a.parabolic) {
+        const double gk = a.gamma * (a.ky0 + n2 * a.dky);
         for (int i = 0; i < b; ++i) w *= gk;
-      x[r] = cscale(nxt[r], w);
+      }
+      x[r] = cscale(from_d<Vc>(to_d(nxt[r])), (Rc)w);
     }
-    if (CFFT_COL_PREFETCH && b < a.order) {
-      const V* src = col0 + (size_t)(a.tensor ? 0 : a.parabolic ? b + 1 : a.order - b - 1) * plane;
-#pragma unroll
-      for (int r = 0; r < R; ++r) nxt[r] = load_term(src, r, tb);
-    }
-    fft_forward<V, N, R>(x, my_lds, ltw, t);
+    fft_forward<Vc, N, R>(x, my_lds, ltw, t);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j2 = tb + T * r;
       const double dy = a.y0 + j2 * a.ddy;
       double cf = 1.0;
       for (int i = 1; i <= b; ++i) cf *= dy * a.rinv[i];
-      const Acc xv = from_d<Acc>(to_d(x[r]));
-      Z[r].x += (Ra)cf * xv.x;
-      Z[r].y += (Ra)cf * xv.y;
+      const double2 xv = to_d(x[r]);
+      Z[r].x += cf * xv.x;
+      Z[r].y += cf * xv.y;
     }
   }
-  V* dst = (V*)a.z + (size_t)pair * plane + j1;
+  Vs* dst = (Vs*)a.z + (size_t)pair * plane + j1;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j2 = t + T * r;
-    double2 v = cmul(to_d(Z[r]), a.scale);
+    double2 v = cmul(Z[r], a.scale);
     if ((j1 + j2) & 1) v = make_double2(-v.x, -v.y);
     // streaming stores for whole 64-byte row pieces; narrower tiles store
-    // through the cache, where the neighbouring tiles' pieces complete a line
-    if constexpr (CFFT_COL_NT_STORE == 1 || (CFFT_COL_NT_STORE == 2 && C * sizeof(V) >= 64))
-      store_nt(dst + (size_t)j2 * a.nx, from_d<V>(v));
-    else dst[(size_t)j2 * a.nx] = from_d<V>(v);
+    // through the cache, where the neighbouring tiles' pieces complete a
+    // line before it is written back (streaming 16-32 byte pieces out one
+    // by one cost 40% more time at 4096^2)
+    if constexpr (C * sizeof(Vs) >= 64) store_nt(dst + (size_t)j2 * a.nx, from_d<Vs>(v));
+    else dst[(size_t)j2 * a.nx] = from_d<Vs>(v);
   }
 }
-
-// Points per thread of the column pass: 8, except on the columns whose LDS
-// tile would otherwise be one or two columns wide (FP32 columns of 4096
-// points; FP64 columns of 2048 and 4096 when CFFT_COL_R_F64_2048 asks for
-// it): there 16 or 32 points per thread keep a tile of four columns within
-// 512 threads and 152 KiB of LDS.
-__host__ __device__ constexpr int col_r(int ny, int bytes) {
-  return (bytes == 8 && ny >= 4096) ? CFFT_COL_R_F32_4096 : (bytes == 16 && ny >= 2048) ? CFFT_COL_R_F64_2048 : 8;
-}
-
-// Column tile width for r points per thread: as close to CFFT_COL_ROW_BYTES
-// of contiguous row data as an 80 KiB LDS tile (152 KiB when r > 8: one block
-// per CU) and 512 threads allow (1024-thread blocks cap a kernel at 128
-// VGPRs: the FP64 kernels would spill; the FP32 kernels of columns of 2048
-// and 4096 take 1024 threads when CFFT_COL_WIDE_FP32 is set).
-__host__ __device__ constexpr int col_tile_cr(int ny, int bytes, int r) {
-  int c = (bytes == 8 ? CFFT_COL_ROW_BYTES_F32 : CFFT_COL_ROW_BYTES) / bytes;
-  const int max_threads = (CFFT_COL_WIDE_FP32 && bytes == 8 && ny >= 2048) ? 1024 : 512;
-  const int lds_cap = r > 8 ? 155648 : 81920;
-  while (c > 1 && (c * (lds_len(ny) + CFFT_COL_LDP_EXTRA) * bytes > lds_cap || c * (ny / r) > max_threads)) c /= 2;
-  return c;
-}
-
-__host__ __device__ constexpr int col_tile_c(int ny, int bytes) { return col_tile_cr(ny, bytes, col_r(ny, bytes)); }
-
-int col_tile(int ny, int precision) { return col_tile_c(ny, precision == 0 ? 16 : 8); }
 
 // ------------------------------------------------ dispatch over sizes
 static void fill_rinv(double* r) {
@@ -591,32 +505,33 @@ static void fill_rinv(double* r) {
   for (int i = 1; i <= kMaxOrder; ++i) r[i] = 1.0 / i;
 }
 
-template <typename V, int N>
+template <typename Vs, typename Vc, int N>
 static hipError_t row_launch(const RowArgs& args, hipStream_t s) {
-  using Cfg = RowCfg<N>;
+  constexpr int R = row_r<Vc, N>();
+  using Cfg = RowCfg<N, R>;
   const int rows = args.band ? args.ny / 2 : args.ny;
   const int nblk = ((rows + Cfg::ROWS - 1) / Cfg::ROWS) * args.npairs;
-  hipLaunchKernelGGL((row_pass_kernel<V, N>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
+  hipLaunchKernelGGL((row_pass_kernel<Vs, Vc, N, R>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
   return hipGetLastError();
 }
 
-template <typename V, int N>
+template <typename Vs, typename Vc, int N>
 static hipError_t col_launch(const ColArgs& args, hipStream_t s) {
-  constexpr int C0 = col_tile_c(N, sizeof(V));
-  constexpr int R = col_r(N, sizeof(V));
+  using Sh = ColShape<Vs, Vc, N>;
+  constexpr int C0 = Sh::C, R = Sh::R;
   // the autotuner's alternative: tiles of half the width (more, smaller
   // blocks; shorter row pieces)
   if constexpr (C0 > 1) {
     if (args.narrow) {
       constexpr int C = C0 / 2;
       if (args.nx % C != 0) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((col_pass_kernel<V, N, C, R>), dim3((args.nx / C) * args.npairs),
+      hipLaunchKernelGGL((col_pass_kernel<Vs, Vc, N, C, R>), dim3((args.nx / C) * args.npairs),
                          dim3(ColCfg<N, C, R>::THREADS), 0, s, args);
       return hipGetLastError();
     }
   }
   if (args.nx % C0 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((col_pass_kernel<V, N, C0, R>), dim3((args.nx / C0) * args.npairs),
+  hipLaunchKernelGGL((col_pass_kernel<Vs, Vc, N, C0, R>), dim3((args.nx / C0) * args.npairs),
                      dim3(ColCfg<N, C0, R>::THREADS), 0, s, args);
   return hipGetLastError();
 }
@@ -637,7 +552,7 @@ static hipError_t col_launch(const ColArgs& args, hipStream_t s) {
 
 // Grouped launch: pairs are grouped by testing MBF into groups of <= NPW
 // (4 when every MBF's pair count is a multiple of 4, else 2).
-template <typename V, int N>
+template <typename Vs, typename Vc, int N>
 static hipError_t rowg_launch(const RowArgs& ra, hipStream_t s) {
   RowGArgs a;
   a.g = ra.g;
@@ -686,23 +601,31 @@ static hipError_t rowg_launch(const RowArgs& ra, hipStream_t s) {
   a.ngroups = ng;
   const int nblk = ng * (ra.band ? ra.ny / 2 : ra.ny);
   if (npw == 4) {
-    hipLaunchKernelGGL((row_pass_grouped_kernel<V, N, 4>), dim3(nblk), dim3(RowGCfg<N, 4>::THREADS), 0, s, a);
+    hipLaunchKernelGGL((row_pass_grouped_kernel<Vs, Vc, N, 4>), dim3(nblk), dim3(RowGCfg<N, 4>::THREADS), 0, s, a);
   } else {
-    hipLaunchKernelGGL((row_pass_grouped_kernel<V, N, 2>), dim3(nblk), dim3(RowGCfg<N, 2>::THREADS), 0, s, a);
+    hipLaunchKernelGGL((row_pass_grouped_kernel<Vs, Vc, N, 2>), dim3(nblk), dim3(RowGCfg<N, 2>::THREADS), 0, s, a);
   }
   return hipGetLastError();
 }
 
-template <int N> static hipError_t row_fp64(const RowArgs& a, hipStream_t s) {
-  if constexpr (N >= 128 && N <= 1024) return rowg_launch<double2, N>(a, s);
-  else return row_launch<double2, N>(a, s);
+template <typename Vs, typename Vc, int N> static hipError_t row_any(const RowArgs& a, hipStream_t s) {
+  if constexpr (N >= 128 && N <= 1024) return rowg_launch<Vs, Vc, N>(a, s);
+  else return row_launch<Vs, Vc, N>(a, s);
 }
-template <int N> static hipError_t row_fp32(const RowArgs& a, hipStream_t s) {
-  if constexpr (N >= 128 && N <= 1024) return rowg_launch<float2, N>(a, s);
-  else return row_launch<float2, N>(a, s);
+template <int N> static hipError_t row_fp64(const RowArgs& a, hipStream_t s) { return row_any<double2, double2, N>(a, s); }
+template <int N> static hipError_t row_fp32(const RowArgs& a, hipStream_t s) { return row_any<float2, float2, N>(a, s); }
+template <int N> static hipError_t row_fp32_hi(const RowArgs& a, hipStream_t s) {
+  return row_any<float2, double2, N>(a, s);
 }
-template <int N> static hipError_t col_fp64(const ColArgs& a, hipStream_t s) { return col_launch<double2, N>(a, s); }
-template <int N> static hipError_t col_fp32(const ColArgs& a, hipStream_t s) { return col_launch<float2, N>(a, s); }
+template <int N> static hipError_t col_fp64(const ColArgs& a, hipStream_t s) {
+  return col_launch<double2, double2, N>(a, s);
+}
+template <int N> static hipError_t col_fp32(const ColArgs& a, hipStream_t s) {
+  return col_launch<float2, float2, N>(a, s);
+}
+template <int N> static hipError_t col_fp32_hi(const ColArgs& a, hipStream_t s) {
+  return col_launch<float2, double2, N>(a, s);
+}
 
 hipError_t launch_row_pass(const PassParams& p, const double2* g, const void* spec, const int* pm,
                            const int* pn, int npairs, void* inter, const void* twx, hipStream_t s) {
@@ -734,6 +657,9 @@ hipError_t launch_row_pass(const PassParams& p, const double2* g, const void* sp
   }
   if (p.precision == 0) {
     CFFT_SIZE_SWITCH(p.x.n, row_fp64, a, s)
+  }
+  if (p.hi_compute) {
+    CFFT_SIZE_SWITCH(p.x.n, row_fp32_hi, a, s)
   }
   CFFT_SIZE_SWITCH(p.x.n, row_fp32, a, s)
 }
@@ -773,6 +699,9 @@ hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, v
   if (p.precision == 0) {
     CFFT_SIZE_SWITCH(p.y.n, col_fp64, a, s)
   }
+  if (p.hi_compute) {
+    CFFT_SIZE_SWITCH(p.y.n, col_fp32_hi, a, s)
+  }
   CFFT_SIZE_SWITCH(p.y.n, col_fp32, a, s)
 }
 
@@ -792,6 +721,14 @@ struct AdjColArgs {
   double2 cscale;  // conj(K sigma W)
   double rinv[kMaxOrder + 1];
 };
+
+// Adjoint column tile: FP64, 8 points per thread, up to four columns (64-byte
+// row pieces) within 80 KiB of LDS and 512 threads.
+template <int N> constexpr int adj_col_tile() {
+  int c = 4;
+  while (c > 1 && (c * (lds_len(N) + 4) * 16 > 81920 || c * (N / 8) > 512)) c /= 2;
+  return c;
+}
 
 template <int N, int C>
 __global__ void __launch_bounds__(C * (N / 8)) adj_col_kernel(AdjColArgs a) {
@@ -857,9 +794,9 @@ struct AdjRowArgs {
 };
 
 template <int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs a) {
-  using Cfg = RowCfg<N>;
-  constexpr int T = Cfg::T, R = Cfg::R, ROWS = Cfg::ROWS;
+__global__ void __launch_bounds__((RowCfg<N, 8>::THREADS)) adj_row_kernel(AdjRowArgs a) {
+  using Cfg = RowCfg<N, 8>;
+  constexpr int T = Cfg::T, R = 8, ROWS = Cfg::ROWS;
   __shared__ double2 lds[ROWS * lds_len<row_pad<double2>()>(N)];
   __shared__ double2 ltw[TwLds<N>::LEN];
   load_twiddles<double2, N>(ltw, a.tw, threadIdx.x, Cfg::THREADS);
@@ -912,7 +849,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) adj_row_kernel(AdjRowArgs 
 
 template <int N>
 static hipError_t adj_col_launch(const AdjColArgs& args, hipStream_t s) {
-  constexpr int C = col_tile_cr(N, 16, 8);
+  constexpr int C = adj_col_tile<N>();
   using Cfg = ColCfg<N, C, 8>;
   if (args.nx % C != 0) return hipErrorInvalidValue;
   const int nblk = (args.nx / C) * args.npairs;
@@ -922,7 +859,7 @@ static hipError_t adj_col_launch(const AdjColArgs& args, hipStream_t s) {
 
 template <int N>
 static hipError_t adj_row_launch(const AdjRowArgs& args, hipStream_t s) {
-  using Cfg = RowCfg<N>;
+  using Cfg = RowCfg<N, 8>;
   const int nblk = ((args.ny + Cfg::ROWS - 1) / Cfg::ROWS) * args.npairs;
   hipLaunchKernelGGL((adj_row_kernel<N>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
   return hipGetLastError();

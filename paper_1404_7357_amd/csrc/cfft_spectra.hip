@@ -119,14 +119,8 @@ hipError_t launch_spectra_tables(const Axis& x, const Axis& y, double gamma, con
   return hipGetLastError();
 }
 
-#ifndef CFFT_SPEC_THREADS
-#define CFFT_SPEC_THREADS 256
-#endif
-#ifndef CFFT_SPEC_ROWS
-#define CFFT_SPEC_ROWS 2
-#endif
-constexpr int kSpecThreads = CFFT_SPEC_THREADS;   // spectra kernel block size
-constexpr int kSpecRows = CFFT_SPEC_ROWS;         // rows per spectra block
+constexpr int kSpecThreads = 256;   // spectra kernel block size
+constexpr int kSpecRows = 2;         // rows per spectra block
 constexpr int kMaxGroups = 32;  // host refuses basis sets needing more
 constexpr int kMChunk = 4;
 

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import cfft_oracle as co
-from tolerances import mixed_tolerance
+from tolerances import FP64_TARGET, MIXED_TARGET
 from workloads import (FP64, MIXED, Grid, c3_frequency_sweep, c4_large, gaussian_coefficients, random_smooth_field,
                        rooftop_lattice)
 
@@ -156,7 +156,7 @@ def test_large_table_sampled(prec):
     ref = co.tabulate_from_factors(gd, sel, tuple(g), mt, mh, out_idx=idx, workers=8)
     scale = np.abs(ref).max(axis=1)
     err = (np.abs(got - ref).max(axis=1) / scale).max()
-    tol = 1e-10 if prec == FP64 else mixed_tolerance(n)
+    tol = FP64_TARGET if prec == FP64 else MIXED_TARGET
     print(f"[gpu-case] c4 table prec={prec} err={err:.3e}", flush=True)
     assert err < tol, err
 
