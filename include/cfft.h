@@ -106,7 +106,7 @@ enum { CFFT_FLAG_CHECK_FINITE = 1, CFFT_FLAG_AUTOTUNE = 2, CFFT_FLAG_ZERO_PAD2 =
 
 /* One spectral grid.  64 bytes, natural alignment. */
 typedef struct {
-  int32_t nx, ny;        /* samples = outputs per axis: powers of two, 8 <= n <= 4096 */
+  int32_t nx, ny;        /* samples = outputs per axis: powers of two, 16 <= n <= 4096 */
   double kx_max, ky_max; /* spectral half-spans (rad per lambda0), > 0 */
   double k0;             /* free-space wavenumber 2 pi f/f0, > 0 */
   double gamma;          /* contour height ratio beta_I/beta_R (eq. ratioNew), > 0 */
@@ -181,6 +181,27 @@ cfft_status_t mbf_spectra(cfft_plan_t plan, int32_t grid, const cfft_basis_t* ba
 cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, int32_t nmbf,
                             const void* g, const int32_t* pairs, int32_t npairs, void* z,
                             void* stream);
+
+/* Allocation-free cfft_tabulate, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, result and errors as cfft_tabulate, but
+ * the intermediates between the row and column passes live in a fixed
+ * device array of CFFT_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device it runs on (resolved by c_fft_plan) instead of the plan's
+ * workspace, and no schedule is autotuned (one lane, pairs in chunks that
+ * fit the array; CFFT_FLAG_AUTOTUNE is ignored here).  The call allocates
+ * no device memory.
+ *   Limit: the intermediates of one pair, (P+1) nx ny complex values in the
+ *   grid's storage precision (one value per sample with the tensor
+ *   truncation), must fit the array: up to 2048^2 FP64 or 4096 x 2048 mixed
+ *   at P = 3.  Larger grids return CFFT_ERR_UNSUPPORTED before any launch.
+ *   Concurrency: every call on a device shares that device's array, so calls
+ *   that overlap in time on one device (other streams, other plans, other
+ *   host threads) race; serialise them. */
+#define CFFT_NOALLOC_SCRATCH_BYTES (256u << 20)
+cfft_status_t cfft_tabulate_noalloc(cfft_plan_t plan, int32_t grid, const void* spec, int32_t nmbf,
+                                    const void* g, const int32_t* pairs, int32_t npairs, void* z,
+                                    void* stream);
 
 /* Bilinear interpolation in the table (first-order stand-in for the
  * interpolation of Sec. III-B.3, last paragraph).

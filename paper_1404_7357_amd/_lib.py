@@ -26,6 +26,7 @@ FLAG_AUTOTUNE = 2
 FLAG_ZERO_PAD2 = 4
 
 ENTRY_POINTS = ("c_fft_plan", "c_fft_plan_destroy", "slab_green_eval", "mbf_spectra", "cfft_tabulate",
+                "cfft_tabulate_noalloc",
                 "cfft_lookup", "cfft_lookup_quadratic", "cfft_fill", "cfft_fill_backward", "cfft_lookup_backward",
                 "cfft_lookup_quadratic_backward", "cfft_backward", "cfft_profile",
                 "cfft_profile_read",
@@ -73,6 +74,7 @@ def load(path: str = LIB_PATH):
     lib.slab_green_eval.argtypes = [vp, i32, dbl, dbl, dbl, vp, vp]
     lib.mbf_spectra.argtypes = [vp, i32, ctypes.POINTER(Basis), i32, vp, i32, vp, vp]
     lib.cfft_tabulate.argtypes = [vp, i32, vp, i32, vp, ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
+    lib.cfft_tabulate_noalloc.argtypes = [vp, i32, vp, i32, vp, ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
     lib.cfft_lookup.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_lookup_quadratic.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cfft_fill.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int32), i32, i32, vp, i32, i32, vp, vp]
@@ -170,6 +172,12 @@ def cfft_tabulate(plan: Plan, grid: int, spec, nmbf: int, g, pairs, z, stream=No
     pa = pairs_array(pairs)
     check(load().cfft_tabulate(plan.handle, grid, _ptr(spec), int(nmbf), _ptr(g), pa, len(pa) // 2, _ptr(z),
                                _stream(stream)))
+
+
+def cfft_tabulate_noalloc(plan: Plan, grid: int, spec, nmbf: int, g, pairs, z, stream=None):
+    pa = pairs_array(pairs)
+    check(load().cfft_tabulate_noalloc(plan.handle, grid, _ptr(spec), int(nmbf), _ptr(g), pa, len(pa) // 2,
+                                       _ptr(z), _stream(stream)))
 
 
 def cfft_lookup(plan: Plan, grid: int, z, npairs: int, pts, out, stream=None):

@@ -171,6 +171,44 @@ uint64_t hash_bytes(const void* p, size_t n, uint64_t h = 1469598103934665603ull
 
 }  // namespace
 
+// Device scratch of the allocation-free entry point (cfft_tabulate_noalloc):
+// the intermediates between the row and column passes of one pair chunk.
+// Each device the library runs on holds its own copy until the process
+// ends.  In host code `scratch` names a host-side stand-in, not a device
+// address: c_fft_plan resolves the device address with hipGetSymbolAddress
+// once per device (with that device current), and only that address is
+// ever handed to kernels.
+constexpr size_t kNoAllocScratchBytes = CFFT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), resolved on
+// the first call for that device.
+cfft_status_t resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(CFFT_ERR_UNSUPPORTED, "device index %d >= %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return CFFT_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    return fail(CFFT_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                e != hipSuccess ? hipGetErrorString(e) : "null address");
+  }
+  g_scratch_ptr[device] = ptr;
+  return CFFT_OK;
+}
+
+void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
+}  // namespace
+
 struct GridState {
   cfft_grid_desc_t d;
   Axis x, y;
@@ -607,6 +645,13 @@ cfft_status_t c_fft_plan(const cfft_grid_desc_t* grids, int32_t ngrids, int32_t 
     delete p;
     return hip_fail(e, "hipGetDevice");
   }
+  {
+    cfft_status_t sst = resolve_scratch(p->device);
+    if (sst != CFFT_OK) {
+      delete p;
+      return sst;
+    }
+  }
   p->max_mbf = max_mbf;
   p->flags = flags;
   p->grids.resize(ngrids);
@@ -870,6 +915,55 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   }
   {
     hipError_t e = run_passes(chunk, lanes, narrow);
+    if (e != hipSuccess) return hip_fail(e, "pass launch");
+  }
+  return check_finite(plan, z, 2 * n * (size_t)npairs, pp.precision != CFFT_FP64, s);
+}
+
+cfft_status_t cfft_tabulate_noalloc(cfft_plan_t plan, int32_t grid, const void* spec, int32_t nmbf, const void* g,
+                                    const int32_t* pairs, int32_t npairs, void* z, void* stream) {
+  g_last_error.clear();
+  cfft_status_t st = check_plan(plan, grid);
+  if (st != CFFT_OK) return st;
+  if (!spec || !g || !z) return fail(CFFT_ERR_INVALID_ARG, "spec, g or z is NULL");
+  if (nmbf < 1 || nmbf > plan->max_mbf)
+    return fail(CFFT_ERR_INVALID_ARG, "nmbf %d outside [1, max_mbf = %d]", nmbf, plan->max_mbf);
+  st = validate_pairs(pairs, npairs, nmbf);
+  if (st != CFFT_OK) return st;
+  GridState& gs = plan->grids[grid];
+  const PassParams pp = pass_params(gs);
+  const size_t n = (size_t)gs.x.n * gs.y.n;
+  const size_t cbytes = pp.precision == CFFT_FP64 ? 16 : 8;
+  const size_t per_pair = (size_t)inter_slots(pp) * n * cbytes;
+  if (per_pair > kNoAllocScratchBytes)
+    return fail(CFFT_ERR_UNSUPPORTED,
+                "grid %d needs %zu bytes of intermediates per pair; the allocation-free entry point holds %zu",
+                grid, per_pair, kNoAllocScratchBytes);
+  void* ws = scratch_of(plan->device);
+  if (!ws) return fail(CFFT_ERR_HIP, "scratch address of device %d not resolved", plan->device);
+  const int chunk = (int)std::min<size_t>(kNoAllocScratchBytes / per_pair, (size_t)kMaxPairsPerLaunch);
+  const bool c64 = pp.precision == CFFT_FP64 || pp.hi_compute;
+  const void* twx = c64 ? gs.tw64x : gs.tw32x;
+  const void* twy = c64 ? gs.tw64y : gs.tw32y;
+  hipStream_t s = (hipStream_t)stream;
+  // every intermediate the column pass reads is written by the row pass of
+  // the same chunk first, so the scratch needs no clearing
+  int pm[kMaxPairsPerLaunch], pn[kMaxPairsPerLaunch];
+  for (int p0 = 0; p0 < npairs; p0 += chunk) {
+    const int np = std::min(chunk, npairs - p0);
+    for (int i = 0; i < np; ++i) {
+      pm[i] = pairs[2 * (p0 + i)];
+      pn[i] = pairs[2 * (p0 + i) + 1];
+    }
+    hipError_t e;
+    {
+      ProfScope ps(plan, 2, s);
+      e = launch_row_pass(pp, (const double2*)g, spec, pm, pn, np, ws, twx, s);
+    }
+    if (e == hipSuccess) {
+      ProfScope ps(plan, 3, s);
+      e = launch_col_pass(pp, ws, np, (char*)z + (size_t)p0 * n * cbytes, twy, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "pass launch");
   }
   return check_finite(plan, z, 2 * n * (size_t)npairs, pp.precision != CFFT_FP64, s);
