@@ -396,11 +396,12 @@ def band_mask(grid):
     return (in2[:, None] & in1[None, :]).ravel()
 
 
-def tabulate(grid, substrate, basis, q, pairs, out_idx=None, order=None, workers=1):
+def tabulate(grid, substrate, basis, q, pairs, out_idx=None, order=None, workers=1, block=32):
     """Table Z'_mn on the displacement grid (or on a subset of it).
 
     out_idx: None for the full [npairs][ny][nx] table, else an int array of
     flattened output indices j2*nx + j1 (returns [npairs][len(out_idx)]).
+    block: outputs per task of the direct sum (workers share the tasks).
     """
     order = grid.order if order is None else order
     kx, ky, w, g, mt, mh = sampled_factors(grid, substrate, basis, q)
@@ -417,14 +418,14 @@ def tabulate(grid, substrate, basis, q, pairs, out_idx=None, order=None, workers
     dkx = 2.0 * grid.kx_max / grid.nx
     dky = 2.0 * grid.ky_max / grid.ny
     gam = grid_contour(kx, ky, grid)[3]
-    z = direct_sum(integ, kx, ky, dx, dy, gam, order, dkx, dky, workers=workers,
+    z = direct_sum(integ, kx, ky, dx, dy, gam, order, dkx, dky, block=block, workers=workers,
                    truncation=getattr(grid, "truncation", 0))
     if out_idx is None:
         z = z.reshape(len(pairs), grid.ny, grid.nx)
     return z
 
 
-def tabulate_from_factors(grid, pairs, g, mt, mh, out_idx=None, order=None, workers=1):
+def tabulate_from_factors(grid, pairs, g, mt, mh, out_idx=None, order=None, workers=1, block=32):
     """Same as tabulate() but from given sampled factors (kernel-level tests).
 
     g: (gxx, gxy, gyy) each [ny*nx]; mt, mh: [M][2][ny*nx].  The contour
@@ -445,7 +446,7 @@ def tabulate_from_factors(grid, pairs, g, mt, mh, out_idx=None, order=None, work
         dx, dy = dx[out_idx], dy[out_idx]
     dkx = 2.0 * grid.kx_max / grid.nx
     dky = 2.0 * grid.ky_max / grid.ny
-    z = direct_sum(integ, kx, ky, dx, dy, gam, order, dkx, dky, workers=workers,
+    z = direct_sum(integ, kx, ky, dx, dy, gam, order, dkx, dky, block=block, workers=workers,
                    truncation=getattr(grid, "truncation", 0))
     if out_idx is None:
         z = z.reshape(len(pairs), grid.ny, grid.nx)
