@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcfft.so")
 
-SOURCES = ["cfft_api.cpp", "cfft_green.hip", "cfft_spectra.hip", "cfft_passes.hip"]
+SOURCES = ["cfft_api.cpp", "cfft_green.hip", "cfft_spectra.hip", "cfft_passes.hip", "cfft_scatter.hip"]
 
 COMMON = [
     "--offload-arch=gfx950",
@@ -52,7 +52,7 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libcfft.so; returns the library path."""
     lib = LIB
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]

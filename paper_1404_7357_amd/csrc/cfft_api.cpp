@@ -233,6 +233,8 @@ struct cfft_plan_s {
   size_t ws2_bytes = 0;
   void* ws3 = nullptr;      // spectra scratch (per-row contractions over y-centres)
   size_t ws3_bytes = 0;
+  void* ws4 = nullptr;      // interpolation adjoints: sort keys, runs and sort scratch
+  size_t ws4_bytes = 0;
   // geometry cache (one basis set at a time)
   uint64_t geo_hash = 0;
   int geo_nbasis = 0;
@@ -393,7 +395,7 @@ cfft_status_t ensure_geometry(cfft_plan_s* plan, GridState& gs, const cfft_basis
     GeomDevice probe{};
     probe.ngroups = (int)gh.groups.size();
     probe.total_r = gh.total_r;
-    if (spectra_lds_bytes(probe, plan->max_mbf) > 65536)
+    if (spectra_lds_bytes(probe, plan->max_mbf) > kMaxDynamicLds)
       return fail(CFFT_ERR_UNSUPPORTED, "%d distinct y-centres: too many for the per-row LDS tables", gh.total_r);
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "synchronise before geometry upload");
@@ -547,6 +549,7 @@ void release_plan(cfft_plan_s* plan) {
   if (plan->ws) (void)hipFree(plan->ws);
   if (plan->ws2) (void)hipFree(plan->ws2);
   if (plan->ws3) (void)hipFree(plan->ws3);
+  if (plan->ws4) (void)hipFree(plan->ws4);
   if (plan->flag_dev) (void)hipFree(plan->flag_dev);
   if (plan->flag_host) (void)hipHostFree(plan->flag_host);
   for (auto& v : plan->prof)
@@ -1023,10 +1026,22 @@ static cfft_status_t fill_common(cfft_plan_t plan, int32_t grid, const void* z, 
   if (dout && gs.d.precision != CFFT_FP64) return fail(CFFT_ERR_UNSUPPORTED, "the fill adjoint needs an FP64 grid");
   if (nelem == 1) return CFFT_OK;   // only the self block, which is not written
   hipError_t e;
-  {
+  if (dout) {
+    const size_t need = scatter_workspace_bytes((long long)nelem * nelem);
+    if (need == 0) return fail(CFFT_ERR_UNSUPPORTED, "fill adjoint of %d elements: too many element pairs", nelem);
+    st = ensure_ws(&plan->ws4, &plan->ws4_bytes, need, "scatter workspace");
+    if (st != CFFT_OK) return st;
+    int pm[kScatterMaxPairs], pn[kScatterMaxPairs];
+    for (int k = 0; k < npairs; ++k) {
+      pm[k] = pairs[2 * k];
+      pn[k] = pairs[2 * k + 1];
+    }
     ProfScope ps(plan, 4, (hipStream_t)stream);
-    e = launch_fill(pass_params(gs), z, slot, nmbf, pos, nelem, order, (double2*)out, (const double2*)dout,
-                    (hipStream_t)stream);
+    e = launch_fill_backward(pass_params(gs), pm, pn, npairs, nmbf, pos, nelem, order, (const double2*)dout,
+                             (double2*)out, plan->ws4, (hipStream_t)stream);
+  } else {
+    ProfScope ps(plan, 4, (hipStream_t)stream);
+    e = launch_fill(pass_params(gs), z, slot, nmbf, pos, nelem, order, (double2*)out, (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(e, "fill launch");
   return CFFT_OK;
@@ -1062,8 +1077,12 @@ static cfft_status_t lookup_backward_common(cfft_plan_t plan, int32_t grid, cons
     return fail(CFFT_ERR_INVALID_ARG, "npts %d invalid", npts);
   GridState& gs = plan->grids[grid];
   if (gs.d.precision != CFFT_FP64) return fail(CFFT_ERR_UNSUPPORTED, "lookup adjoint needs an FP64 grid");
+  const size_t need = scatter_workspace_bytes(npts);
+  if (need == 0) return fail(CFFT_ERR_UNSUPPORTED, "lookup adjoint of %d points: too many points", npts);
+  st = ensure_ws(&plan->ws4, &plan->ws4_bytes, need, "scatter workspace");
+  if (st != CFFT_OK) return st;
   hipError_t e = launch_lookup_backward(pass_params(gs), (const double2*)dout, npairs, pts, npts, (double2*)dz,
-                                        quadratic, (hipStream_t)stream);
+                                        quadratic, plan->ws4, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "lookup adjoint launch");
   return CFFT_OK;
 }
@@ -1103,6 +1122,10 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   hipStream_t s = (hipStream_t)stream;
   st = ensure_geometry(plan, gs, basis, nbasis, s);
   if (st != CFFT_OK) return st;
+  if (adj_spectra_lds_bytes(plan->geo_dev, nmbf) > kMaxDynamicLds)
+    return fail(CFFT_ERR_UNSUPPORTED,
+                "the spectra adjoint keeps %d MBFs x %d distinct x-centres in LDS: %zu bytes, more than %zu", nmbf,
+                plan->geo_dev.total_p, adj_spectra_lds_bytes(plan->geo_dev, nmbf), kMaxDynamicLds);
   const PassParams pp = pass_params(gs);
   const size_t n = (size_t)gs.x.n * gs.y.n;
   const size_t per_pair = (size_t)inter_slots(pp) * n * 16 + n * 16;   // intermediates + gH

@@ -124,7 +124,7 @@ __device__ __forceinline__ void contour_ratio(double beta, double gamma, int par
   else slope = beta < beta_end ? gamma * (1.0 - 2.0 * beta / beta_end) : 0.0;
 }
 
-// Non-temporal (streaming) accesses for data touched once; the store moves
+// Non-temporal (streaming) store for data written once; it moves
 // the whole complex value in one instruction.
 template <typename V> __device__ __forceinline__ void store_nt(V* p, V v) {
   using Rl = typename real_of<V>::type;
@@ -133,14 +133,6 @@ template <typename V> __device__ __forceinline__ void store_nt(V* p, V v) {
   w.x = v.x;
   w.y = v.y;
   __builtin_nontemporal_store(w, reinterpret_cast<pair_t*>(p));
-}
-template <typename V> __device__ __forceinline__ V load_nt(const V* p) {
-  using Rl = typename real_of<V>::type;
-  const Rl* q = reinterpret_cast<const Rl*>(p);
-  V v;
-  v.x = __builtin_nontemporal_load(q);
-  v.y = __builtin_nontemporal_load(q + 1);
-  return v;
 }
 
 // ---------------------------------------------------------------- FFT
@@ -343,6 +335,40 @@ __device__ __forceinline__ void fft_inverse(V (&x)[R], V* lds, const V* ltw, int
   fft_forward<V, N, R, WAVE, PS>(x, lds, ltw, t);
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = cconj(x[r]);
+}
+
+// ---------------------------------------------------------------- table stencils
+// Bilinear cell of the fractional table index (ux, uy): rejects NaN,
+// negative and beyond-the-last-cell points before any cast.
+__device__ __forceinline__ bool cell_at(double ux, double uy, int nx, int ny, int& j1, int& j2, double& tx,
+                                        double& ty) {
+  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux < (double)(nx - 1)) || !(uy < (double)(ny - 1))) return false;
+  j1 = (int)floor(ux);
+  j2 = (int)floor(uy);
+  if (j1 > nx - 2 || j2 > ny - 2) return false;
+  tx = ux - j1;
+  ty = uy - j2;
+  return true;
+}
+
+// Second-order interpolation (Sec. III-B.3, last paragraph): per axis the
+// nodes c - 1, c, c + 1 around the nearest node c = round(u), kept in
+// [1, n-2], with the quadratic Lagrange weights in t = u - c.  Points need
+// 0 <= u <= n - 1 on both axes; others (and NaN) yield NaN.
+__device__ __forceinline__ bool stencil_at(double ux, double uy, int nx, int ny, int& c1, int& c2, double& tx,
+                                           double& ty) {
+  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux <= (double)(nx - 1)) || !(uy <= (double)(ny - 1))) return false;
+  c1 = min(max((int)floor(ux + 0.5), 1), nx - 2);
+  c2 = min(max((int)floor(uy + 0.5), 1), ny - 2);
+  tx = ux - c1;
+  ty = uy - c2;
+  return true;
+}
+
+__device__ __forceinline__ void lagrange3(double t, double (&w)[3]) {
+  w[0] = 0.5 * t * (t - 1.0);
+  w[1] = (1.0 - t) * (1.0 + t);
+  w[2] = 0.5 * t * (t + 1.0);
 }
 
 // XCD-aware remap of the block index: the hardware deals consecutive block

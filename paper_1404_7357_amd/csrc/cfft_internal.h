@@ -97,6 +97,8 @@ hipError_t launch_spectra_direct(const Axis& x, const Axis& y, const Contour& c,
 size_t spectra_direct_scratch_len(const GeomDevice& geo, int nmbf);
 size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf);
 size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf);
+size_t adj_spectra_lds_bytes(const GeomDevice& geo, int nmbf);
+constexpr size_t kMaxDynamicLds = 65536;   // dynamic LDS a launch may ask for
 
 // Row + column passes for one chunk of <= kMaxPairsPerLaunch pairs.
 hipError_t launch_row_pass(const PassParams& p, const double2* g, const void* spec,
@@ -111,11 +113,19 @@ hipError_t launch_lookup_quadratic(const PassParams& p, const void* z, int npair
                                   int npts, double2* out, hipStream_t s);
 // Reduced-matrix fill; slot[m * kFillMaxMbf + n] = pair index of (m, n) or -1.
 constexpr int kFillMaxMbf = 16;
-// dout != nullptr: the adjoint, accumulating into the FP64 table gradient `out`.
 hipError_t launch_fill(const PassParams& p, const void* z, const short* slot, int nmbf, const double* pos,
-                       int nelem, int order, double2* out, const double2* dout, hipStream_t s);
-hipError_t launch_lookup_backward(const PassParams& p, const double2* dout, int npairs,
-                                  const double* pts, int npts, double2* dz, bool quadratic, hipStream_t s);
+                       int nelem, int order, double2* out, hipStream_t s);
+
+// Deterministic adjoints of the interpolations (cfft_scatter.hip): the
+// cotangents scattered onto the FP64 table gradient dz (accumulated into);
+// ws holds scatter_workspace_bytes(points) bytes (0: too many points).
+constexpr int kScatterMaxPairs = kFillMaxMbf * kFillMaxMbf;
+size_t scatter_workspace_bytes(long long npoints);
+hipError_t launch_lookup_backward(const PassParams& p, const double2* dout, int npairs, const double* pts,
+                                  int npts, double2* dz, bool quadratic, void* ws, hipStream_t s);
+hipError_t launch_fill_backward(const PassParams& p, const int* pm, const int* pn, int npairs, int nmbf,
+                                const double* pos, int nelem, int order, const double2* dout, double2* dz,
+                                void* ws, hipStream_t s);
 
 // Adjoint.
 hipError_t launch_adj_col_pass(const PassParams& p, const double2* dz, int npairs, double2* inter,

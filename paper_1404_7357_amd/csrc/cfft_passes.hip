@@ -1119,19 +1119,6 @@ struct LookupArgs {
   double x0, ddx, y0, ddy;
 };
 
-// Bilinear cell of the fractional table index (ux, uy): rejects NaN,
-// negative and beyond-the-last-cell points before any cast.
-__device__ __forceinline__ bool cell_at(double ux, double uy, int nx, int ny, int& j1, int& j2, double& tx,
-                                        double& ty) {
-  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux < (double)(nx - 1)) || !(uy < (double)(ny - 1))) return false;
-  j1 = (int)floor(ux);
-  j2 = (int)floor(uy);
-  if (j1 > nx - 2 || j2 > ny - 2) return false;
-  tx = ux - j1;
-  ty = uy - j2;
-  return true;
-}
-
 __device__ __forceinline__ bool cell_of(const LookupArgs& a, int q, int& j1, int& j2, double& tx, double& ty) {
   return cell_at((a.pts[2 * q] - a.x0) / a.ddx, (a.pts[2 * q + 1] - a.y0) / a.ddy, a.nx, a.ny, j1, j2, tx, ty);
 }
@@ -1162,26 +1149,6 @@ __global__ void lookup_kernel(LookupArgs a) {
     return;
   }
   a.out[e] = bilinear_at(a.z, a.precision, (size_t)p * a.nx * a.ny, a.nx, j1, j2, tx, ty);
-}
-
-// Second-order interpolation (Sec. III-B.3, last paragraph): per axis the
-// nodes c - 1, c, c + 1 around the nearest node c = round(u), kept in
-// [1, n-2], with the quadratic Lagrange weights in t = u - c.  Points need
-// 0 <= u <= n - 1 on both axes; others (and NaN) yield NaN.
-__device__ __forceinline__ bool stencil_at(double ux, double uy, int nx, int ny, int& c1, int& c2, double& tx,
-                                           double& ty) {
-  if (!(ux >= 0.0) || !(uy >= 0.0) || !(ux <= (double)(nx - 1)) || !(uy <= (double)(ny - 1))) return false;
-  c1 = min(max((int)floor(ux + 0.5), 1), nx - 2);
-  c2 = min(max((int)floor(uy + 0.5), 1), ny - 2);
-  tx = ux - c1;
-  ty = uy - c2;
-  return true;
-}
-
-__device__ __forceinline__ void lagrange3(double t, double (&w)[3]) {
-  w[0] = 0.5 * t * (t - 1.0);
-  w[1] = (1.0 - t) * (1.0 + t);
-  w[2] = 0.5 * t * (t + 1.0);
 }
 
 __device__ __forceinline__ double2 quadratic_at(const void* z, int precision, size_t base, int nx, int c1, int c2,
@@ -1215,25 +1182,6 @@ __global__ void lookup_quadratic_kernel(LookupArgs a) {
     return;
   }
   a.out[e] = quadratic_at(a.z, a.precision, (size_t)p * a.nx * a.ny, a.nx, c1, c2, tx, ty);
-}
-
-__global__ void lookup_backward_kernel(LookupArgs a, const double2* __restrict__ dout, double2* dz) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.npairs * a.npts) return;
-  const int p = e / a.npts, q = e % a.npts;
-  int j1, j2;
-  double tx, ty;
-  if (!cell_of(a, q, j1, j2, tx, ty)) return;
-  const double2 g = dout[e];
-  const size_t i00 = (size_t)p * a.nx * a.ny + (size_t)j2 * a.nx + j1;
-  const double w[4] = {(1 - tx) * (1 - ty), tx * (1 - ty), (1 - tx) * ty, tx * ty};
-  const size_t id[4] = {i00, i00 + 1, i00 + a.nx, i00 + a.nx + 1};
-  double* d = (double*)dz;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    atomicAdd(d + 2 * id[k], w[k] * g.x);
-    atomicAdd(d + 2 * id[k] + 1, w[k] * g.y);
-  }
 }
 
 // Reduced-matrix fill (Sec. II eq. MBF; Sec. III-B.1 and III-B.3): one
@@ -1275,54 +1223,8 @@ __global__ __launch_bounds__(256) void fill_kernel(FillArgs a) {
   a.out[(size_t)r * am + c] = v;
 }
 
-// Adjoint of the fill: every written entry scatters dout[r][c] with its
-// interpolation weights into the table of its pair (FP64 tables).
-template <int ORDER>
-__global__ __launch_bounds__(256) void fill_backward_kernel(FillArgs a, const double2* __restrict__ dout, double2* dz) {
-  const int am = a.nelem * a.nmbf;
-  const int r = blockIdx.x / a.ncb;
-  const int c = (blockIdx.x - r * a.ncb) * 256 + threadIdx.x;
-  if (c >= am) return;
-  const int i = r / a.nmbf, m = r - i * a.nmbf;
-  const int j = c / a.nmbf, n = c - j * a.nmbf;
-  if (i == j) return;
-  const int p = a.slot[m * kFillMaxMbf + n];
-  if (p < 0) return;
-  const double ux = (a.pos[2 * i] - a.pos[2 * j] - a.x0) / a.ddx;
-  const double uy = (a.pos[2 * i + 1] - a.pos[2 * j + 1] - a.y0) / a.ddy;
-  const double2 g = dout[(size_t)r * am + c];
-  double* d = (double*)dz + 2 * (size_t)p * a.nx * a.ny;
-  int c1, c2;
-  double tx, ty;
-  if (ORDER == 1) {
-    if (!cell_at(ux, uy, a.nx, a.ny, c1, c2, tx, ty)) return;
-    const double w[4] = {(1 - tx) * (1 - ty), tx * (1 - ty), (1 - tx) * ty, tx * ty};
-    const size_t id[4] = {(size_t)c2 * a.nx + c1, (size_t)c2 * a.nx + c1 + 1, (size_t)(c2 + 1) * a.nx + c1,
-                          (size_t)(c2 + 1) * a.nx + c1 + 1};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      atomicAdd(d + 2 * id[k], w[k] * g.x);
-      atomicAdd(d + 2 * id[k] + 1, w[k] * g.y);
-    }
-  } else {
-    if (!stencil_at(ux, uy, a.nx, a.ny, c1, c2, tx, ty)) return;
-    double wx[3], wy[3];
-    lagrange3(tx, wx);
-    lagrange3(ty, wy);
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const size_t id = (size_t)(c2 + b - 1) * a.nx + (c1 + k - 1);
-        atomicAdd(d + 2 * id, wy[b] * wx[k] * g.x);
-        atomicAdd(d + 2 * id + 1, wy[b] * wx[k] * g.y);
-      }
-    }
-  }
-}
-
 hipError_t launch_fill(const PassParams& p, const void* z, const short* slot, int nmbf, const double* pos, int nelem,
-                       int order, double2* out, const double2* dout, hipStream_t s) {
+                       int order, double2* out, hipStream_t s) {
   FillArgs a;
   a.z = z;
   a.pos = pos;
@@ -1340,44 +1242,11 @@ hipError_t launch_fill(const PassParams& p, const void* z, const short* slot, in
   a.ddy = p.y.dd;
   for (int k = 0; k < kFillMaxMbf * kFillMaxMbf; ++k) a.slot[k] = slot[k];
   const dim3 grid((unsigned)((long long)am * a.ncb));
-  if (dout != nullptr) {   // adjoint: out is the table gradient dz
-    if (order == 1)
-      hipLaunchKernelGGL(fill_backward_kernel<1>, grid, dim3(256), 0, s, a, dout, out);
-    else
-      hipLaunchKernelGGL(fill_backward_kernel<2>, grid, dim3(256), 0, s, a, dout, out);
-    return hipGetLastError();
-  }
   if (order == 1)
     hipLaunchKernelGGL(fill_kernel<1>, grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(fill_kernel<2>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
-}
-
-// Adjoint of the second-order lookup: dz[p][stencil] += w dout[p][q].
-__global__ void lookup_quadratic_backward_kernel(LookupArgs a, const double2* __restrict__ dout, double2* dz) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.npairs * a.npts) return;
-  const int p = e / a.npts, q = e % a.npts;
-  int c1, c2;
-  double tx, ty;
-  if (!stencil_at((a.pts[2 * q] - a.x0) / a.ddx, (a.pts[2 * q + 1] - a.y0) / a.ddy, a.nx, a.ny, c1, c2, tx, ty)) return;
-  double wx[3], wy[3];
-  lagrange3(tx, wx);
-  lagrange3(ty, wy);
-  const double2 g = dout[e];
-  double* d = (double*)dz;
-  const size_t base = (size_t)p * a.nx * a.ny;
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const size_t id = base + (size_t)(c2 + b - 1) * a.nx + (c1 + i - 1);
-      const double w = wy[b] * wx[i];
-      atomicAdd(d + 2 * id, w * g.x);
-      atomicAdd(d + 2 * id + 1, w * g.y);
-    }
-  }
 }
 
 static LookupArgs lookup_args(const PassParams& p, const void* z, int npairs, const double* pts, int npts,
@@ -1411,18 +1280,6 @@ hipError_t launch_lookup_quadratic(const PassParams& p, const void* z, int npair
   const LookupArgs a = lookup_args(p, z, npairs, pts, npts, out);
   const long long n = (long long)npairs * npts;
   hipLaunchKernelGGL(lookup_quadratic_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_lookup_backward(const PassParams& p, const double2* dout, int npairs, const double* pts,
-                                  int npts, double2* dz, bool quadratic, hipStream_t s) {
-  const LookupArgs a = lookup_args(p, nullptr, npairs, pts, npts, nullptr);
-  const long long n = (long long)npairs * npts;
-  if (quadratic)
-    hipLaunchKernelGGL(lookup_quadratic_backward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, dout,
-                       dz);
-  else
-    hipLaunchKernelGGL(lookup_backward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, dout, dz);
   return hipGetLastError();
 }
 

@@ -260,6 +260,10 @@ spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
                        n2_0, y.n, spec);
 }
 
+// Dynamic LDS of the spectra adjoint's row kernel: the testing and reflected
+// accumulators of every MBF and distinct x-centre.
+size_t adj_spectra_lds_bytes(const GeomDevice& geo, int nmbf) { return sizeof(double2) * 2 * (size_t)nmbf * geo.total_p; }
+
 size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf) {
   (void)nmbf;
   return sizeof(double2) * (size_t)(2 * geo.total_r + geo.ngroups);
@@ -546,7 +550,7 @@ size_t adj_spectra_scratch(const Axis& y, const GeomDevice& geo, int nmbf) {
 hipError_t launch_adj_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
                               const double2* utab, const double2* gspec, int nmbf, double2* rowacc,
                               double2* gq, hipStream_t s) {
-  const size_t lds = sizeof(double2) * 2 * (size_t)nmbf * geo.total_p;
+  const size_t lds = adj_spectra_lds_bytes(geo, nmbf);
   hipLaunchKernelGGL(adj_spectra_rows_kernel, dim3(y.n), dim3(kAdjThreads), lds, s, x, y, gamma, geo, utab,
                      gspec, nmbf, rowacc);
   hipError_t e = hipGetLastError();

@@ -320,3 +320,101 @@ def test_fill_loss_gradient_vs_oracle():
     assert abs(de - o_de) < 1e-9 * abs(o_de), (de, o_de)
     assert abs(dh - o_dh) < 1e-9 * abs(o_dh), (dh, o_dh)
     assert np.abs(dq - o_dq).max() < 1e-9 * np.abs(o_dq).max()
+
+
+def _clustered_points(rng, grid, count):
+    """Points packed into a few table cells (many share a cell), plus some
+    spread over the table, on its edges and outside it."""
+    dxa = co.displacement_axis(grid.nx, grid.kx_max)
+    dya = co.displacement_axis(grid.ny, grid.ky_max)
+    cx, cy = dxa[grid.nx // 3], dya[grid.ny // 2]
+    dd = dxa[1] - dxa[0]
+    tight = np.stack([cx + rng.uniform(0, 2.5 * dd, count), cy + rng.uniform(0, 2.5 * dd, count)], 1)
+    spread = np.stack([rng.uniform(dxa[0], dxa[-1], count // 4), rng.uniform(dya[0], dya[-1], count // 4)], 1)
+    edges = [[dxa[0], dya[0]], [dxa[-1], dya[-1]], [dxa[-2], dya[0]], [dxa[-1] + 1.0, 0.0]]
+    return np.concatenate([tight, spread, edges])
+
+
+def test_interpolation_adjoints_are_deterministic():
+    """The bilinear and second-order lookup adjoints and the fill adjoint give
+    the same bits on every run (sorted per-cell sums, no atomics), with
+    thousands of points sharing a few cells; the bilinear adjoint is the
+    transpose of the lookup."""
+    _say("interpolation adjoints: run-twice determinism")
+    from paper_1404_7357_amd import Tabulator, cfft_fill_backward, cfft_lookup_backward, cfft_lookup_quadratic_backward
+    rng = np.random.default_rng(91)
+    grid = Grid(64, 32, 8 * K0, 6 * K0, K0)
+    tab = Tabulator(grid, rooftop_lattice(1, 1), 3)
+    pts = _clustered_points(rng, grid, 6000)
+    p = torch.tensor(pts, device="cuda")
+    dout = torch.tensor(rng.standard_normal((3, len(pts))) + 1j * rng.standard_normal((3, len(pts))), device="cuda")
+    for name, fn in (("bilinear", cfft_lookup_backward), ("second order", cfft_lookup_quadratic_backward)):
+        runs = []
+        for _ in range(3):
+            dz = torch.zeros((3, 32, 64), dtype=torch.complex128, device="cuda")
+            fn(tab.plan, 0, dout, 3, p, dz)
+            torch.cuda.synchronize()
+            runs.append(dz.cpu())
+        assert torch.equal(runs[0], runs[1]) and torch.equal(runs[0], runs[2]), name
+        assert float(runs[0].abs().max()) > 0
+    # bilinear transpose identity <dout, L z> = <L^T dout, z> on the same points
+    z = torch.tensor(rng.standard_normal((3, 32, 64)) + 1j * rng.standard_normal((3, 32, 64)), device="cuda")
+    v = tab.lookup(z, p)
+    inside = ~torch.isnan(v[0])
+    dz = torch.zeros_like(z)
+    cfft_lookup_backward(tab.plan, 0, dout, 3, p, dz)
+    lhs = torch.sum(torch.conj(dout[:, inside]) * v[:, inside]).item()
+    rhs = torch.sum(torch.conj(dz) * z).item()
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # fill adjoint: a layout with many repeated displacements
+    pos = torch.tensor(rng.integers(-3, 4, (60, 2)) * 0.21 + rng.uniform(0, 1e-3, (60, 2)), device="cuda")
+    pairs = [(0, 0), (0, 2), (1, 1), (2, 1)]
+    am = 60 * 3
+    doutf = torch.tensor(rng.standard_normal((am, am)) + 1j * rng.standard_normal((am, am)), device="cuda")
+    for order in (1, 2):
+        runs = []
+        for _ in range(3):
+            dz = torch.zeros((4, 32, 64), dtype=torch.complex128, device="cuda")
+            cfft_fill_backward(tab.plan, 0, doutf, pairs, 3, pos, order, dz)
+            torch.cuda.synchronize()
+            runs.append(dz.cpu())
+        assert torch.equal(runs[0], runs[1]) and torch.equal(runs[0], runs[2]), order
+    tab.close()
+
+
+def test_backward_is_deterministic():
+    """The whole adjoint (lookup adjoint, adjoint passes, integrand, Green's
+    function and spectra adjoints) run twice gives identical gradients."""
+    _say("backward run-twice determinism")
+    grid, sub, basis, q, pairs, pts, zt = _problem(n=128, m=3, npts=512)
+    a = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt)
+    b = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt)
+    assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
+    assert np.array_equal(a[3], b[3])
+
+
+def test_backward_rejects_a_spectra_adjoint_beyond_lds():
+    """A basis set with 600 distinct x-centres and 4 MBFs needs 76.8 kB of LDS
+    in the spectra adjoint: cfft_backward refuses it on the host, before any
+    adjoint kernel runs, and leaves the gradient buffers untouched."""
+    _say("backward LDS limit")
+    from paper_1404_7357_amd import CfftError, Tabulator, cfft_backward
+    from workloads import ROOFTOP_X, basis_array
+    rng = np.random.default_rng(5)
+    basis = basis_array([(ROOFTOP_X, -0.3 + 0.001 * i, 0.0, 0.01, 0.02) for i in range(600)])
+    grid = Grid(32, 32, 6 * K0, 6 * K0, K0)
+    tab = Tabulator(grid, basis, max_mbf=4)
+    q = torch.tensor(gaussian_coefficients(rng, 4, 600), device="cuda")
+    g = tab.green(2.2, 0.0, 0.05)
+    spec = tab.spectra(q)
+    pairs = [(0, 1), (2, 3)]
+    z = tab.tabulate(spec, g, pairs)
+    dz = torch.ones_like(z)
+    grad_sub = torch.full((2,), 7.0, dtype=torch.float64, device="cuda")
+    grad_q = torch.full_like(q, 7.0)
+    with pytest.raises(CfftError) as ei:
+        cfft_backward(tab.plan, 0, dz, 2.2, 0.0, 0.05, tab.basis, q, pairs, g, spec, grad_sub, grad_q)
+    assert "UNSUPPORTED" in str(ei.value)
+    torch.cuda.synchronize()
+    assert bool((grad_sub == 7.0).all()) and bool((grad_q == 7.0).all())
+    tab.close()

@@ -87,6 +87,35 @@ def test_spectra_match_oracle():
     assert _err(spec, ref) < 1e-12
 
 
+def test_spectra_irregular_mesh_against_oracle():
+    """An irregular mesh (B = 96: rooftops of three sizes at random centres in
+    both orientations, two sharing a slot) takes the general group products of
+    the separable spectra; every sample of a 64 x 32 grid against the oracle."""
+    from workloads import ROOFTOP_X, ROOFTOP_Y
+    rng = np.random.default_rng(606)
+    recs = []
+    for i in range(96):
+        kind = ROOFTOP_X if i % 2 == 0 else ROOFTOP_Y
+        a, b = [(0.04, 0.03), (0.06, 0.02), (0.05, 0.05)][i % 3]
+        recs.append((kind, rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), a, b))
+    recs.append((recs[0][0], recs[0][1], recs[0][2], recs[0][3], recs[0][4]))   # a second basis on one slot
+    basis = basis_array(recs)
+    q = gaussian_coefficients(rng, 3, basis.shape[0])
+    for prec, tol in [(FP64, 1e-12), (MIXED, 1e-7)]:
+        grid = Grid(64, 32, 9 * K0, 7 * K0, K0, precision=prec)
+        _say(f"irregular mesh spectra prec={prec}")
+        tab = _tab(grid, basis, 3)
+        spec = tab.spectra(torch.tensor(q, device="cuda")).cpu().numpy().astype(np.complex128)
+        tab.close()
+        kx, ky = co.grid_samples(grid.nx, grid.ny, grid.kx_max, grid.ky_max)
+        kcx, kcy, _ = co.ray_contour(kx, ky, grid.gamma)
+        mt, mh = co.mbf_spectra(basis, q, kcx, kcy)
+        ref = np.concatenate([mt, mh], axis=1).reshape(spec.shape)
+        err = np.abs(spec - ref).max() / np.abs(ref).max()
+        _say(f"irregular mesh spectra prec={prec} err={err:.3e}")
+        assert err < tol, (prec, err)
+
+
 def test_spectra_cosine_and_duplicates():
     """Half-cosine basis, y-directed kinds, and two bases on one slot (overflow group)."""
     _say("spectra mixed kinds")
