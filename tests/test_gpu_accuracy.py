@@ -13,6 +13,14 @@ order for the moderate heights 1/100 and 1/130; too high a contour
 (1/50) leaves a large Taylor error and too low a one (1/400) runs close to
 the surface-wave pole, where more Taylor terms no longer help but finer
 sampling does; at order 3 the moderate heights are best by a wide margin.
+
+The same study on the parabolic contour (the deformation the paper names,
+Sec. I and Fig. 1: the path leaves the origin with slope gamma and rejoins
+the real axis at beta_end past every pole and branch point): samples beyond
+beta_end lie on the real axis, where E_I = 1 and the Taylor series is exact,
+so a high contour (1/50) keeps far less Taylor error than the ray; near the
+poles the parabola sits lower than the ray of the same gamma, so a low one
+(1/400) runs into the pole sooner.
 """
 import json
 import math
@@ -21,7 +29,7 @@ import sys
 
 import pytest
 
-from workloads import COSINE_X, Grid, basis_array
+from workloads import CONTOUR_PARABOLIC, COSINE_X, Grid, basis_array
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -30,8 +38,9 @@ REF = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "accuracy
 GAMMAS = (50, 100, 130, 200, 400)
 
 
-def _errors_db(n, offset):
-    """20 log10 |Z_table - Z_ref| / |Z_ref| per (1/gamma, P) at one node."""
+def _errors_db(n, offset, beta_end=None):
+    """20 log10 |Z_table - Z_ref| / |Z_ref| per (1/gamma, P) at one node, on the
+    ray contour or (beta_end given) the parabolic one."""
     from paper_1404_7357_amd import Tabulator
     pt = next(p for p in REF["points"] if p["offset"] == offset)
     zr = complex(pt["re"], pt["im"])
@@ -41,12 +50,16 @@ def _errors_db(n, offset):
     for g in GAMMAS:
         for order in range(4):
             grid = Grid(n, n, REF["k_max"], REF["k_max"], REF["k0"], gamma=1.0 / g, order=order)
+            if beta_end is not None:
+                grid.contour, grid.beta_end = CONTOUR_PARABOLIC, beta_end
             tab = Tabulator(grid, basis, 1)
             z = tab.tabulate(tab.spectra(q), tab.green(REF["eps_r"], REF["tan_delta"], REF["h"]), [(0, 0)])
             v = complex(z[0, n // 2 + offset, n // 2 + offset].item())
             tab.close()
             err[(g, order)] = 20.0 * math.log10(abs(v - zr) / abs(zr))
-    print(f"[gpu-case] accuracy N={n} offset={offset} (d = {math.hypot(pt['dx'], pt['dy']):.2f} lambda0)", flush=True)
+    path = "ray" if beta_end is None else f"parabolic, beta_end {beta_end / REF['k0']:.2f} k0"
+    print(f"[gpu-case] accuracy N={n} offset={offset} (d = {math.hypot(pt['dx'], pt['dy']):.2f} lambda0), {path}",
+          flush=True)
     for g in GAMMAS:
         print(f"  gamma 1/{g}: " + " ".join(f"{err[(g, p)]:7.1f}" for p in range(4)) + " dB", flush=True)
     sys.stdout.flush()
@@ -69,3 +82,20 @@ def test_table_i_trend_at_21_lambda():
         assert abs(e[(400, 3)] - e[(400, 1)]) < 1.5                             # terms no longer help
     assert min(e1[(100, 3)], e1[(130, 3)]) < -20.0
     assert e2[(400, 3)] < e1[(400, 3)] - 5.0                                    # finer sampling does
+
+
+@pytest.mark.parametrize("end", [2.0, 3.0])
+def test_parabolic_contour_against_ray(end):
+    """The parabolic contour with beta_end = end sqrt(eps_r) k0 against the ray,
+    both against the continuum, at the 21.2 lambda0 node."""
+    be = end * math.sqrt(REF["eps_r"]) * REF["k0"]
+    best = {}
+    for n in (1024, 2048):
+        ray = _errors_db(n, 222)
+        par = _errors_db(n, 222, beta_end=be)
+        assert par[(50, 3)] < ray[(50, 3)] - 4.0                      # less Taylor error on a high contour
+        for g in (50, 100):
+            assert all(par[(g, p + 1)] < par[(g, p)] - 2.0 for p in range(3)), g   # more terms help
+        assert par[(400, 3)] > ray[(400, 3)]                          # a low parabola meets the pole sooner
+        best[n] = min(par[(g, 3)] for g in GAMMAS)
+    assert best[2048] < -30.0 and best[2048] < best[1024] - 5.0      # finer sampling helps
