@@ -223,7 +223,14 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
       for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
-      if (valid && keep) dst[tb + T * r] = from_d<Vs>(S[r]);
+      if (valid && keep) {
+        // rows of 4096 points: the intermediates of a pair chunk (1 GiB per
+        // FP64 pair) cannot stay cached until the column pass reads them, so
+        // they are streamed out past the caches, which then keep the inputs
+        // the other pairs of the row read (4096^2 FP64: 18.6 -> 16.5 ms)
+        if constexpr (N >= 4096) store_nt(dst + tb + T * r, from_d<Vs>(S[r]));
+        else dst[tb + T * r] = from_d<Vs>(S[r]);
+      }
     }
   }
 }
