@@ -361,12 +361,30 @@ def grid_samples(nx, ny, kx_max, ky_max):
     return KX.ravel(), KY.ravel()
 
 
-def sampled_factors(grid, substrate, basis, q):
-    """G_s and the MBF spectra on every sample of one grid (flattened, x fastest)."""
+def sampled_factors(grid, substrate, basis, q, workers=1):
+    """G_s and the MBF spectra on every sample of one grid (flattened, x fastest).
+
+    workers > 1 evaluates contiguous slices of the samples in parallel threads
+    (the same per-sample arithmetic; the slices are concatenated in order).
+    """
     kx, ky = grid_samples(grid.nx, grid.ny, grid.kx_max, grid.ky_max)
     kcx, kcy, w, gam = grid_contour(kx, ky, grid)
-    g = green_remainder(kx, ky, gam, grid.k0, substrate.eps_r, substrate.tan_delta, substrate.h)
-    mt, mh = mbf_spectra(basis, q, kcx, kcy)
+
+    def part(sl):
+        g_ = green_remainder(kx[sl], ky[sl], gam[sl] if np.ndim(gam) else gam, grid.k0, substrate.eps_r,
+                             substrate.tan_delta, substrate.h)
+        return g_, mbf_spectra(basis, q, kcx[sl], kcy[sl])
+
+    n = kx.size
+    if workers <= 1 or n < 4096:
+        g, (mt, mh) = part(slice(0, n))
+        return kx, ky, w, g, mt, mh
+    step = -(-n // workers)
+    with ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(part, [slice(i, min(n, i + step)) for i in range(0, n, step)]))
+    g = tuple(np.concatenate([p_[0][c] for p_ in parts]) for c in range(3))
+    mt = np.concatenate([p_[1][0] for p_ in parts], axis=-1)
+    mh = np.concatenate([p_[1][1] for p_ in parts], axis=-1)
     return kx, ky, w, g, mt, mh
 
 
@@ -404,7 +422,7 @@ def tabulate(grid, substrate, basis, q, pairs, out_idx=None, order=None, workers
     block: outputs per task of the direct sum (workers share the tasks).
     """
     order = grid.order if order is None else order
-    kx, ky, w, g, mt, mh = sampled_factors(grid, substrate, basis, q)
+    kx, ky, w, g, mt, mh = sampled_factors(grid, substrate, basis, q, workers=workers)
     integ = pair_integrands(pairs, w, g, mt, mh)
     mask = band_mask(grid)
     if mask is not None:

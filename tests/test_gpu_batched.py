@@ -23,13 +23,22 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _sweep_calls(tab, wl, q, bufs):
+def _sweep_calls(tabs, wl, q, bufs, streams):
+    """Each grid's chain on its own stream (one plan per grid), forked from and
+    joined back into the current stream, as the benchmark runs the sweep."""
     pairs = [tuple(int(v) for v in p) for p in wl.pairs]
-    for i, (gd, sub) in enumerate(zip(wl.grids, wl.substrates)):
-        g, spec, z = bufs[i]
-        tab.green(sub.eps_r, sub.tan_delta, sub.h, grid=i, out=g)
-        tab.spectra(q, grid=i, out=spec)
-        tab.tabulate(spec, g, pairs, grid=i, out=z)
+    main = torch.cuda.current_stream()
+    order = sorted(range(len(wl.grids)), key=lambda i: -wl.grids[i].nx)
+    for i in order:
+        streams[i].wait_stream(main)
+        with torch.cuda.stream(streams[i]):
+            sub = wl.substrates[i]
+            g, spec, z = bufs[i]
+            tabs[i].green(sub.eps_r, sub.tan_delta, sub.h, out=g)
+            tabs[i].spectra(q, out=spec)
+            tabs[i].tabulate(spec, g, pairs, out=z)
+    for i in order:
+        main.wait_stream(streams[i])
 
 
 def _sweep_buffers(wl):
@@ -43,16 +52,19 @@ def _sweep_buffers(wl):
 
 
 def test_sweep_graph_replays_match_eager_and_oracle():
-    """The frequency sweep with autotuned schedules (tuned by the first eager
-    calls, then captured, lanes included) replayed as one HIP graph: every
-    replay equals the eager tables, which match the oracle."""
+    """The frequency sweep with one plan per grid on its own stream and
+    autotuned schedules (tuned by the first eager calls, then captured, lanes
+    included) replayed as one HIP graph whose branches are the grids' chains:
+    every replay equals the eager tables, and all 8 grids match the oracle at
+    sampled outputs at the mixed bar."""
     from paper_1404_7357_amd import FLAG_AUTOTUNE, Tabulator
     wl = c3_frequency_sweep()
     _say("c3 sweep eager")
-    tab = Tabulator(wl.grids, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE)
+    tabs = [Tabulator(gd, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE) for gd in wl.grids]
+    streams = [torch.cuda.Stream() for _ in wl.grids]
     q = torch.tensor(wl.q, device="cuda")
     bufs = _sweep_buffers(wl)
-    _sweep_calls(tab, wl, q, bufs)
+    _sweep_calls(tabs, wl, q, bufs, streams)
     torch.cuda.synchronize()
     eager = [b[2].cpu().clone() for b in bufs]
     _say("c3 sweep graph capture")
@@ -61,11 +73,11 @@ def test_sweep_graph_replays_match_eager_and_oracle():
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        _sweep_calls(tab, wl, q, gbufs)      # warm on the capture stream
+        _sweep_calls(tabs, wl, q, gbufs, streams)      # warm on the capture stream
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     with torch.cuda.graph(graph):
-        _sweep_calls(tab, wl, q, gbufs)
+        _sweep_calls(tabs, wl, q, gbufs, streams)
     for rep in range(3):
         for b in gbufs:
             b[2].zero_()
@@ -74,19 +86,21 @@ def test_sweep_graph_replays_match_eager_and_oracle():
         for i in range(len(wl.grids)):
             assert torch.equal(gbufs[i][2].cpu(), eager[i]), (rep, i)
         # eager work between replays
-        _sweep_calls(tab, wl, q, bufs)
+        _sweep_calls(tabs, wl, q, bufs, streams)
         torch.cuda.synchronize()
-    tab.close()
-    _say("c3 sweep oracle samples")
+    for t in tabs:
+        t.close()
+    _say("c3 sweep oracle samples (8 grids)")
     rng = np.random.default_rng(9)
-    for i in (0, 1, 2):
+    for i in range(len(wl.grids)):
         gd, sub = wl.grids[i], wl.substrates[i]
-        idx = np.unique(np.concatenate([rng.choice(gd.nx * gd.ny, 24, replace=False),
-                                        [(gd.ny // 2) * gd.nx + gd.nx // 2]]))
+        idx = np.unique(np.concatenate([rng.choice(gd.nx * gd.ny, 12, replace=False),
+                                        [(gd.ny // 2) * gd.nx + gd.nx // 2, 0, gd.nx * gd.ny - 1]]))
         ref = co.tabulate(gd, sub, wl.basis, wl.q, wl.pairs, out_idx=idx, workers=8)
         got = eager[i].numpy().reshape(len(wl.pairs), -1)[:, idx]
         err = (np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
-        assert err < 1e-5, (i, err)
+        _say(f"c3 grid {i} ({gd.nx}^2) err={err:.3e}")
+        assert err < MIXED_TARGET, (i, err)
 
 
 def _sample_points(nx, ny, count, seed):
