@@ -75,6 +75,9 @@ struct PassParams {
   double beta_end;
   int band;           // 1: x2 zero-padded grid, integrand only on n in [N/4, 3N/4) per axis
   int col_narrow;     // 1: column tiles of half the default width
+  int stream_out;     // 1: the row pass writes the intermediates with non-temporal
+                      // stores (a launch's intermediates too large to stay in the
+                      // memory-side cache until the column pass reads them)
 };
 
 // Intermediate arrays per pair between the row and column passes.

@@ -67,6 +67,7 @@ template <int N, int R> struct RowCfg {
 
 struct RowArgs {
   int tensor;   // tensor-product truncation: only S_P is stored, in slot 0
+  int stream_out;   // write the intermediates with non-temporal stores (see PassParams)
   int band;     // x2 zero-padded grid: integrand only on n in [N/4, 3N/4) per axis
   int parabolic;                // per-sample contour ratio (see row_terms_general)
   double ky0, dky, beta_end;
@@ -224,11 +225,7 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
       if (valid && keep) {
-        // rows of 4096 points: the intermediates of a pair chunk (1 GiB per
-        // FP64 pair) cannot stay cached until the column pass reads them, so
-        // they are streamed out past the caches, which then keep the inputs
-        // the other pairs of the row read (4096^2 FP64: 18.6 -> 16.5 ms)
-        if constexpr (N >= 4096) store_nt(dst + tb + T * r, from_d<Vs>(S[r]));
+        if (a.stream_out) store_nt(dst + tb + T * r, from_d<Vs>(S[r]));
         else dst[tb + T * r] = from_d<Vs>(S[r]);
       }
     }
@@ -244,6 +241,7 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
 // input arrays per pair instead of 7.
 struct RowGArgs {
   int tensor;
+  int stream_out;
   int band;
   int parabolic;
   double ky0, dky, beta_end;
@@ -360,7 +358,10 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<Vc, N>())) row_p
       for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
       const double2 xv = to_d(x[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
-      if (active && keep) dst[tb + T * r] = from_d<Vs>(S[r]);
+      if (active && keep) {
+        if (a.stream_out) store_nt(dst + tb + T * r, from_d<Vs>(S[r]));
+        else dst[tb + T * r] = from_d<Vs>(S[r]);
+      }
     }
   }
 }
@@ -570,6 +571,7 @@ static hipError_t rowg_launch(const RowArgs& ra, hipStream_t s) {
   a.ny = ra.ny;
   a.order = ra.order;
   a.tensor = ra.tensor;
+  a.stream_out = ra.stream_out;
   a.band = ra.band;
   a.parabolic = ra.parabolic;
   a.ky0 = ra.ky0;
@@ -646,6 +648,7 @@ hipError_t launch_row_pass(const PassParams& p, const double2* g, const void* sp
   a.ny = p.y.n;
   a.order = p.order;
   a.tensor = p.tensor;
+  a.stream_out = p.stream_out;
   a.band = p.band;
   a.parabolic = p.parabolic;
   a.ky0 = p.y.k_first;
