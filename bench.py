@@ -367,17 +367,14 @@ def _paper_leg(torch, steps, warmup):
 
 
 def _sweep(torch, steps, warmup):
-    """Frequency sweep, 8 uneven grids x 16 pairs (mixed): one plan per grid (each
-    with its own workspace and autotuned schedule), each grid's Green's
-    function, spectra and table on its own stream, forked from and joined back
-    into the caller's stream, largest grids first; eager and as one replayed
-    HIP graph (the grids' chains are the graph's parallel branches)."""
+    """Frequency sweep, 8 uneven grids x 16 pairs (mixed), eager and as one replayed HIP graph; the
+    schedules are autotuned per grid by the first (warm-up) calls, before the capture."""
     import numpy as np
 
     from paper_1404_7357_amd import FLAG_AUTOTUNE, Tabulator
     from workloads import c3_frequency_sweep
     wl = c3_frequency_sweep()
-    tabs = [Tabulator(gd, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE) for gd in wl.grids]
+    tab = Tabulator(wl.grids, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE)
     q = torch.tensor(wl.q, device="cuda")
     pairs = [tuple(int(v) for v in p) for p in wl.pairs]
     bufs = []
@@ -385,21 +382,13 @@ def _sweep(torch, steps, warmup):
         bufs.append((torch.empty((3, gd.ny, gd.nx), dtype=torch.complex128, device="cuda"),
                      torch.empty((wl.M, 4, gd.ny, gd.nx), dtype=torch.complex64, device="cuda"),
                      torch.empty((len(pairs), gd.ny, gd.nx), dtype=torch.complex64, device="cuda")))
-    streams = [torch.cuda.Stream() for _ in wl.grids]
-    order = sorted(range(len(wl.grids)), key=lambda i: -wl.grids[i].nx)
 
     def calls():
-        main = torch.cuda.current_stream()
-        for i in order:
-            streams[i].wait_stream(main)
-            with torch.cuda.stream(streams[i]):
-                sub = wl.substrates[i]
-                g, spec, z = bufs[i]
-                tabs[i].green(sub.eps_r, sub.tan_delta, sub.h, out=g)
-                tabs[i].spectra(q, out=spec)
-                tabs[i].tabulate(spec, g, pairs, out=z)
-        for i in order:
-            main.wait_stream(streams[i])
+        for i, (gd, sub) in enumerate(zip(wl.grids, wl.substrates)):
+            g, spec, z = bufs[i]
+            tab.green(sub.eps_r, sub.tan_delta, sub.h, grid=i, out=g)
+            tab.spectra(q, grid=i, out=spec)
+            tab.tabulate(spec, g, pairs, grid=i, out=z)
 
     t_eager, _ = _timed(torch, calls, steps, warmup)
     side = torch.cuda.Stream()
@@ -418,11 +407,10 @@ def _sweep(torch, steps, warmup):
         it = torch.tensor(idx, device="cuda")
         samples.append((idx, bufs[i][2].reshape(len(pairs), -1)[:, it].cpu().numpy().astype(np.complex128)))
     entries = sum(gd.nx * gd.ny for gd in wl.grids) * len(pairs)
-    for t in tabs:
-        t.close()
+    tab.close()
     return {"workload": wl.name, "entries": entries, "value_graph": entries / t_graph,
             "ms_graph": t_graph * 1e3, "value_eager": entries / t_eager, "ms_eager": t_eager * 1e3,
-            "dtype": "fp32 storage", "streams": len(wl.grids)}, {"wl": wl, "samples": samples}
+            "dtype": "fp32 storage"}, {"wl": wl, "samples": samples}
 
 
 def _adjoint_ratio(torch, steps, warmup):

@@ -144,6 +144,46 @@ __device__ __forceinline__ void row_terms_general(const Args& a, const Vc (&f)[R
   }
 }
 
+// Integrand samples s(n1) W H(n1, n2) of the R points of thread t on row n2
+// (H = Mx_m (Gxx Mx#_n + Gxy My#_n) + My_m (Gxy Mx#_n + Gyy My#_n)).  The
+// loads of all points are issued without branches (a row past the end reads
+// row row0 and is zeroed by a select) so that they are in flight together.
+// On a zero-padded grid (BAND) the point n1 = t + T r lies in the band
+// [N/4, 3N/4) exactly when R/4 <= r < 3R/4 (T = N/R), the same for every
+// thread, so the other points are neither loaded nor computed.
+template <bool BAND, typename Vs, typename Vc, int N, int R>
+__device__ __forceinline__ void row_inputs(const RowArgs& a, int t, int n2, bool valid, int row0, int m, int n,
+                                           size_t plane, Vc (&f)[R]) {
+  constexpr int T = N / R;
+  const size_t rowb = (size_t)(valid ? n2 : row0) * N;
+  const Vs* sp = (const Vs*)a.spec;
+  const Vs* spm = sp + (size_t)m * 4 * plane + rowb;
+  const Vs* spn = sp + ((size_t)n * 4 + 2) * plane + rowb;
+  const double2* gr = a.g + rowb;
+  auto live = [](int r) { return !BAND || (4 * r >= R && 4 * r < 3 * R); };
+  double2 h[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    h[r] = make_double2(0.0, 0.0);
+    if (!live(r)) continue;
+    const int n1 = t + T * r;
+    const double2 gxx = gr[n1], gxy = gr[plane + n1], gyy = gr[2 * plane + n1];
+    const double2 mx = to_d(spm[n1]), my = to_d(spm[plane + n1]);
+    const double2 mxh = to_d(spn[n1]), myh = to_d(spn[plane + n1]);
+    h[r] = cadd(cmul(mx, cadd(cmul(gxx, mxh), cmul(gxy, myh))), cmul(my, cadd(cmul(gxy, mxh), cmul(gyy, myh))));
+  }
+  if (a.parabolic) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (live(r)) h[r] = cmul(h[r], contour_weight(a, a.kx0 + (t + T * r) * a.dkx, a.ky0 + n2 * a.dky));
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double2 v = (live(r) && ((t + T * r) & 1)) ? make_double2(-h[r].x, -h[r].y) : h[r];
+    f[r] = from_d<Vc>(valid ? v : make_double2(0.0, 0.0));
+  }
+}
+
 template <typename Vs, typename Vc, int N, int R>
 __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>())) row_pass_kernel(RowArgs a) {
   using Cfg = RowCfg<N, R>;
@@ -167,24 +207,8 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
   Vs* inter = (Vs*)a.inter;
 
   Vc f[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int n1 = t + T * r;
-    double2 h = make_double2(0.0, 0.0);
-    if (valid && (!a.band || in_band(n1, N))) {
-      const size_t idx = (size_t)n2 * N + n1;
-      const double2 gxx = a.g[idx], gxy = a.g[plane + idx], gyy = a.g[2 * plane + idx];
-      const Vs* sp = (const Vs*)a.spec;
-      const double2 mx = to_d(sp[((size_t)m * 4 + 0) * plane + idx]);
-      const double2 my = to_d(sp[((size_t)m * 4 + 1) * plane + idx]);
-      const double2 mxh = to_d(sp[((size_t)n * 4 + 2) * plane + idx]);
-      const double2 myh = to_d(sp[((size_t)n * 4 + 3) * plane + idx]);
-      h = cadd(cmul(mx, cadd(cmul(gxx, mxh), cmul(gxy, myh))), cmul(my, cadd(cmul(gxy, mxh), cmul(gyy, myh))));
-      if (n1 & 1) h = make_double2(-h.x, -h.y);
-      if (a.parabolic) h = cmul(h, contour_weight(a, a.kx0 + n1 * a.dkx, a.ky0 + n2 * a.dky));
-    }
-    f[r] = from_d<Vc>(h);
-  }
+  if (a.band) row_inputs<true, Vs, Vc, N, R>(a, t, n2, valid, row0, m, n, plane, f);
+  else row_inputs<false, Vs, Vc, N, R>(a, t, n2, valid, row0, m, n, plane, f);
   Vc* my_lds = lds + grp * lds_len<row_pad<Vc>()>(N);
   __syncthreads();   // twiddle tables ready
   if (a.parabolic) {
@@ -265,6 +289,70 @@ template <int N, int NPW> struct RowGCfg {
   static constexpr int THREADS = NPW * T;
 };
 
+// A tables of the grouped row pass (see above) for row n2, in LDS.  The loads
+// of all of a thread's entries are issued without branches so that they are
+// in flight together; the contour weight follows in a loop of its own.  On a
+// zero-padded grid (BAND) only the band [N/4, 3N/4) is formed: the
+// transforms never read the entries outside it.
+template <bool BAND, typename Vs, int N, int THREADS>
+__device__ __forceinline__ void grouped_a_tables(const RowGArgs& a, int m, int n2, size_t row, size_t plane,
+                                                 double2* ax, double2* ay) {
+  constexpr int LEN = BAND ? N / 2 : N;
+  constexpr int I0 = BAND ? N / 4 : 0;
+  constexpr int PER = LEN / THREADS;
+  static_assert(PER * THREADS == LEN, "whole rows per block");
+  const Vs* sp = (const Vs*)a.spec;
+  double2 vx[PER], vy[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = I0 + threadIdx.x + THREADS * u;
+    const double2 gxx = a.g[row + i], gxy = a.g[plane + row + i], gyy = a.g[2 * plane + row + i];
+    const double2 mx = to_d(sp[((size_t)m * 4 + 0) * plane + row + i]);
+    const double2 my = to_d(sp[((size_t)m * 4 + 1) * plane + row + i]);
+    vx[u] = cfma(cmul(mx, gxx), my, gxy);
+    vy[u] = cfma(cmul(mx, gxy), my, gyy);
+  }
+  if (a.parabolic) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = I0 + threadIdx.x + THREADS * u;
+      const double2 wc = contour_weight(a, a.kx0 + i * a.dkx, a.ky0 + n2 * a.dky);
+      vx[u] = cmul(vx[u], wc);
+      vy[u] = cmul(vy[u], wc);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = I0 + threadIdx.x + THREADS * u;
+    ax[i] = (i & 1) ? make_double2(-vx[u].x, -vx[u].y) : vx[u];
+    ay[i] = (i & 1) ? make_double2(-vy[u].x, -vy[u].y) : vy[u];
+  }
+}
+
+// Integrand samples H = A_x Mx#_n + A_y My#_n of the R points of thread t
+// (zero for an inactive transform slot, whose loads stay in the plane of
+// pair 0).  On a zero-padded grid only the points R/4 <= r < 3R/4 lie in
+// the band (n1 = t + T r, T = N/R) and are loaded.
+template <bool BAND, typename Vs, typename Vc, int N, int R>
+__device__ __forceinline__ void grouped_inputs(const Vs* sp, int n, size_t row, size_t plane, int t, bool active,
+                                               const double2* ax, const double2* ay, Vc (&f)[R]) {
+  constexpr int T = N / R;
+  auto live = [](int r) { return !BAND || (4 * r >= R && 4 * r < 3 * R); };
+  const Vs* spn = sp + ((size_t)n * 4 + 2) * plane + row;
+  double2 mxh[R], myh[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!live(r)) continue;
+    mxh[r] = to_d(spn[t + T * r]);
+    myh[r] = to_d(spn[plane + t + T * r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int n1 = t + T * r;
+    f[r] = from_d<Vc>(live(r) && active ? cfma(cmul(ax[n1], mxh[r]), ay[n1], myh[r]) : make_double2(0.0, 0.0));
+  }
+}
+
 template <typename Vs, typename Vc, int N, int NPW>
 __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<Vc, N>())) row_pass_grouped_kernel(RowGArgs a) {
   using Cfg = RowGCfg<N, NPW>;
@@ -283,28 +371,8 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<Vc, N>())) row_p
   const int m = a.gm[grp];
   const size_t row = (size_t)n2 * N;
   const Vs* sp = (const Vs*)a.spec;
-  for (int i = threadIdx.x; i < N; i += Cfg::THREADS) {
-    if (a.band && !in_band(i, N)) {
-      ax[i] = ay[i] = make_double2(0.0, 0.0);
-      continue;
-    }
-    const double2 gxx = a.g[row + i], gxy = a.g[plane + row + i], gyy = a.g[2 * plane + row + i];
-    const double2 mx = to_d(sp[((size_t)m * 4 + 0) * plane + row + i]);
-    const double2 my = to_d(sp[((size_t)m * 4 + 1) * plane + row + i]);
-    double2 vx = cfma(cmul(mx, gxx), my, gxy);
-    double2 vy = cfma(cmul(mx, gxy), my, gyy);
-    if (i & 1) {
-      vx = make_double2(-vx.x, -vx.y);
-      vy = make_double2(-vy.x, -vy.y);
-    }
-    if (a.parabolic) {
-      const double2 wc = contour_weight(a, a.kx0 + i * a.dkx, a.ky0 + n2 * a.dky);
-      vx = cmul(vx, wc);
-      vy = cmul(vy, wc);
-    }
-    ax[i] = vx;
-    ay[i] = vy;
-  }
+  if (a.band) grouped_a_tables<true, Vs, N, Cfg::THREADS>(a, m, n2, row, plane, ax, ay);
+  else grouped_a_tables<false, Vs, N, Cfg::THREADS>(a, m, n2, row, plane, ax, ay);
   __syncthreads();   // A tables and twiddle tables ready
   const bool active = w < a.gcnt[grp];
   if constexpr (T <= 64) {
@@ -313,17 +381,8 @@ __global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<Vc, N>())) row_p
   const int pair = active ? a.gpair[a.gfirst[grp] + w] : 0;
   const int n = a.pn[pair];
   Vc f[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int n1 = t + T * r;
-    double2 h = make_double2(0.0, 0.0);
-    if (active && (!a.band || in_band(n1, N))) {
-      const double2 mxh = to_d(sp[((size_t)n * 4 + 2) * plane + row + n1]);
-      const double2 myh = to_d(sp[((size_t)n * 4 + 3) * plane + row + n1]);
-      h = cfma(cmul(ax[n1], mxh), ay[n1], myh);
-    }
-    f[r] = from_d<Vc>(h);
-  }
+  if (a.band) grouped_inputs<true, Vs, Vc, N, R>(sp, n, row, plane, t, active, ax, ay, f);
+  else grouped_inputs<false, Vs, Vc, N, R>(sp, n, row, plane, t, active, ax, ay, f);
   Vc* my_lds = lds + w * lds_len<row_pad<Vc>()>(N);
   Vs* inter = (Vs*)a.inter;
   if (a.parabolic) {

@@ -23,22 +23,15 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _sweep_calls(tabs, wl, q, bufs, streams):
-    """Each grid's chain on its own stream (one plan per grid), forked from and
-    joined back into the current stream, as the benchmark runs the sweep."""
+def _sweep_calls(tab, wl, q, bufs):
+    """The grids' chains (Green's function, spectra, table) one after the
+    other on the current stream, through one plan holding all 8 grids."""
     pairs = [tuple(int(v) for v in p) for p in wl.pairs]
-    main = torch.cuda.current_stream()
-    order = sorted(range(len(wl.grids)), key=lambda i: -wl.grids[i].nx)
-    for i in order:
-        streams[i].wait_stream(main)
-        with torch.cuda.stream(streams[i]):
-            sub = wl.substrates[i]
-            g, spec, z = bufs[i]
-            tabs[i].green(sub.eps_r, sub.tan_delta, sub.h, out=g)
-            tabs[i].spectra(q, out=spec)
-            tabs[i].tabulate(spec, g, pairs, out=z)
-    for i in order:
-        main.wait_stream(streams[i])
+    for i, (gd, sub) in enumerate(zip(wl.grids, wl.substrates)):
+        g, spec, z = bufs[i]
+        tab.green(sub.eps_r, sub.tan_delta, sub.h, grid=i, out=g)
+        tab.spectra(q, grid=i, out=spec)
+        tab.tabulate(spec, g, pairs, grid=i, out=z)
 
 
 def _sweep_buffers(wl):
@@ -52,19 +45,18 @@ def _sweep_buffers(wl):
 
 
 def test_sweep_graph_replays_match_eager_and_oracle():
-    """The frequency sweep with one plan per grid on its own stream and
+    """The frequency sweep through one plan holding all 8 grids, with
     autotuned schedules (tuned by the first eager calls, then captured, lanes
-    included) replayed as one HIP graph whose branches are the grids' chains:
-    every replay equals the eager tables, and all 8 grids match the oracle at
-    sampled outputs at the mixed bar."""
+    included), replayed as one HIP graph: every replay equals the eager
+    tables, and all 8 grids match the oracle at sampled outputs at the mixed
+    bar."""
     from paper_1404_7357_amd import FLAG_AUTOTUNE, Tabulator
     wl = c3_frequency_sweep()
     _say("c3 sweep eager")
-    tabs = [Tabulator(gd, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE) for gd in wl.grids]
-    streams = [torch.cuda.Stream() for _ in wl.grids]
+    tab = Tabulator(wl.grids, wl.basis, max_mbf=wl.M, flags=FLAG_AUTOTUNE)
     q = torch.tensor(wl.q, device="cuda")
     bufs = _sweep_buffers(wl)
-    _sweep_calls(tabs, wl, q, bufs, streams)
+    _sweep_calls(tab, wl, q, bufs)
     torch.cuda.synchronize()
     eager = [b[2].cpu().clone() for b in bufs]
     _say("c3 sweep graph capture")
@@ -73,11 +65,11 @@ def test_sweep_graph_replays_match_eager_and_oracle():
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        _sweep_calls(tabs, wl, q, gbufs, streams)      # warm on the capture stream
+        _sweep_calls(tab, wl, q, gbufs)      # warm on the capture stream
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     with torch.cuda.graph(graph):
-        _sweep_calls(tabs, wl, q, gbufs, streams)
+        _sweep_calls(tab, wl, q, gbufs)
     for rep in range(3):
         for b in gbufs:
             b[2].zero_()
@@ -86,10 +78,9 @@ def test_sweep_graph_replays_match_eager_and_oracle():
         for i in range(len(wl.grids)):
             assert torch.equal(gbufs[i][2].cpu(), eager[i]), (rep, i)
         # eager work between replays
-        _sweep_calls(tabs, wl, q, bufs, streams)
+        _sweep_calls(tab, wl, q, bufs)
         torch.cuda.synchronize()
-    for t in tabs:
-        t.close()
+    tab.close()
     _say("c3 sweep oracle samples (8 grids)")
     rng = np.random.default_rng(9)
     for i in range(len(wl.grids)):
