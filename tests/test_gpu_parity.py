@@ -173,11 +173,13 @@ def test_shapes_fp64_and_mixed(nx, ny):
         _full_case(f"{nx}x{ny} prec={prec}", grid, Substrate(2.2, 0.0, 0.05), basis, q, pairs, tol)
 
 
-@pytest.mark.parametrize("nx,ny", [(2048, 16), (16, 2048), (1024, 32), (32, 1024), (4096, 16), (16, 4096)])
+@pytest.mark.parametrize("nx,ny", [(2048, 16), (16, 2048), (1024, 32), (32, 1024), (4096, 16), (16, 4096),
+                                   (64, 2048), (64, 4096)])
 def test_long_axes_sampled(nx, ny):
     """Transform lengths 1024, 2048 and 4096 along either axis (block-wide
     exchanges, two-level twiddle tables; 4096-point columns in two-column
-    tiles), FP64 and mixed, at sampled outputs including the
+    tiles; 64 columns under columns of 2048 and 4096 points), FP64 and mixed,
+    at sampled outputs including the
     table corners and Delta = 0.  The mixed bar is 1e-5 at every length: past
     2048 points the library transforms mixed grids in FP64 on FP32-stored
     data, since FP32 transforms met 1.1e-5 at 4096 points."""
@@ -330,7 +332,7 @@ def test_many_pairs_chunked(monkeypatch):
 
 @pytest.mark.parametrize("nx,ny,variant", [(64, 32, "ray"), (128, 512, "ray"), (32, 64, "parabolic"),
                                             (256, 128, "tensor"), (128, 64, "band"), (16, 2048, "ray"),
-                                            (16, 4096, "ray")])
+                                            (16, 4096, "ray"), (64, 2048, "tensor"), (64, 4096, "ray")])
 def test_narrow_column_tiles(monkeypatch, nx, ny, variant):
     """The autotuner's alternative column tiles (half the default width),
     forced, against the oracle: FP64 and mixed, ray and parabolic contours,
@@ -518,7 +520,7 @@ def test_fill_matches_oracle_on_given_tables():
 
 
 @pytest.mark.parametrize("nx,ny,variant", [(64, 32, "ray"), (32, 128, "parabolic"), (256, 64, "tensor"),
-                                            (2048, 16, "ray"), (16, 2048, "ray")])
+                                            (2048, 16, "ray"), (16, 2048, "ray"), (64, 2048, "ray")])
 def test_zero_padded_kernels_and_variants(nx, ny, variant):
     """Zero-padded grids through both row kernels (one row per block of
     several, short and long rows), the column pass skipping the zero rows,
