@@ -122,7 +122,19 @@ hipError_t launch_spectra_tables(const Axis& x, const Axis& y, double gamma, con
 constexpr int kSpecThreads = 256;   // spectra kernel block size
 constexpr int kSpecRows = 2;         // rows per spectra block
 constexpr int kMaxGroups = 32;  // host refuses basis sets needing more
-constexpr int kMChunk = 4;
+constexpr int kMChunk = 4;   // MBFs per pass of the parabolic (direct) kernel
+
+// MBFs per pass of the separable per-sample kernel: 3 or 4, whichever pads
+// the MBF count less (M = 6: 6 not 8 slots, M = 9: 9 not 12; ties take 4).
+// The w tables hold mpad = the padded count of MBF slots.
+static int spectra_mchunk(int nmbf) {
+  const int p3 = (nmbf + 2) / 3 * 3, p4 = (nmbf + 3) / 4 * 4;
+  return p3 < p4 ? 3 : 4;
+}
+static int spectra_mpad(int nmbf) {
+  const int mc = spectra_mchunk(nmbf);
+  return (nmbf + mc - 1) / mc * mc;
+}
 
 // Per-row contraction over y-centres, one thread per table entry
 //   v = 0:  w [n2][m][pp] = SY_g(n2) sum_r conj(q_m,j(g,p,r)) V_gr(n2)
@@ -187,20 +199,20 @@ spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ 
 //   M_m^c(n1, n2) = sum_{g of component c} sum_p (SX_g U_gp)(n1) w[n2][m][p].
 // A U value is loaded once and used for every row.  Padded centres use a
 // clamped U times a zero w.
-template <int RB, typename O>
+template <int RB, int MC, typename O>
 __device__ __forceinline__ void spectra_block(const GeomDevice& geo, const double2* __restrict__ utab, size_t rs,
                                               unsigned boff, const double2* const (&wrow)[RB], int v, int nmbf,
                                               int mpad, int n1, int n2_0, int ny, O* __restrict__ spec) {
   const int ppad = geo.ppad;
   const size_t plane = rs * (size_t)ny;
-  for (int m0 = 0; m0 < mpad; m0 += kMChunk) {
+  for (int m0 = 0; m0 < mpad; m0 += MC) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      double2 acc[RB][kMChunk];
+      double2 acc[RB][MC];
 #pragma unroll
       for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int i = 0; i < kMChunk; ++i) acc[r][i] = make_double2(0.0, 0.0);
+        for (int i = 0; i < MC; ++i) acc[r][i] = make_double2(0.0, 0.0);
       const int g0 = c == 0 ? 0 : geo.ngroups_x;
       const int g1 = c == 0 ? geo.ngroups_x : geo.ngroups;
       for (int g = g0; g < g1; ++g) {
@@ -220,7 +232,7 @@ __device__ __forceinline__ void spectra_block(const GeomDevice& geo, const doubl
 #pragma unroll
             for (int k = 0; k < kSpecPChunk; ++k) {
 #pragma unroll
-              for (int i = 0; i < kMChunk; ++i) acc[r][i] = cfma(acc[r][i], u[k], wg[(size_t)i * ppad + k]);
+              for (int i = 0; i < MC; ++i) acc[r][i] = cfma(acc[r][i], u[k], wg[(size_t)i * ppad + k]);
             }
           }
         }
@@ -229,7 +241,7 @@ __device__ __forceinline__ void spectra_block(const GeomDevice& geo, const doubl
       for (int r = 0; r < RB; ++r) {
         if (n2_0 + r >= ny) continue;
 #pragma unroll
-        for (int i = 0; i < kMChunk; ++i) {
+        for (int i = 0; i < MC; ++i) {
           if (m0 + i < nmbf)
             spec[((size_t)(m0 + i) * 4 + 2 * v + c) * plane + (size_t)(n2_0 + r) * rs + n1] = from_d<O>(acc[r][i]);
         }
@@ -244,7 +256,7 @@ __device__ __forceinline__ void spectra_block(const GeomDevice& geo, const doubl
 // 0 = M with U and w, 1 = M# with U# and w#).  O is the stored type:
 // complex128 for FP64 grids, complex64 (rounded from the FP64 sums) for
 // mixed ones.
-template <typename O>
+template <typename O, int MC>
 __global__ void __launch_bounds__(kSpecThreads)
 spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
                const double2* __restrict__ wtab, int nmbf, int mpad, O* __restrict__ spec) {
@@ -256,7 +268,7 @@ spectra_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
   const double2* wrow[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) wrow[r] = wtab + ((size_t)min(n2_0 + r, y.n - 1) * 2 + v) * mpad * geo.ppad;
-  spectra_block<RB, O>(geo, utab, (size_t)x.n, (unsigned)n1 * (unsigned)sizeof(double2), wrow, v, nmbf, mpad, n1,
+  spectra_block<RB, MC, O>(geo, utab, (size_t)x.n, (unsigned)n1 * (unsigned)sizeof(double2), wrow, v, nmbf, mpad, n1,
                        n2_0, y.n, spec);
 }
 
@@ -271,26 +283,35 @@ size_t spectra_lds_bytes(const GeomDevice& geo, int nmbf) {
 
 
 size_t spectra_scratch_len(const Axis& y, const GeomDevice& geo, int nmbf) {
-  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
-  return (size_t)y.n * 2 * mpad * geo.ppad;
+  return (size_t)y.n * 2 * spectra_mpad(nmbf) * geo.ppad;
 }
 
 hipError_t launch_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo, const double2* utab,
                           const double2* q, int nmbf, double2* scratch, void* spec, int precision, hipStream_t s) {
   (void)gamma;
-  const int mpad = (nmbf + kMChunk - 1) / kMChunk * kMChunk;
+  const int mpad = spectra_mpad(nmbf);
   dim3 grid((x.n + kSpecThreads - 1) / kSpecThreads, (y.n + kSpecRows - 1) / kSpecRows, 2);
   const long long rows_entries = (long long)2 * mpad * geo.ppad * y.n;
   hipLaunchKernelGGL(spectra_rows_kernel, dim3((unsigned)((rows_entries + kRowsThreads - 1) / kRowsThreads)),
                      dim3(kRowsThreads), 0, s, x, y, geo, utab, q, nmbf, mpad, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (precision == 0)
-    hipLaunchKernelGGL(spectra_kernel<double2>, grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf, mpad,
-                       (double2*)spec);
-  else
-    hipLaunchKernelGGL(spectra_kernel<float2>, grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf, mpad,
-                       (float2*)spec);
+  const bool three = spectra_mchunk(nmbf) == 3;
+  if (precision == 0) {
+    if (three)
+      hipLaunchKernelGGL((spectra_kernel<double2, 3>), grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf,
+                         mpad, (double2*)spec);
+    else
+      hipLaunchKernelGGL((spectra_kernel<double2, 4>), grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf,
+                         mpad, (double2*)spec);
+  } else {
+    if (three)
+      hipLaunchKernelGGL((spectra_kernel<float2, 3>), grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf,
+                         mpad, (float2*)spec);
+    else
+      hipLaunchKernelGGL((spectra_kernel<float2, 4>), grid, dim3(kSpecThreads), 0, s, x, y, geo, utab, scratch, nmbf,
+                         mpad, (float2*)spec);
+  }
   return hipGetLastError();
 }
 
