@@ -152,8 +152,11 @@ def test_c1_full_grid_mixed():
     _full_case("c1 mixed", wl.grids[0], wl.substrates[0], wl.basis, wl.q, wl.pairs.tolist(), 1e-5)
 
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3, 5])
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 5, 7])
 def test_orders_nonsquare_fp64(order):
+    """Taylor orders 0 (no Taylor term: the plain FFT of the weighted
+    integrand) up to the largest the library accepts (7), on a non-square
+    grid, against the oracle's whole table."""
     rng = np.random.default_rng(100 + order)
     grid = Grid(64, 32, 9 * K0, 7 * K0, K0, order=order)
     basis = rooftop_lattice(3, 4)
