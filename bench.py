@@ -25,6 +25,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import platform
 import subprocess
 import sys
@@ -48,11 +49,18 @@ def _ensure_built():
         __graft_entry__.build()
 
 
+def _code_text(text):
+    """Source text without comments and blank lines (a comment edit leaves the kernels unchanged)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.strip() for line in text.splitlines() if line.strip())
+
+
 def _source_hash(files):
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_1404_7357_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1404_7357_amd", "csrc", f)) as fh:
+            h.update(_code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -55,8 +55,10 @@ template <typename Vc, int N> constexpr int row_min_waves() { return (sizeof(Vc)
 // occupancy target (elsewhere the rebuilt factors cost 3%).
 template <typename Vc, int N> constexpr bool row_opaque_t() { return sizeof(Vc) == 8 && N >= 1024; }
 
-// Points per thread of the row transforms (16 points per thread in the
-// FP64 rows of 4096 points take 256 registers and one wave per SIMD).
+// Points per thread of the row transforms.  In the FP64 rows of 4096 points,
+// 16 points per thread take 256 registers and one wave per SIMD, and 4 points
+// per thread (radix-4 stages, 1024 threads, four waves per SIMD) took 11%
+// longer than 8: two more LDS exchanges per transform.
 template <typename Vc, int N> __host__ __device__ constexpr int row_r() { return 8; }
 
 template <int N, int R> struct RowCfg {
