@@ -327,6 +327,119 @@ __device__ __forceinline__ void fft_forward(V (&x)[R], V* lds, const V* ltw, int
   }
 }
 
+// Two independent transforms of the same length through one sequence of
+// stages: a stage's twiddles are formed once for both, and the two exchanges
+// (each transform in its own LDS region, lx and lz) share one pair of
+// barriers.  Each transform sees exactly the operations of fft_forward, so
+// the results are the same bit for bit; what changes is that a wave has two
+// independent butterfly chains to issue from between its LDS waits.
+template <typename V, int N, int R, int RHO, bool LAST, bool WAVE, int PS>
+__device__ __forceinline__ void stockham_stage2(V (&x)[R], V (&z)[R], V* lx, V* lz, const V* ltw, int t, int L) {
+  constexpr int T = N / R;
+  constexpr int BPT = R / RHO;
+#pragma unroll
+  for (int mb = 0; mb < BPT; ++mb) {
+    const int i = t + T * mb;
+    const int k = i & (L - 1);
+    V y[RHO], u[RHO];
+#pragma unroll
+    for (int j = 0; j < RHO; ++j) {
+      y[j] = x[mb + j * BPT];
+      u[j] = z[mb + j * BPT];
+    }
+    if (L > 1) {
+      const int step = N / (L * RHO);
+      if constexpr (RHO == 8) {
+        // the powers w^j as in stockham_stage, formed once for both transforms
+        const int m = k * step;
+        V w1;
+        if constexpr (N / RHO <= 64) w1 = ltw[m];
+        else w1 = tw_at<V, N>(ltw, m);
+        const V w2 = cmul(w1, w1);
+        const V w4 = cmul(w2, w2);
+        const V w3 = cmul(w2, w1);
+        const V w5 = cmul(w4, w1);
+        const V w6 = cmul(w3, w3);
+        const V w7 = cmul(w4, w3);
+        y[1] = cmul(y[1], w1);
+        u[1] = cmul(u[1], w1);
+        y[2] = cmul(y[2], w2);
+        u[2] = cmul(u[2], w2);
+        y[5] = cmul(y[5], w5);
+        u[5] = cmul(u[5], w5);
+        y[4] = cmul(y[4], w4);
+        u[4] = cmul(u[4], w4);
+        y[3] = cmul(y[3], w3);
+        u[3] = cmul(u[3], w3);
+        y[6] = cmul(y[6], w6);
+        u[6] = cmul(u[6], w6);
+        y[7] = cmul(y[7], w7);
+        u[7] = cmul(u[7], w7);
+      } else {
+#pragma unroll
+        for (int j = 1; j < RHO; ++j) {
+          const V w = tw_at<V, N>(ltw, j * k * step);
+          y[j] = cmul(y[j], w);
+          u[j] = cmul(u[j], w);
+        }
+      }
+    }
+    dft_small<V, RHO>(y);
+    dft_small<V, RHO>(u);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int q = 0; q < RHO; ++q) {
+        x[mb + q * BPT] = y[q];
+        z[mb + q * BPT] = u[q];
+      }
+    } else {
+      const int base = (i - k) * RHO + k;
+#pragma unroll
+      for (int q = 0; q < RHO; ++q) {
+        lx[lds_slot<PS>(base + q * L)] = y[q];
+        lz[lds_slot<PS>(base + q * L)] = u[q];
+      }
+    }
+  }
+  if constexpr (!LAST) {
+    exchange_sync<WAVE>();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      x[r] = lx[lds_slot<PS>(t + T * r)];
+      z[r] = lz[lds_slot<PS>(t + T * r)];
+    }
+    exchange_sync<WAVE>();
+  }
+}
+
+// fft_forward of two independent inputs at once (see stockham_stage2).
+template <typename V, int N, int R, bool WAVE = false, int PS = 3>
+__device__ __forceinline__ void fft_forward2(V (&x)[R], V (&z)[R], V* lx, V* lz, const V* ltw, int t) {
+  static_assert(R == 8, "8 points per thread");
+  asm volatile("" : "+v"(t));
+  constexpr int LOG = ilog2c(N);
+  constexpr int NR8 = LOG / 3;
+  constexpr int REM = LOG % 3;
+  int L = 1;
+  if constexpr (REM == 1) {
+    stockham_stage2<V, N, R, 2, NR8 == 0, WAVE, PS>(x, z, lx, lz, ltw, t, L);
+    L *= 2;
+  } else if constexpr (REM == 2) {
+    stockham_stage2<V, N, R, 4, NR8 == 0, WAVE, PS>(x, z, lx, lz, ltw, t, L);
+    L *= 4;
+  }
+  if constexpr (NR8 >= 1) {
+    if constexpr (NR8 >= 2) {
+#pragma unroll
+      for (int s = 0; s < NR8 - 1; ++s) {
+        stockham_stage2<V, N, R, 8, false, WAVE, PS>(x, z, lx, lz, ltw, t, L);
+        L *= 8;
+      }
+    }
+    stockham_stage2<V, N, R, 8, true, WAVE, PS>(x, z, lx, lz, ltw, t, L);
+  }
+}
+
 // Inverse (unnormalised) DFT: conj(DFT(conj x)).
 template <typename V, int N, int R, bool WAVE = false, int PS = 3>
 __device__ __forceinline__ void fft_inverse(V (&x)[R], V* lds, const V* ltw, int t) {

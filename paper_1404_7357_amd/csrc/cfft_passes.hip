@@ -61,6 +61,14 @@ template <typename Vc, int N> constexpr bool row_opaque_t() { return sizeof(Vc) 
 // longer than 8: two more LDS exchanges per transform.
 template <typename Vc, int N> __host__ __device__ constexpr int row_r() { return 8; }
 
+// Whether the row pass runs its Taylor terms two at a time through one
+// sequence of transform stages (fft_forward2): in the FP64 transforms of
+// rows of 2048 points and more (one 512- or 256-thread block per row, two
+// waves per SIMD at about 200 registers, latency-bound), where the second
+// transform's registers still fit that occupancy and its LDS region fits
+// beside the first.
+template <typename Vc, int N> constexpr bool row_paired() { return sizeof(Vc) == 16 && N >= 2048; }
+
 template <int N, int R> struct RowCfg {
   static constexpr int T = N / R;
   static constexpr int ROWS = T >= 64 ? 1 : 64 / T;
@@ -191,7 +199,7 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
   using Cfg = RowCfg<N, R>;
   constexpr int T = Cfg::T, ROWS = Cfg::ROWS;
   using Rc = typename real_of<Vc>::type;
-  __shared__ Vc lds[ROWS * lds_len<row_pad<Vc>()>(N)];
+  __shared__ Vc lds[(row_paired<Vc, N>() ? 2 : 1) * ROWS * lds_len<row_pad<Vc>()>(N)];
   __shared__ Vc ltw[TwLds<N>::LEN];
   load_twiddles<Vc, N>(ltw, (const Vc*)a.tw, threadIdx.x, Cfg::THREADS);
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -223,24 +231,10 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
   double2 S[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
-  for (int ao = 0; ao <= a.order; ++ao) {
-    // opaque copy of t: the per-point factors and store addresses are
-    // rebuilt per term instead of being hoisted and held across the loop
-    int tb = t;
-    if constexpr (row_opaque_t<Vc, N>()) asm volatile("" : "+v"(tb));
-    if (ao > 0) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int n1 = tb + T * r;
-        f[r] = cscale(f[r], (Rc)(a.gamma * (a.kx0 + n1 * a.dkx)));
-      }
-    }
-    Vc x[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = f[r];
-    fft_forward<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, my_lds, ltw, t);
+  const int nsl = a.tensor ? 1 : a.order + 1;
+  // Fold the transform xx of term ao into S and store S_ao.
+  auto accumulate = [&](int ao, int tb, const Vc(&xx)[R]) {
     const bool keep = !a.tensor || ao == a.order;
-    const int nsl = a.tensor ? 1 : a.order + 1;
     Vs* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + (valid ? n2 : 0)) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -248,13 +242,48 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
       const double dx = a.x0 + (tb + T * r) * a.ddx;
       double cf = 1.0;
       for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
-      const double2 xv = to_d(x[r]);
+      const double2 xv = to_d(xx[r]);
       S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
       if (valid && keep) {
         if (a.stream_out) store_nt(dst + tb + T * r, from_d<Vs>(S[r]));
         else dst[tb + T * r] = from_d<Vs>(S[r]);
       }
     }
+  };
+  // f <- (gamma kx) f: the input of the next term
+  auto next_term = [&](int tb) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int n1 = tb + T * r;
+      f[r] = cscale(f[r], (Rc)(a.gamma * (a.kx0 + n1 * a.dkx)));
+    }
+  };
+  for (int ao = 0; ao <= a.order;) {
+    // opaque copy of t: the per-point factors and store addresses are
+    // rebuilt per term instead of being hoisted and held across the loop
+    int tb = t;
+    if constexpr (row_opaque_t<Vc, N>()) asm volatile("" : "+v"(tb));
+    if (ao > 0) next_term(tb);
+    Vc x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = f[r];
+    if constexpr (row_paired<Vc, N>()) {
+      if (ao < a.order) {
+        // terms ao and ao + 1 through one sequence of stages
+        next_term(tb);
+        Vc z[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[r] = f[r];
+        fft_forward2<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, z, my_lds, my_lds + lds_len<row_pad<Vc>()>(N), ltw, t);
+        accumulate(ao, tb, x);
+        accumulate(ao + 1, tb, z);
+        ao += 2;
+        continue;
+      }
+    }
+    fft_forward<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, my_lds, ltw, t);
+    accumulate(ao, tb, x);
+    ++ao;
   }
 }
 
