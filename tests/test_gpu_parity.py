@@ -203,6 +203,34 @@ def test_long_axes_sampled(nx, ny):
         assert err < tol, (nx, ny, prec, err)
 
 
+@pytest.mark.parametrize("nx,order,truncation", [(2048, 0, None), (2048, 2, None), (4096, 4, None),
+                                                  (4096, 3, "tensor"), (2048, 2, "tensor")])
+def test_long_rows_term_counts(nx, order, truncation):
+    """Rows of 2048 and 4096 points with FP64 transforms run their Taylor terms
+    two at a time; an odd number of terms (P = 0, 2, 4) leaves one term
+    alone, and the tensor truncation stores only the full sum.  FP64 and
+    mixed (FP64 transforms on FP32 data past the amplification limit, FP32
+    transforms below it), at sampled outputs against the oracle."""
+    ny = 16
+    rng = np.random.default_rng(7 * nx + 31 * order)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 2, basis.shape[0])
+    pairs = [(0, 1), (1, 1), (1, 0)]
+    idx = _sample_idx(nx, ny, 40, nx + order)
+    for prec, tol in [(FP64, FP64_TARGET), (MIXED, MIXED_TARGET)]:
+        grid = Grid(nx, ny, 8 * K0, 6 * K0, K0, order=order, precision=prec)
+        if truncation == "tensor":
+            grid = dataclasses.replace(grid, truncation=TRUNC_TENSOR)
+        sub = Substrate(3.0, 0.001, 0.07)
+        _say(f"long rows {nx}x{ny} P={order} {truncation or 'total'} prec={prec}")
+        _, _, z = _run(grid, sub, basis, q, pairs)
+        ref = co.tabulate(grid, sub, basis, q, np.asarray(pairs), out_idx=idx, workers=8)
+        zs = z.reshape(len(pairs), -1)[:, idx]
+        err = (np.abs(zs - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
+        _say(f"long rows {nx}x{ny} P={order} {truncation or 'total'} prec={prec} err={err:.3e}")
+        assert err < tol, (nx, order, truncation, prec, err)
+
+
 @pytest.mark.parametrize("nx,ny", [(4096, 16), (16, 4096)])
 def test_long_axes_low_order_mixed(nx, ny):
     """Order 1 on 4096-point axes: the Taylor amplification (about 50) stays
