@@ -631,6 +631,36 @@ def _cpu_cfft_paper_pair(workers):
             "paper_seconds_per_pair": 1.56, "paper_hardware": "one i7-3770"}
 
 
+def _cpu_cfft_headline_pair(workers):
+    """The passes of one pair of the headline workload on the CPU: eq. fftarry
+    literally, scipy FFT2 (10 transforms of 4096^2, complex128) on a synthetic
+    integrand of the same size, with every worker thread of the host; scaled
+    to the 36 pairs of the step as passes-only entries/s (the analogue of the
+    GPU's passes_only figure)."""
+    import numpy as np
+
+    from oracle import cfft_cpu
+    from oracle import cfft_oracle as co
+    from workloads import c4_large
+    wl = c4_large(precision=0)
+    grid = wl.grids[0]
+    rng = np.random.default_rng(6)
+    n = grid.nx * grid.ny
+    kx, ky = co.grid_samples(grid.nx, grid.ny, grid.kx_max, grid.ky_max)
+    w = np.full(n, (1 + 1j * grid.gamma) ** 2)
+    noise = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)   # noqa: E731
+    fac = (kx, ky, w, noise(3, n), noise(1, 2, n), noise(1, 2, n))
+    t0 = time.perf_counter()
+    cfft_cpu.tabulate_cfft(grid, wl.substrates[0], wl.basis, wl.q[:1], np.array([(0, 0)]), workers=workers,
+                           factors=fac)
+    sec = time.perf_counter() - t0
+    npairs = len(wl.pairs)
+    return {"seconds_per_pair": sec, "passes_entries_per_s": n / sec, "seconds_all_pairs": sec * npairs,
+            "cores": workers, "kind": "cpu-cfft",
+            "sample": f"one pair of the {grid.nx}^2 FP64 headline grid, 10 FFT2 + weighting, synthetic integrand; "
+                      f"x {npairs} pairs for the step (passes only: no Green's function or spectra)"}
+
+
 def _cpu_leg(out, checks, workers):
     """The host-CPU leg, run after every GPU leg: the oracle timed on bounded
     samples of the headline workload (cpu_baseline) and each GPU result's error
@@ -680,6 +710,8 @@ def _cpu_leg(out, checks, workers):
         out["adjoint"]["rel_err_vs_oracle"] = _table_err_real(checks["adjoint"], workers)
     _log("cpu C-FFT, one pair of the paper's 2048^2 setup")
     out["cpu_cfft_paper_pair"] = _cpu_cfft_paper_pair(workers)
+    _log("cpu C-FFT, one pair of the headline 4096^2 grid")
+    out["cpu_cfft_headline_pair"] = _cpu_cfft_headline_pair(workers)
 
 
 # --------------------------------------------------------------------------- main
