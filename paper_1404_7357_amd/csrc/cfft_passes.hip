@@ -69,6 +69,16 @@ template <typename Vc, int N> __host__ __device__ constexpr int row_r() { return
 // beside the first.
 template <typename Vc, int N> constexpr bool row_paired() { return sizeof(Vc) == 16 && N >= 2048; }
 
+// Whether the row pass keeps its blocks resident and loops over rows: FP64
+// rows of 4096 points (one block per CU, each row ~25 us), where a fresh
+// block per row costs about 4% in dispatch and start-up (4096^2 FP64:
+// 14.24 -> 13.68 ms).  The loop raises the kernel to 256 registers: at 2048
+// points that halves the resident blocks (the pass lost 27%), and with FP32
+// storage (a larger spill) it gained nothing.
+template <typename Vs, typename Vc, int N> constexpr bool row_persistent() {
+  return sizeof(Vs) == 16 && row_paired<Vc, N>() && N >= 4096;
+}
+
 template <int N, int R> struct RowCfg {
   static constexpr int T = N / R;
   static constexpr int ROWS = T >= 64 ? 1 : 64 / T;
@@ -202,7 +212,9 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
   __shared__ Vc lds[(row_paired<Vc, N>() ? 2 : 1) * ROWS * lds_len<row_pad<Vc>()>(N)];
   __shared__ Vc ltw[TwLds<N>::LEN];
   load_twiddles<Vc, N>(ltw, (const Vc*)a.tw, threadIdx.x, Cfg::THREADS);
-  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  __syncthreads();   // twiddle tables ready
+  // One row (ROWS rows) of one pair: logical block lid.
+  auto process = [&](const int lid) {
   const int pair = lid % a.npairs;
   const int rb = lid / a.npairs;
   const int grp = threadIdx.x / T;
@@ -220,7 +232,6 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
   if (a.band) row_inputs<true, Vs, Vc, N, R>(a, t, n2, valid, row0, m, n, plane, f);
   else row_inputs<false, Vs, Vc, N, R>(a, t, n2, valid, row0, m, n, plane, f);
   Vc* my_lds = lds + grp * lds_len<row_pad<Vc>()>(N);
-  __syncthreads();   // twiddle tables ready
   if (a.parabolic) {
     const size_t slot = (size_t)a.ny * N;
     row_terms_general<Vs, Vc, N, R, (T <= 64), row_pad<Vc>()>(
@@ -284,6 +295,17 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
     fft_forward<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, my_lds, ltw, t);
     accumulate(ao, tb, x);
     ++ao;
+  }
+  };
+  if constexpr (row_persistent<Vs, Vc, N>()) {
+    // persistent blocks (as many as fit the device at once) take the logical
+    // blocks vb = blockIdx.x + i gridDim.x in turn; gridDim.x is a multiple
+    // of 8, so every one stays on its block's XCD and the remap keeps its
+    // order
+    const int total = (((a.band ? a.ny / 2 : a.ny) + ROWS - 1) / ROWS) * a.npairs;
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) process(xcd_remap(vb, total));
+  } else {
+    process(xcd_remap(blockIdx.x, gridDim.x));
   }
 }
 
@@ -609,7 +631,24 @@ static hipError_t row_launch(const RowArgs& args, hipStream_t s) {
   using Cfg = RowCfg<N, R>;
   const int rows = args.band ? args.ny / 2 : args.ny;
   const int nblk = ((rows + Cfg::ROWS - 1) / Cfg::ROWS) * args.npairs;
-  hipLaunchKernelGGL((row_pass_kernel<Vs, Vc, N, R>), dim3(nblk), dim3(Cfg::THREADS), 0, s, args);
+  int grid = nblk;
+  if constexpr (row_persistent<Vs, Vc, N>()) {
+    // blocks resident at once on this device, in multiples of 8 (XCDs)
+    static thread_local int cached_dev = -1, cached_resident = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev != cached_dev) {
+      int per_cu = 0, cus = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, row_pass_kernel<Vs, Vc, N, R>, Cfg::THREADS, 0);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      cached_resident = std::max(8, per_cu * cus / 8 * 8);
+      cached_dev = dev;
+    }
+    grid = std::min(nblk, cached_resident);
+  }
+  hipLaunchKernelGGL((row_pass_kernel<Vs, Vc, N, R>), dim3(grid), dim3(Cfg::THREADS), 0, s, args);
   return hipGetLastError();
 }
 
