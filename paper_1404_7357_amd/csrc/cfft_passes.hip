@@ -215,87 +215,87 @@ __global__ void __launch_bounds__((RowCfg<N, R>::THREADS), (row_min_waves<Vc, N>
   __syncthreads();   // twiddle tables ready
   // One row (ROWS rows) of one pair: logical block lid.
   auto process = [&](const int lid) {
-  const int pair = lid % a.npairs;
-  const int rb = lid / a.npairs;
-  const int grp = threadIdx.x / T;
-  const int t = threadIdx.x % T;
-  // zero-padded grid: only the rows of the band are launched (the others
-  // are zero and the column pass does not read them)
-  const int row0 = a.band ? a.ny / 4 : 0;
-  const int n2 = row0 + rb * ROWS + grp;
-  const bool valid = n2 < a.ny - row0;
-  const size_t plane = (size_t)a.nx * a.ny;
-  const int m = a.pm[pair], n = a.pn[pair];
-  Vs* inter = (Vs*)a.inter;
+    const int pair = lid % a.npairs;
+    const int rb = lid / a.npairs;
+    const int grp = threadIdx.x / T;
+    const int t = threadIdx.x % T;
+    // zero-padded grid: only the rows of the band are launched (the others
+    // are zero and the column pass does not read them)
+    const int row0 = a.band ? a.ny / 4 : 0;
+    const int n2 = row0 + rb * ROWS + grp;
+    const bool valid = n2 < a.ny - row0;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const int m = a.pm[pair], n = a.pn[pair];
+    Vs* inter = (Vs*)a.inter;
 
-  Vc f[R];
-  if (a.band) row_inputs<true, Vs, Vc, N, R>(a, t, n2, valid, row0, m, n, plane, f);
-  else row_inputs<false, Vs, Vc, N, R>(a, t, n2, valid, row0, m, n, plane, f);
-  Vc* my_lds = lds + grp * lds_len<row_pad<Vc>()>(N);
-  if (a.parabolic) {
-    const size_t slot = (size_t)a.ny * N;
-    row_terms_general<Vs, Vc, N, R, (T <= 64), row_pad<Vc>()>(
-        a, f, my_lds, ltw, t, valid ? n2 : 0, inter + ((size_t)pair * (a.order + 1) * a.ny + (valid ? n2 : 0)) * N,
-        slot, valid);
-    return;
-  }
-  double2 S[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
-  const int nsl = a.tensor ? 1 : a.order + 1;
-  // Fold the transform xx of term ao into S and store S_ao.
-  auto accumulate = [&](int ao, int tb, const Vc(&xx)[R]) {
-    const bool keep = !a.tensor || ao == a.order;
-    Vs* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + (valid ? n2 : 0)) * N;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      // Dx(j1)^a / a!, rebuilt per term (cheaper than keeping it live)
-      const double dx = a.x0 + (tb + T * r) * a.ddx;
-      double cf = 1.0;
-      for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
-      const double2 xv = to_d(xx[r]);
-      S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
-      if (valid && keep) {
-        if (a.stream_out) store_nt(dst + tb + T * r, from_d<Vs>(S[r]));
-        else dst[tb + T * r] = from_d<Vs>(S[r]);
+    Vc f[R];
+    if (a.band) row_inputs<true, Vs, Vc, N, R>(a, t, n2, valid, row0, m, n, plane, f);
+    else row_inputs<false, Vs, Vc, N, R>(a, t, n2, valid, row0, m, n, plane, f);
+    Vc* my_lds = lds + grp * lds_len<row_pad<Vc>()>(N);
+    if (a.parabolic) {
+      const size_t slot = (size_t)a.ny * N;
+      row_terms_general<Vs, Vc, N, R, (T <= 64), row_pad<Vc>()>(
+          a, f, my_lds, ltw, t, valid ? n2 : 0, inter + ((size_t)pair * (a.order + 1) * a.ny + (valid ? n2 : 0)) * N,
+          slot, valid);
+      return;
+    }
+    double2 S[R];
+  #pragma unroll
+    for (int r = 0; r < R; ++r) S[r] = make_double2(0.0, 0.0);
+    const int nsl = a.tensor ? 1 : a.order + 1;
+    // Fold the transform xx of term ao into S and store S_ao.
+    auto accumulate = [&](int ao, int tb, const Vc(&xx)[R]) {
+      const bool keep = !a.tensor || ao == a.order;
+      Vs* dst = inter + (((size_t)pair * nsl + (a.tensor ? 0 : ao)) * a.ny + (valid ? n2 : 0)) * N;
+  #pragma unroll
+      for (int r = 0; r < R; ++r) {
+        // Dx(j1)^a / a!, rebuilt per term (cheaper than keeping it live)
+        const double dx = a.x0 + (tb + T * r) * a.ddx;
+        double cf = 1.0;
+        for (int i = 1; i <= ao; ++i) cf *= dx * a.rinv[i];
+        const double2 xv = to_d(xx[r]);
+        S[r] = make_double2(S[r].x + cf * xv.x, S[r].y + cf * xv.y);
+        if (valid && keep) {
+          if (a.stream_out) store_nt(dst + tb + T * r, from_d<Vs>(S[r]));
+          else dst[tb + T * r] = from_d<Vs>(S[r]);
+        }
       }
-    }
-  };
-  // f <- (gamma kx) f: the input of the next term
-  auto next_term = [&](int tb) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int n1 = tb + T * r;
-      f[r] = cscale(f[r], (Rc)(a.gamma * (a.kx0 + n1 * a.dkx)));
-    }
-  };
-  for (int ao = 0; ao <= a.order;) {
-    // opaque copy of t: the per-point factors and store addresses are
-    // rebuilt per term instead of being hoisted and held across the loop
-    int tb = t;
-    if constexpr (row_opaque_t<Vc, N>()) asm volatile("" : "+v"(tb));
-    if (ao > 0) next_term(tb);
-    Vc x[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = f[r];
-    if constexpr (row_paired<Vc, N>()) {
-      if (ao < a.order) {
-        // terms ao and ao + 1 through one sequence of stages
-        next_term(tb);
-        Vc z[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) z[r] = f[r];
-        fft_forward2<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, z, my_lds, my_lds + lds_len<row_pad<Vc>()>(N), ltw, t);
-        accumulate(ao, tb, x);
-        accumulate(ao + 1, tb, z);
-        ao += 2;
-        continue;
+    };
+    // f <- (gamma kx) f: the input of the next term
+    auto next_term = [&](int tb) {
+  #pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int n1 = tb + T * r;
+        f[r] = cscale(f[r], (Rc)(a.gamma * (a.kx0 + n1 * a.dkx)));
       }
+    };
+    for (int ao = 0; ao <= a.order;) {
+      // opaque copy of t: the per-point factors and store addresses are
+      // rebuilt per term instead of being hoisted and held across the loop
+      int tb = t;
+      if constexpr (row_opaque_t<Vc, N>()) asm volatile("" : "+v"(tb));
+      if (ao > 0) next_term(tb);
+      Vc x[R];
+  #pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = f[r];
+      if constexpr (row_paired<Vc, N>()) {
+        if (ao < a.order) {
+          // terms ao and ao + 1 through one sequence of stages
+          next_term(tb);
+          Vc z[R];
+  #pragma unroll
+          for (int r = 0; r < R; ++r) z[r] = f[r];
+          fft_forward2<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, z, my_lds, my_lds + lds_len<row_pad<Vc>()>(N), ltw, t);
+          accumulate(ao, tb, x);
+          accumulate(ao + 1, tb, z);
+          ao += 2;
+          continue;
+        }
+      }
+      fft_forward<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, my_lds, ltw, t);
+      accumulate(ao, tb, x);
+      ++ao;
     }
-    fft_forward<Vc, N, R, (T <= 64), row_pad<Vc>()>(x, my_lds, ltw, t);
-    accumulate(ao, tb, x);
-    ++ao;
-  }
   };
   if constexpr (row_persistent<Vs, Vc, N>()) {
     // persistent blocks (as many as fit the device at once) take the logical
