@@ -89,8 +89,9 @@ enum { CFFT_ROOFTOP_X = 0, CFFT_ROOFTOP_Y = 1, CFFT_COSINE_X = 2, CFFT_COSINE_Y 
  *   (makes the call synchronous).
  * AUTOTUNE: the first cfft_tabulate per (grid, npairs) times the candidate
  *   schedules (synchronously): pairs per launch, one or two plan-owned lanes
- *   taking alternate chunks, default or half-width column tiles; the plan
- *   keeps the fastest.  That first call runs the passes several times on the
+ *   taking alternate chunks, and the column tile (the default, half its
+ *   width, or for columns of 1024 points and more the other number of points
+ *   per thread, 8 or 16, with its widest tile); the plan keeps the fastest.  That first call runs the passes several times on the
  *   caller's buffers (z ends with the same table).
  * ZERO_PAD2: every grid of the plan is the x2 zero-padded extension of the
  *   grid the caller samples (Sec. III-B.3, last paragraph: Whittaker-Shannon

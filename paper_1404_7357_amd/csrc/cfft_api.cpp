@@ -248,7 +248,7 @@ struct cfft_plan_s {
   struct Schedule {
     long long chunk;   // pairs per row/column launch
     int lanes;         // 1, or 2 plan-owned streams taking alternate chunks
-    int narrow;        // column tiles of half the default width
+    int tile;          // kColTile*: column tile of the column pass
   };
   std::map<long long, Schedule> tuned;   // (grid, npairs) -> the autotuner's choice
   hipStream_t lane[2] = {nullptr, nullptr};
@@ -351,7 +351,7 @@ PassParams pass_params(const GridState& gs) {
   p.band = gs.band;
   p.precision = gs.d.precision;
   p.hi_compute = gs.d.precision == CFFT_MIXED && taylor_amplification(gs.d) > kFp32MaxAmplification ? 1 : 0;
-  p.col_narrow = 0;
+  p.col_tile = kColTileDefault;
   p.stream_out = 0;
   return p;
 }
@@ -808,8 +808,8 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   // row pass (the second lane starts once the first row pass is done).  The
   // lanes fork from and join back into the caller's stream through events,
   // which keeps the call capturable in a HIP graph.
-  auto run_passes = [&](long long ck, int lanes, int narrow) -> hipError_t {
-    pp.col_narrow = narrow;
+  auto run_passes = [&](long long ck, int lanes, int tile) -> hipError_t {
+    pp.col_tile = tile;
     pp.stream_out = stream_out(per_pair * (size_t)ck * (size_t)lanes);
     hipStream_t ls[2] = {s, s};
     if (lanes == 2) {
@@ -857,14 +857,18 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   int lanes = 1;
   const long long forced_lanes = env_ll("CFFT_LANES", 0);
   if (forced_lanes == 1 || forced_lanes == 2) lanes = (int)forced_lanes;
-  int narrow = env_ll("CFFT_COL_NARROW", 0) == 1 ? 1 : 0;
+  int tile = kColTileDefault;
+  const long long forced_tile = env_ll("CFFT_COL_TILE", -1);
+  if (forced_tile == kColTileHalf || (forced_tile == kColTileAltR && pp.y.n >= 1024)) tile = (int)forced_tile;
   auto lanes_ok = [&](long long ck) { return (npairs + ck - 1) / ck >= 2; };
   // With CFFT_FLAG_AUTOTUNE the first call per (grid, npairs) times every
-  // (pair chunk, lanes, column tile width) candidate (synchronously) and the
-  // plan keeps the fastest.  Smaller chunks keep a chunk's intermediates
-  // resident in the memory-side cache between the two passes; narrower
-  // column tiles trade row-piece length for more, smaller blocks.
-  if ((plan->flags & CFFT_FLAG_AUTOTUNE) && forced <= 0 && forced_lanes <= 0) {
+  // (pair chunk, lanes, column tile) candidate (synchronously) and the plan
+  // keeps the fastest.  Smaller chunks keep a chunk's intermediates resident
+  // in the memory-side cache between the two passes; narrower column tiles
+  // trade row-piece length for more, smaller blocks; the other number of
+  // points per thread trades threads per transform for work per thread and
+  // changes the widest tile that fits the LDS.
+  if ((plan->flags & CFFT_FLAG_AUTOTUNE) && forced <= 0 && forced_lanes <= 0 && forced_tile < 0) {
     const long long key = (long long)grid * 1000003LL + npairs;
     auto it = plan->tuned.find(key);
     if (it == plan->tuned.end()) {
@@ -883,9 +887,10 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
             }
             if (st != CFFT_OK) return st;
           }
-          for (int w : {0, 1}) {
+          for (int w : {kColTileDefault, kColTileHalf, kColTileAltR}) {
+            if (w == kColTileAltR && pp.y.n < 1024) continue;
             bool dup = false;
-            for (const auto& x : cands) dup = dup || (x.chunk == c && x.lanes == l && x.narrow == w);
+            for (const auto& x : cands) dup = dup || (x.chunk == c && x.lanes == l && x.tile == w);
             if (!dup) cands.push_back({c, l, w});
           }
         }
@@ -894,14 +899,14 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
       hipError_t e = hipEventCreate(&ea);
       if (e == hipSuccess) e = hipEventCreate(&eb);
       if (e != hipSuccess) return hip_fail(e, "autotune events");
-      cfft_plan_s::Schedule best{chunk, 1, 0};
+      cfft_plan_s::Schedule best{chunk, 1, kColTileDefault};
       float best_ms = 3.4e38f;
       for (const auto& c : cands) {
-        e = run_passes(c.chunk, c.lanes, c.narrow);  // warm-up
+        e = run_passes(c.chunk, c.lanes, c.tile);  // warm-up
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventRecord(ea, s);
-        if (e == hipSuccess) e = run_passes(c.chunk, c.lanes, c.narrow);
-        if (e == hipSuccess) e = run_passes(c.chunk, c.lanes, c.narrow);
+        if (e == hipSuccess) e = run_passes(c.chunk, c.lanes, c.tile);
+        if (e == hipSuccess) e = run_passes(c.chunk, c.lanes, c.tile);
         if (e == hipSuccess) e = hipEventRecord(eb, s);
         if (e == hipSuccess) e = hipEventSynchronize(eb);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
@@ -918,7 +923,7 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
     }
     chunk = it->second.chunk;
     lanes = it->second.lanes;
-    narrow = it->second.narrow;
+    tile = it->second.tile;
   }
   if (lanes == 2 && !lanes_ok(chunk)) lanes = 1;
   if (lanes == 2) {
@@ -926,7 +931,7 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
     if (st != CFFT_OK) return st;
   }
   {
-    hipError_t e = run_passes(chunk, lanes, narrow);
+    hipError_t e = run_passes(chunk, lanes, tile);
     if (e != hipSuccess) return hip_fail(e, "pass launch");
   }
   return check_finite(plan, z, 2 * n * (size_t)npairs, pp.precision != CFFT_FP64, s);

@@ -64,6 +64,12 @@ struct GeomDevice {
   int* index;         // [total_idx]
 };
 
+// Column tiles of the column pass: the default shape, tiles of half its
+// width, or (columns of 1024 points and more) the other number of points per
+// thread, 8 or 16, with its own widest tile.  The two alternatives are the
+// autotuner's candidates beside the default.
+enum { kColTileDefault = 0, kColTileHalf = 1, kColTileAltR = 2 };
+
 struct PassParams {
   Axis x, y;
   double gamma;
@@ -74,7 +80,7 @@ struct PassParams {
   int parabolic;      // 1: parabolic contour (per-sample ratio; N_t row transforms)
   double beta_end;
   int band;           // 1: x2 zero-padded grid, integrand only on n in [N/4, 3N/4) per axis
-  int col_narrow;     // 1: column tiles of half the default width
+  int col_tile;       // kColTile*: column tile of the column pass
   int stream_out;     // 1: the row pass writes the intermediates with non-temporal
                       // stores (a launch's intermediates too large to stay in the
                       // memory-side cache until the column pass reads them)

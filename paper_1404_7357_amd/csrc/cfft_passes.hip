@@ -482,7 +482,7 @@ struct ColArgs {
   int tensor;   // every term reads slot 0 (the full row sum S_P)
   int parabolic;   // term b reads slot b and carries no (gamma ky)^b factor
   int band;     // x2 zero-padded grid: rows outside [N/4, 3N/4) are zero and not read
-  int narrow;   // tiles of half the default width (an autotuner candidate)
+  int tile;     // kColTile*: the default tile or one of the autotuner's alternatives
   const void* inter;   // Vs elements
   void* z;             // Vs elements
   const void* tw;      // Vc elements
@@ -496,8 +496,9 @@ struct ColArgs {
 // each column transform.  The widest C that keeps a block within 64-byte row
 // pieces, its LDS budget (80 KiB: two blocks per CU; 152 KiB with more than
 // 8 points per thread: one block) and 512 threads (1024 for FP32 transforms
-// of 2048 points and more).
-template <typename Vs, typename Vc, int N> struct ColShape {
+// of 2048 points and more).  RF != 0 imposes R (the autotuner's alternative
+// number of points per thread).
+template <typename Vs, typename Vc, int N, int RF = 0> struct ColShape {
   static constexpr int lds_per_col() { return (lds_len(N) + 4) * (int)sizeof(Vc); }
   // FP64 transforms of 4096 points: two-column tiles of 8 points per thread
   // (1024 threads, one block per CU).  Measured on the 4096^2 table against
@@ -506,9 +507,13 @@ template <typename Vs, typename Vc, int N> struct ColShape {
   // was the fastest in both storage precisions (one-column tiles move 16-byte
   // row pieces; 16 points per thread leave one wave per SIMD).
   static constexpr bool wide4096 = sizeof(Vc) == 16 && N >= 4096;
-  static constexpr int R = wide4096 ? 8 : (sizeof(Vc) == 8 && N >= 4096) ? 16 : 8;
+  static constexpr int R_DEFAULT = wide4096 ? 8 : (sizeof(Vc) == 8 && N >= 4096) ? 16 : 8;
+  static constexpr int R = RF ? RF : R_DEFAULT;
+  // the other number of points per thread, offered for columns of 1024
+  // points and more
+  static constexpr int R_ALT = R_DEFAULT == 8 ? 16 : 8;
   static constexpr int pick_c() {
-    if (wide4096) return 2;
+    if (wide4096 && R == 8) return 2;
     int c = 64 / (int)sizeof(Vs);
     const int max_threads = (sizeof(Vc) == 8 && N >= 2048 && R == 8) ? 1024 : 512;
     const int cap = R > 8 ? 155648 : 81920;
@@ -652,25 +657,29 @@ static hipError_t row_launch(const RowArgs& args, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename Vs, typename Vc, int N, int C, int R>
+static hipError_t col_launch_tile(const ColArgs& args, hipStream_t s) {
+  if (args.nx % C != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((col_pass_kernel<Vs, Vc, N, C, R>), dim3((args.nx / C) * args.npairs),
+                     dim3(ColCfg<N, C, R>::THREADS), 0, s, args);
+  return hipGetLastError();
+}
+
 template <typename Vs, typename Vc, int N>
 static hipError_t col_launch(const ColArgs& args, hipStream_t s) {
   using Sh = ColShape<Vs, Vc, N>;
   constexpr int C0 = Sh::C, R = Sh::R;
-  // the autotuner's alternative: tiles of half the width (more, smaller
-  // blocks; shorter row pieces)
+  // the autotuner's alternatives: tiles of half the width (more, smaller
+  // blocks; shorter row pieces), or, for columns of 1024 points and more,
+  // the other number of points per thread with its own widest tile
   if constexpr (C0 > 1) {
-    if (args.narrow) {
-      constexpr int C = C0 / 2;
-      if (args.nx % C != 0) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((col_pass_kernel<Vs, Vc, N, C, R>), dim3((args.nx / C) * args.npairs),
-                         dim3(ColCfg<N, C, R>::THREADS), 0, s, args);
-      return hipGetLastError();
-    }
+    if (args.tile == kColTileHalf) return col_launch_tile<Vs, Vc, N, C0 / 2, R>(args, s);
   }
-  if (args.nx % C0 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((col_pass_kernel<Vs, Vc, N, C0, R>), dim3((args.nx / C0) * args.npairs),
-                     dim3(ColCfg<N, C0, R>::THREADS), 0, s, args);
-  return hipGetLastError();
+  if constexpr (N >= 1024) {
+    using Alt = ColShape<Vs, Vc, N, Sh::R_ALT>;
+    if (args.tile == kColTileAltR) return col_launch_tile<Vs, Vc, N, Alt::C, Alt::R>(args, s);
+  }
+  return col_launch_tile<Vs, Vc, N, C0, R>(args, s);
 }
 
 #define CFFT_SIZE_SWITCH(n, F, ...)      \
@@ -826,7 +835,7 @@ hipError_t launch_col_pass(const PassParams& p, const void* inter, int npairs, v
   a.tensor = p.tensor;
   a.parabolic = p.parabolic;
   a.band = p.band;
-  a.narrow = p.col_narrow;
+  a.tile = p.col_tile;
   a.npairs = npairs;
   a.ky0 = p.y.k_first;
   a.dky = p.y.dk;

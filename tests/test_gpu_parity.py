@@ -361,15 +361,12 @@ def test_many_pairs_chunked(monkeypatch):
     _full_case("32x32 11 pairs chunk 3", grid, Substrate(4.4, 0.002, 0.06), basis, q, pairs, 1e-10)
 
 
-@pytest.mark.parametrize("nx,ny,variant", [(64, 32, "ray"), (128, 512, "ray"), (32, 64, "parabolic"),
-                                            (256, 128, "tensor"), (128, 64, "band"), (16, 2048, "ray"),
-                                            (16, 4096, "ray"), (64, 2048, "tensor"), (64, 4096, "ray")])
-def test_narrow_column_tiles(monkeypatch, nx, ny, variant):
-    """The autotuner's alternative column tiles (half the default width),
-    forced, against the oracle: FP64 and mixed, ray and parabolic contours,
-    tensor truncation, zero-padded grid, 2048- and 4096-point columns."""
+def _forced_tile_case(monkeypatch, tile, nx, ny, variant):
+    """One schedule's column tile forced through CFFT_COL_TILE, FP64 and
+    mixed, against the oracle (whole table, or sampled outputs on the larger
+    grids)."""
     from paper_1404_7357_amd import FLAG_ZERO_PAD2
-    monkeypatch.setenv("CFFT_COL_NARROW", "1")
+    monkeypatch.setenv("CFFT_COL_TILE", str(tile))
     rng = np.random.default_rng(97 + nx + ny)
     basis = rooftop_lattice(2, 3)
     q = gaussian_coefficients(rng, 2, basis.shape[0])
@@ -386,7 +383,9 @@ def test_narrow_column_tiles(monkeypatch, nx, ny, variant):
         elif variant == "band":
             grid = dataclasses.replace(grid, kx_max=16 * K0, ky_max=12 * K0, zero_pad=1)
             flags = FLAG_ZERO_PAD2
-        _say(f"narrow column tiles {variant} {nx}x{ny} prec={prec}")
+        elif variant == "order1":
+            grid = dataclasses.replace(grid, order=1)
+        _say(f"column tile {tile} {variant} {nx}x{ny} prec={prec}")
         tab = _tab(grid, basis, 2, flags)
         qd = torch.tensor(q, device="cuda")
         z = tab.tabulate(tab.spectra(qd), tab.green(sub.eps_r, sub.tan_delta, sub.h), pairs).cpu().numpy()
@@ -394,32 +393,59 @@ def test_narrow_column_tiles(monkeypatch, nx, ny, variant):
         ref = co.tabulate(grid, sub, basis, q, np.asarray(pairs), out_idx=idx, workers=8).reshape(len(pairs), -1)
         got = z.reshape(len(pairs), -1) if idx is None else z.reshape(len(pairs), -1)[:, idx]
         err = (np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
-        assert err < tol, (variant, nx, ny, prec, err)
+        assert err < tol, (tile, variant, nx, ny, prec, err)
+
+
+@pytest.mark.parametrize("nx,ny,variant", [(64, 32, "ray"), (128, 512, "ray"), (32, 64, "parabolic"),
+                                            (256, 128, "tensor"), (128, 64, "band"), (16, 2048, "ray"),
+                                            (16, 4096, "ray"), (64, 2048, "tensor"), (64, 4096, "ray")])
+def test_narrow_column_tiles(monkeypatch, nx, ny, variant):
+    """The autotuner's column tiles of half the default width, forced:
+    ray and parabolic contours, tensor truncation, zero-padded grid, 2048-
+    and 4096-point columns."""
+    _forced_tile_case(monkeypatch, 1, nx, ny, variant)
+
+
+@pytest.mark.parametrize("nx,ny,variant", [(32, 1024, "ray"), (64, 1024, "band"), (16, 2048, "ray"),
+                                            (64, 2048, "tensor"), (32, 2048, "parabolic"), (16, 4096, "ray"),
+                                            (64, 4096, "ray"), (32, 4096, "band"), (16, 4096, "order1")])
+def test_other_points_per_thread_column_tiles(monkeypatch, nx, ny, variant):
+    """The autotuner's column tiles with the other number of points per
+    thread (16 where the default is 8, 8 where it is 16), forced, on columns
+    of 1024, 2048 and 4096 points: ray and parabolic contours, tensor
+    truncation, zero-padded grids, and order 1 (FP32 transforms of 4096
+    points in the mixed path)."""
+    _forced_tile_case(monkeypatch, 2, nx, ny, variant)
 
 
 def test_autotuned_schedules_match_oracle():
     """CFFT_FLAG_AUTOTUNE: the first call times every (pair chunk, lanes,
     column tile) candidate on the caller's buffers; the tables of that call
     and of the following calls (the chosen schedule) match the oracle, FP64
-    and mixed, for two pair counts of one plan."""
+    and mixed, for two pair counts of one plan.  The 32 x 1024 grid adds the
+    tiles with the other number of points per thread to the candidates
+    (sampled outputs there)."""
     from paper_1404_7357_amd import FLAG_AUTOTUNE
     rng = np.random.default_rng(101)
     basis = rooftop_lattice(2, 3)
     q = gaussian_coefficients(rng, 3, basis.shape[0])
     sub = Substrate(4.4, 0.002, 0.06)
-    for prec, tol in [(FP64, 1e-10), (MIXED, 1e-5)]:
-        grid = Grid(128, 64, 8 * K0, 6 * K0, K0, precision=prec)
-        tab = _tab(grid, basis, 3, FLAG_AUTOTUNE)
-        qd = torch.tensor(q, device="cuda")
-        g = tab.green(sub.eps_r, sub.tan_delta, sub.h)
-        spec = tab.spectra(qd)
-        for pairs in ([(m, n) for m in range(3) for n in range(3)], [(2, 0), (0, 2), (1, 1)]):
-            _say(f"autotuned 128x64 {len(pairs)} pairs prec={prec}")
-            ref = co.tabulate(grid, sub, basis, q, np.asarray(pairs))
-            for _ in range(2):
-                z = tab.tabulate(spec, g, pairs).cpu().numpy()
-                assert _err(z, ref) < tol
-        tab.close()
+    for nx, ny in [(128, 64), (32, 1024)]:
+        idx = None if ny < 1024 else _sample_idx(nx, ny, 48, 103)
+        for prec, tol in [(FP64, 1e-10), (MIXED, 1e-5)]:
+            grid = Grid(nx, ny, 8 * K0, 6 * K0, K0, precision=prec)
+            tab = _tab(grid, basis, 3, FLAG_AUTOTUNE)
+            qd = torch.tensor(q, device="cuda")
+            g = tab.green(sub.eps_r, sub.tan_delta, sub.h)
+            spec = tab.spectra(qd)
+            for pairs in ([(m, n) for m in range(3) for n in range(3)], [(2, 0), (0, 2), (1, 1)]):
+                _say(f"autotuned {nx}x{ny} {len(pairs)} pairs prec={prec}")
+                ref = co.tabulate(grid, sub, basis, q, np.asarray(pairs), out_idx=idx, workers=8)
+                ref = ref.reshape(len(pairs), -1)
+                for _ in range(2):
+                    z = tab.tabulate(spec, g, pairs).cpu().numpy().reshape(len(pairs), -1)
+                    assert _err(z if idx is None else z[:, idx], ref) < tol
+            tab.close()
 
 
 def _sample_idx(nx, ny, count, seed):
