@@ -47,6 +47,15 @@
  * when the plan was made without CFFT_FLAG_CHECK_FINITE.  A plan is not
  * thread-safe: issue its calls from one host thread at a time.
  *
+ * Environment (read at each call).  CFFT_WORKSPACE_MB caps the pass
+ * workspace of a plan (MiB, default 65536; the pairs then go in smaller
+ * chunks).  CFFT_PAIR_CHUNK (pairs per launch), CFFT_LANES (1 or 2) and
+ * CFFT_COL_TILE (0 default, 1 half width, 2 the other points per thread on
+ * columns of 1024 points and more) force one schedule of cfft_tabulate and
+ * switch CFFT_FLAG_AUTOTUNE off; values outside these ranges are ignored.
+ * CFFT_TEST_FAIL_ALLOC (non-empty, not "0") makes every device allocation
+ * of the library fail with CFFT_ERR_ALLOC, to test that path.
+ *
  * Errors.  Every call returns a status.  Arguments are validated on the host
  * before anything is launched; on error nothing is enqueued and
  * cfft_last_error() returns a message (thread-local).  No exception or abort

@@ -854,12 +854,16 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
     }
     return hipSuccess;
   };
+  // schedules forced from the environment (values outside the ranges are ignored)
   int lanes = 1;
-  const long long forced_lanes = env_ll("CFFT_LANES", 0);
-  if (forced_lanes == 1 || forced_lanes == 2) lanes = (int)forced_lanes;
+  const long long env_lanes = env_ll("CFFT_LANES", 0);
+  const bool forced_lanes = env_lanes == 1 || env_lanes == 2;
+  if (forced_lanes) lanes = (int)env_lanes;
   int tile = kColTileDefault;
-  const long long forced_tile = env_ll("CFFT_COL_TILE", -1);
-  if (forced_tile == kColTileHalf || (forced_tile == kColTileAltR && pp.y.n >= 1024)) tile = (int)forced_tile;
+  const long long env_tile = env_ll("CFFT_COL_TILE", -1);
+  const bool forced_tile = env_tile == kColTileDefault || env_tile == kColTileHalf ||
+                           (env_tile == kColTileAltR && pp.y.n >= 1024);
+  if (forced_tile) tile = (int)env_tile;
   auto lanes_ok = [&](long long ck) { return (npairs + ck - 1) / ck >= 2; };
   // With CFFT_FLAG_AUTOTUNE the first call per (grid, npairs) times every
   // (pair chunk, lanes, column tile) candidate (synchronously) and the plan
@@ -868,7 +872,7 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
   // trade row-piece length for more, smaller blocks; the other number of
   // points per thread trades threads per transform for work per thread and
   // changes the widest tile that fits the LDS.
-  if ((plan->flags & CFFT_FLAG_AUTOTUNE) && forced <= 0 && forced_lanes <= 0 && forced_tile < 0) {
+  if ((plan->flags & CFFT_FLAG_AUTOTUNE) && forced <= 0 && !forced_lanes && !forced_tile) {
     const long long key = (long long)grid * 1000003LL + npairs;
     auto it = plan->tuned.find(key);
     if (it == plan->tuned.end()) {
