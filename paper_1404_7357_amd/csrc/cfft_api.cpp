@@ -138,7 +138,7 @@ bool build_geometry(const cfft_basis_t* basis, int nb, GeomHost& out) {
       out.total_r += g.nr;
       out.total_idx += g.np * g.nr;
       out.groups.push_back(g);
-      if ((int)out.groups.size() > 32) return false;
+      if ((int)out.groups.size() > kMaxGroups) return false;
     }
     pending.swap(overflow);
   }
@@ -399,7 +399,7 @@ cfft_status_t ensure_geometry(cfft_plan_s* plan, GridState& gs, const cfft_basis
   if (!(plan->geo_mem && plan->geo_hash == h && plan->geo_nbasis == nbasis)) {
     GeomHost gh;
     if (!build_geometry(basis, nbasis, gh))
-      return fail(CFFT_ERR_UNSUPPORTED, "basis set needs more than 32 shape groups");
+      return fail(CFFT_ERR_UNSUPPORTED, "basis set needs more than %d shape groups", kMaxGroups);
     GeomDevice probe{};
     probe.ngroups = (int)gh.groups.size();
     probe.total_r = gh.total_r;
@@ -1200,7 +1200,7 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, 9, s);
-    e = launch_adj_spectra(gs.x, gs.y, gs.d.gamma, plan->geo_dev, gs.utab, gspec, nmbf, rowacc, (double2*)grad_q, s);
+    e = launch_adj_spectra(gs.x, gs.y, plan->geo_dev, gs.utab, gspec, nmbf, rowacc, (double2*)grad_q, s);
   }
   if (e != hipSuccess) return hip_fail(e, "adjoint reduction launch");
   return CFFT_OK;

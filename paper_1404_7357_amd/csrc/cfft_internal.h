@@ -10,6 +10,7 @@ namespace cfft {
 constexpr int kMaxPairsPerLaunch = 64;
 constexpr int kMaxOrder = 7;
 constexpr int kSpecPChunk = 4;   // spectra kernel: centres per unrolled chunk
+constexpr int kMaxGroups = 32;   // basis shape groups (kind, a, b) a geometry may hold
 
 // Sampling of one axis: k(n) = k0 + n dk, D(j) = d0 + j dd.
 struct Axis {
@@ -147,7 +148,7 @@ hipError_t launch_adj_integrand(const PassParams& p, const double2* gi, const do
 hipError_t launch_adj_green(const GreenParams& p, const double2* gg, double* partial, int nblocks,
                             hipStream_t s);
 hipError_t launch_reduce_sum(const double* partial, int n, int count, double* out, hipStream_t s);
-hipError_t launch_adj_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
+hipError_t launch_adj_spectra(const Axis& x, const Axis& y, const GeomDevice& geo,
                               const double2* utab, const double2* gspec, int nmbf, double2* rowacc,
                               double2* gq, hipStream_t s);
 

@@ -121,7 +121,6 @@ hipError_t launch_spectra_tables(const Axis& x, const Axis& y, double gamma, con
 
 constexpr int kSpecThreads = 256;   // spectra kernel block size
 constexpr int kSpecRows = 2;         // rows per spectra block
-constexpr int kMaxGroups = 32;  // host refuses basis sets needing more
 constexpr int kMChunk = 4;   // MBFs per pass of the parabolic (direct) kernel
 
 // MBFs per pass of the separable per-sample kernel: 3 or 4, whichever pads
@@ -476,7 +475,7 @@ constexpr int kAdjThreads = 256;
 constexpr int kAdjSplit = 64;
 
 __global__ void __launch_bounds__(kAdjThreads)
-adj_spectra_rows_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const double2* __restrict__ utab,
+adj_spectra_rows_kernel(Axis x, Axis y, GeomDevice geo, const double2* __restrict__ utab,
                         const double2* __restrict__ gspec, int nmbf, double2* __restrict__ rowacc) {
   extern __shared__ double2 sh[];
   // a1, a2: [nmbf][total_p]
@@ -484,9 +483,7 @@ adj_spectra_rows_kernel(Axis x, Axis y, double gamma, GeomDevice geo, const doub
   double2* a2 = sh + nmbf * geo.total_p;
   __shared__ GeomGroup grp[kMaxGroups];
   const int n2 = blockIdx.x;
-  const double ky = y.k_first + n2 * y.dk;
-  const double2 kcy = make_double2(ky, gamma * ky);
-  if (threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
+  if ((int)threadIdx.x < geo.ngroups) grp[threadIdx.x] = geo.groups[threadIdx.x];
   __syncthreads();
   const size_t plane = (size_t)x.n * y.n;
   const int lane = threadIdx.x & 63;
@@ -568,11 +565,11 @@ size_t adj_spectra_scratch(const Axis& y, const GeomDevice& geo, int nmbf) {
   return sizeof(double2) * (size_t)y.n * nmbf * geo.nbasis;
 }
 
-hipError_t launch_adj_spectra(const Axis& x, const Axis& y, double gamma, const GeomDevice& geo,
+hipError_t launch_adj_spectra(const Axis& x, const Axis& y, const GeomDevice& geo,
                               const double2* utab, const double2* gspec, int nmbf, double2* rowacc,
                               double2* gq, hipStream_t s) {
   const size_t lds = adj_spectra_lds_bytes(geo, nmbf);
-  hipLaunchKernelGGL(adj_spectra_rows_kernel, dim3(y.n), dim3(kAdjThreads), lds, s, x, y, gamma, geo, utab,
+  hipLaunchKernelGGL(adj_spectra_rows_kernel, dim3(y.n), dim3(kAdjThreads), lds, s, x, y, geo, utab,
                      gspec, nmbf, rowacc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
