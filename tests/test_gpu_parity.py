@@ -577,12 +577,14 @@ def test_fill_matches_oracle_on_given_tables():
 
 
 @pytest.mark.parametrize("nx,ny,variant", [(64, 32, "ray"), (32, 128, "parabolic"), (256, 64, "tensor"),
-                                            (2048, 16, "ray"), (16, 2048, "ray"), (64, 2048, "ray")])
+                                            (2048, 16, "ray"), (16, 2048, "ray"), (64, 2048, "ray"),
+                                            (4096, 16, "ray"), (4096, 32, "tensor"), (16, 4096, "ray")])
 def test_zero_padded_kernels_and_variants(nx, ny, variant):
     """Zero-padded grids through both row kernels (one row per block of
-    several, short and long rows), the column pass skipping the zero rows,
-    on the ray and parabolic contours and with the tensor truncation, FP64
-    and mixed; the long-axis cases at sampled outputs."""
+    several, short and long rows, the persistent blocks of the FP64 rows of
+    4096 points), the column pass skipping the zero rows, on the ray and
+    parabolic contours and with the tensor truncation, FP64 and mixed; the
+    long-axis cases at sampled outputs."""
     from paper_1404_7357_amd import FLAG_ZERO_PAD2
     rng = np.random.default_rng(83 + nx + ny)
     basis = rooftop_lattice(2, 3)
