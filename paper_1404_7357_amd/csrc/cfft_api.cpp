@@ -325,6 +325,14 @@ double taylor_amplification(const cfft_grid_desc_t& d) {
   return d.truncation == CFFT_TRUNC_TENSOR ? poly(x) * poly(y) : poly(x + y);
 }
 
+// Pairs per launch when npairs go in launches of at most `chunk`: the same
+// number of launches, in chunks that differ by at most one pair (81 pairs in
+// launches of at most 64 run as 41 + 40, not 64 + 17).
+long long balanced_chunk(long long npairs, long long chunk) {
+  const long long launches = (npairs + chunk - 1) / chunk;
+  return (npairs + launches - 1) / launches;
+}
+
 // The row pass streams its intermediates past the caches (non-temporal
 // stores) when the intermediates in flight between a row pass and its column
 // pass exceed what the 256 MB memory-side cache can keep: then they return
@@ -793,6 +801,7 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
          chunk > 1 && !env_flag("CFFT_TEST_FAIL_ALLOC"))
     chunk /= 2;
   if (st != CFFT_OK) return st;
+  if (forced <= 0) chunk = balanced_chunk(npairs, chunk);
   // twiddles in the transforms' compute precision
   const bool c64 = pp.precision == CFFT_FP64 || pp.hi_compute;
   const void* twx = c64 ? gs.tw64x : gs.tw32x;
@@ -877,8 +886,9 @@ cfft_status_t cfft_tabulate(cfft_plan_t plan, int32_t grid, const void* spec, in
     auto it = plan->tuned.find(key);
     if (it == plan->tuned.end()) {
       std::vector<cfft_plan_s::Schedule> cands;
-      for (long long c : {chunk, 32LL, 16LL, 8LL, 4LL, 2LL}) {
-        if (c > chunk) continue;
+      for (long long c0 : {chunk, 32LL, 16LL, 8LL, 4LL, 2LL}) {
+        if (c0 > chunk) continue;
+        const long long c = balanced_chunk(npairs, c0);
         for (int l : {1, 2}) {
           if (l == 2 && !lanes_ok(c)) continue;
           if (l == 2 && per_pair * (size_t)c * 2 > plan->ws_bytes) {
@@ -962,7 +972,8 @@ cfft_status_t cfft_tabulate_noalloc(cfft_plan_t plan, int32_t grid, const void* 
                 grid, per_pair, kNoAllocScratchBytes);
   void* ws = scratch_of(plan->device);
   if (!ws) return fail(CFFT_ERR_HIP, "scratch address of device %d not resolved", plan->device);
-  const int chunk = (int)std::min<size_t>(kNoAllocScratchBytes / per_pair, (size_t)kMaxPairsPerLaunch);
+  const int chunk = (int)balanced_chunk(
+      npairs, (long long)std::min<size_t>(kNoAllocScratchBytes / per_pair, (size_t)kMaxPairsPerLaunch));
   pp.stream_out = stream_out(per_pair * (size_t)std::min(chunk, (int)npairs));
   const bool c64 = pp.precision == CFFT_FP64 || pp.hi_compute;
   const void* twx = c64 ? gs.tw64x : gs.tw32x;
@@ -1152,6 +1163,7 @@ cfft_status_t cfft_backward(cfft_plan_t plan, int32_t grid, const void* dz, doub
   chunk = std::min<long long>(chunk, std::min<long long>(npairs, kMaxPairsPerLaunch));
   const long long forced = env_ll("CFFT_PAIR_CHUNK", 0);
   if (forced > 0) chunk = std::min<long long>(chunk, forced);
+  else chunk = balanced_chunk(npairs, chunk);
   const GreenParams gp = green_params(gs, eps_r, tan_delta, h);
   const int green_blocks = std::min(1024, (green_threads(gp) + 255) / 256);
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
