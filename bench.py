@@ -384,7 +384,9 @@ def _paper_leg(torch, steps, warmup):
 
 def _sweep(torch, steps, warmup):
     """Frequency sweep, 8 uneven grids x 16 pairs (mixed), eager and as one replayed HIP graph; the
-    schedules are autotuned per grid by the first (warm-up) calls, before the capture."""
+    schedules are autotuned per grid by the first (warm-up) calls, before the capture.  Eager calls
+    and replays are timed in two alternating rounds after their warm-ups (the first replays after a
+    capture run slower), and each figure is the mean of its two rounds."""
     import numpy as np
 
     from paper_1404_7357_amd import FLAG_AUTOTUNE, Tabulator
@@ -406,7 +408,8 @@ def _sweep(torch, steps, warmup):
             tab.spectra(q, grid=i, out=spec)
             tab.tabulate(spec, g, pairs, grid=i, out=z)
 
-    t_eager, _ = _timed(torch, calls, steps, warmup)
+    for _ in range(warmup):
+        calls()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -416,7 +419,11 @@ def _sweep(torch, steps, warmup):
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         calls()
-    t_graph, _ = _timed(torch, graph.replay, steps, warmup)
+    te, tg = [], []
+    for _ in range(2):
+        te.append(_timed(torch, calls, steps, warmup)[0])
+        tg.append(_timed(torch, graph.replay, steps, warmup)[0])
+    t_eager, t_graph = sum(te) / 2, sum(tg) / 2
     samples = []
     for i, gd in enumerate(wl.grids):
         idx = _sample_idx(gd.nx, gd.ny, 16, 40 + i)
@@ -748,7 +755,7 @@ def main():
         fn = {"mixed": lambda: _headline(torch, args.steps, args.warmup, MIXED, False)[1],
               "c2": lambda: _c2_leg(torch, args.steps, args.warmup, 0)[0],
               "paper_setup": lambda: _paper_leg(torch, args.steps, args.warmup)[0],
-              "sweep": lambda: _sweep(torch, args.steps, args.warmup)[0],
+              "sweep": lambda: _sweep(torch, max(20, args.steps), max(5, args.warmup))[0],
               "adjoint": lambda: _adjoint_ratio(torch, args.steps, args.warmup)[0]}[args.only]
         print(json.dumps({"leg": args.only, **fn()}), flush=True)
         return
@@ -799,7 +806,7 @@ def main():
         _log("paper-setup leg (2048^2 incl. zero padding, 81 pairs, 25 x 25 array fill)")
         out["paper_setup"], checks["paper_setup"] = _paper_leg(torch, 3, 1)
         _log("sweep leg (8 grids, one graph)")
-        out["sweep"], checks["sweep"] = _sweep(torch, max(3, args.steps // 4), 2)
+        out["sweep"], checks["sweep"] = _sweep(torch, max(20, args.steps), max(5, args.warmup))
         _log("adjoint leg (1024^2, 16 pairs, 4096 lookups)")
         out["adjoint"], checks["adjoint"] = _adjoint_ratio(torch, max(3, args.steps // 4), 2)
 
