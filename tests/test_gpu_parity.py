@@ -738,3 +738,39 @@ def test_invalid_pairs_rejected_on_host():
     with pytest.raises(CfftError):
         tab.green(float("nan"), 0.0, 0.05)
     tab.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_every_schedule_gives_the_same_table(monkeypatch, prec):
+    """Pair chunks, two lanes and half-width column tiles change only how the
+    work is laid out, so they must give the default schedule's table bit for
+    bit.  The other number of points per thread runs the same stages and
+    twiddles through another instantiation of the transform, whose compiled
+    arithmetic may round differently: a few units in the last place of the
+    storage type (columns of 1024 and 2048 points)."""
+    rng = np.random.default_rng(4242 + prec)
+    basis = rooftop_lattice(2, 3)
+    q = gaussian_coefficients(rng, 3, basis.shape[0])
+    pairs = [(m, n) for m in range(3) for n in range(3)]
+    sub = Substrate(4.4, 0.002, 0.06)
+    for nx, ny in [(32, 1024), (16, 2048)]:
+        grid = Grid(nx, ny, 8 * K0, 6 * K0, K0, precision=prec)
+        tab = _tab(grid, basis, 3)
+        qd = torch.tensor(q, device="cuda")
+        g = tab.green(sub.eps_r, sub.tan_delta, sub.h)
+        spec = tab.spectra(qd)
+        ref = tab.tabulate(spec, g, pairs).cpu().numpy()
+        for env in ({"CFFT_PAIR_CHUNK": "2"}, {"CFFT_PAIR_CHUNK": "4", "CFFT_LANES": "2"},
+                    {"CFFT_COL_TILE": "1"}, {"CFFT_COL_TILE": "2"}, {"CFFT_COL_TILE": "2", "CFFT_PAIR_CHUNK": "3"}):
+            _say(f"schedule {env} {nx}x{ny} prec={prec}")
+            for k, v in env.items():
+                monkeypatch.setenv(k, v)
+            z = tab.tabulate(spec, g, pairs).cpu().numpy()
+            for k in env:
+                monkeypatch.delenv(k)
+            if env.get("CFFT_COL_TILE") == "2":
+                ulp = np.finfo(np.float64 if prec == FP64 else np.float32).eps
+                assert float(np.abs(z - ref).max()) <= 8 * ulp * float(np.abs(ref).max()), (env, nx, ny, prec)
+            else:
+                assert np.array_equal(z, ref), (env, nx, ny, prec, float(np.abs(z - ref).max()))
+        tab.close()
