@@ -135,6 +135,23 @@ def test_tensor_truncation_gradient_vs_oracle_and_differences():
     assert abs(de - fd_e) < 1e-6 * abs(fd_e), (de, fd_e)
 
 
+@pytest.mark.parametrize("order,truncation", [(0, 0), (7, 0), (7, 1)])
+def test_gradient_at_the_extreme_orders_vs_oracle(order, truncation):
+    """The adjoint at Taylor order 0 (one term: the plain transform) and at
+    the largest order the library takes (7: eight intermediates, or one with
+    the tensor truncation), against the oracle's gradient."""
+    import dataclasses
+    _say(f"adjoint order {order} truncation {truncation} 32^2")
+    grid, sub, basis, q, pairs, pts, zt = _problem(n=32, npts=16, seed=61 + order, truncation=truncation)
+    grid = dataclasses.replace(grid, order=order)
+    loss, de, dh, dq = _gpu_loss_and_grad(grid, sub, basis, q, pairs, pts, zt)
+    o_loss, o_de, o_dh, o_dq = co.loss_gradient(grid, sub, basis, q, np.array(pairs), pts, zt)
+    assert abs(loss - o_loss) < 1e-9 * abs(o_loss)
+    assert abs(de - o_de) < 1e-9 * max(abs(o_de), 1e-300), (de, o_de)
+    assert abs(dh - o_dh) < 1e-9 * max(abs(o_dh), 1e-300), (dh, o_dh)
+    assert np.abs(dq - o_dq).max() < 1e-9 * np.abs(o_dq).max()
+
+
 def test_backward_many_pairs_chunked(monkeypatch):
     """Pair chunks accumulate the Green's and spectra gradients (ragged last chunk)."""
     _say("adjoint chunked pairs")

@@ -253,7 +253,7 @@ def test_long_axes_low_order_mixed(nx, ny):
     assert err < MIXED_TARGET, (nx, ny, err)
 
 
-@pytest.mark.parametrize("nx,ny,order", [(64, 32, 3), (16, 128, 2), (128, 16, 5), (32, 32, 0)])
+@pytest.mark.parametrize("nx,ny,order", [(64, 32, 3), (16, 128, 2), (128, 16, 5), (32, 32, 0), (32, 64, 7)])
 def test_tensor_truncation_full_grid(nx, ny, order):
     """Tensor-product truncation (one intermediate per pair), FP64 and mixed,
     whole table against the oracle's tensor mode."""
@@ -311,7 +311,7 @@ def test_parabolic_green_and_spectra():
     assert _err(spec, np.concatenate([mt, mh], axis=1)) < 1e-12
 
 
-@pytest.mark.parametrize("nx,ny,order", [(64, 32, 3), (32, 64, 2), (16, 128, 1), (256, 16, 3)])
+@pytest.mark.parametrize("nx,ny,order", [(64, 32, 3), (32, 64, 2), (16, 128, 1), (256, 16, 3), (64, 32, 7)])
 def test_parabolic_full_grid(nx, ny, order):
     """Tables on the parabolic contour ((P+1)(P+2)/2 row transforms, no ky
     factor in the column pass, per-sample weight), FP64 and mixed."""
