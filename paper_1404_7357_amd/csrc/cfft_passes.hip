@@ -1346,13 +1346,21 @@ struct FillArgs {
   short slot[kFillMaxMbf * kFillMaxMbf];   // pair index of (m, n), -1 when not listed
 };
 
+// Block = 256 consecutive columns of matrix row i M + m.  The blocks are
+// ordered with the testing MBF m outermost and the element i next, and each
+// XCD takes a contiguous range of them: the rows one XCD fills in turn then
+// share most of their displacements r_i - r_j (a layout's displacements
+// cluster), so the stencil lines of the M tables of one m stay in that
+// XCD's L2 instead of coming from the memory-side cache for every row.
 template <int ORDER>
 __global__ __launch_bounds__(256) void fill_kernel(FillArgs a) {
   const int am = a.nelem * a.nmbf;
-  const int r = blockIdx.x / a.ncb;
-  const int c = (blockIdx.x - r * a.ncb) * 256 + threadIdx.x;
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int rr = lid / a.ncb;   // m * nelem + i
+  const int c = (lid - rr * a.ncb) * 256 + threadIdx.x;
   if (c >= am) return;
-  const int i = r / a.nmbf, m = r - i * a.nmbf;
+  const int m = rr / a.nelem, i = rr - m * a.nelem;
+  const int r = i * a.nmbf + m;
   const int j = c / a.nmbf, n = c - j * a.nmbf;
   if (i == j) return;
   const int p = a.slot[m * kFillMaxMbf + n];
