@@ -406,8 +406,15 @@ __device__ __forceinline__ void grouped_inputs(const Vs* sp, int n, size_t row, 
   }
 }
 
+// The grouped row pass asks for the row pass's occupancy, except that the
+// two-pair blocks of FP32 rows of 1024 points settle for 3 waves per SIMD
+// (their A tables take the registers 4 waves would need).
+template <typename Vc, int N, int NPW> constexpr int rowg_min_waves() {
+  return (NPW == 2 && row_min_waves<Vc, N>() == 4) ? 3 : row_min_waves<Vc, N>();
+}
+
 template <typename Vs, typename Vc, int N, int NPW>
-__global__ void __launch_bounds__(NPW * (N / 8), (row_min_waves<Vc, N>())) row_pass_grouped_kernel(RowGArgs a) {
+__global__ void __launch_bounds__(NPW * (N / 8), (rowg_min_waves<Vc, N, NPW>())) row_pass_grouped_kernel(RowGArgs a) {
   using Cfg = RowGCfg<N, NPW>;
   constexpr int T = Cfg::T, R = Cfg::R;
   using Rc = typename real_of<Vc>::type;
